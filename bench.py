@@ -1,0 +1,171 @@
+"""Benchmark of the MI scan-alignment hot path on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+
+Workload (one step): a full 6-DOF coarse-to-fine alignment of a realistic
+scan pair -- two synthetic 64-ring spinning-scanner scans (~115k points each)
+of a 160 x 160 m urban scene, 0.5 m voxels over 320 x 320 x 20, point-count and
+z-variance features at 32 bins each -- i.e. scan A's resident feature map,
+then 3 levels of 5^6 = 15,625 candidate poses (46,875 MI evaluations), each
+level one batched launch plus the argmax read back.  Inputs are resident in
+HBM before the timed region.
+
+Prints one JSON line: MI pose evals/s (value), Gpoint-transforms/s, the
+roofline of the dominant kernel (the batched evaluator, timed with HIP events
+on its own stream), the per-pose plain path on a sample for comparison, and
+the CPU oracle timed on a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+# MI355X: 256 CUs x 4 SIMDs x 16 FP64 lanes x 2.4 GHz = 3.93e13 FP64 lane-ops/s
+# (78.6 TFLOP/s counts a fused multiply-add as two; the voxel arithmetic has none).
+PEAK_FP64_OPS = 256 * 4 * 16 * 2.4e9
+# Algorithmic FP64 operations per (point, pose): 9 mul + 9 add for R p + t,
+# 3 sub + 3 mul + 3 floor for the voxel coordinate and index.
+OPS_PER_POINT_POSE = 27
+
+
+def _args():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--plain-sample", type=int, default=96)
+    ap.add_argument("--cpu-sample", type=int, default=192)
+    return ap.parse_args()
+
+
+def main():
+    a = _args()
+    if a.gpus != 1:
+        print(json.dumps({"error": "this benchmark runs on one GPU; multi-GPU runs are not part "
+                                   "of this build (pose sharding is described in DESIGN.md)",
+                          "n_gpus": a.gpus}), flush=True)
+        sys.exit(2)
+    import torch
+
+    from paper_1709_06948_amd import mi, synth
+
+    torch.cuda.set_device(0)
+    pair = synth.urban_pair()
+    c2f = synth.urban_c2f_params()
+    grid = mi.Grid(pair.origin, pair.dims, pair.voxel, features=mi.FEAT_COUNT | mi.FEAT_ZVAR,
+                   nb_count=32, nb_zvar=32)
+    A = torch.from_numpy(pair.A).cuda()
+    B = torch.from_numpy(pair.B).cuda()
+    n_b = B.shape[1]
+    init = np.zeros(6)
+    levels = int(c2f["levels"])
+    K_level = int(np.prod(c2f["samples"]))
+    evals_per_step = levels * K_level      # one eval = one pose, both features from one pass
+
+    def step():
+        ref = mi.Ref(grid, A)
+        pose, best = mi.align_coarse_to_fine(ref, B, init, c2f["half"], c2f["samples"], levels,
+                                             c2f["shrink"], feature_slot=1)
+        return pose, best
+
+    for _ in range(a.warmup):
+        step()
+    torch.cuda.synchronize()
+    mi.profile_enable(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(a.steps):
+        pose, best = step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    prof = mi.profile_read()
+    mi.profile_enable(False)
+    dt = t1 - t0
+    ms_per_step = dt * 1e3 / a.steps
+    evals = evals_per_step * a.steps
+    value = evals / dt
+    gpts = evals * n_b / dt / 1e9
+
+    eval_ms_avg = prof["eval_ms"] / max(prof["eval_launches"], 1)
+    pp_per_launch = prof["point_poses"] / max(prof["eval_launches"], 1)
+    achieved = OPS_PER_POINT_POSE * pp_per_launch / (eval_ms_avg * 1e-3)
+    roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP64_OPS / 1e12,
+                "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_OPS, "traffic": None,
+                "kernel": "k_eval", "avg_launch_ms": eval_ms_avg,
+                "point_poses_per_launch": pp_per_launch,
+                "frames_ms_per_step": prof["frames_ms"] / a.steps,
+                "eval_ms_per_step": prof["eval_ms"] / a.steps}
+    err = np.abs(pose - pair.eta_gt)
+
+    # plain per-pose launch path on a sample of level-0 poses
+    plain = None
+    if a.plain_sample > 0:
+        P0 = synth.level_poses(init, c2f["half"], c2f["samples"])
+        rng = np.random.default_rng(1)
+        Ps = P0[np.sort(rng.choice(len(P0), a.plain_sample, replace=False))]
+        ref = mi.Ref(grid, A)
+        mi.eval_poses_plain(ref, B, Ps[:4])
+        torch.cuda.synchronize()
+        tp0 = time.perf_counter()
+        mi.eval_poses_plain(ref, B, Ps)
+        torch.cuda.synchronize()
+        tp = time.perf_counter() - tp0
+        plain = {"evals_per_s": len(Ps) / tp, "sample": f"{len(Ps)} level-0 poses",
+                 "batched_speedup": value / (len(Ps) / tp)}
+
+    cpu = None
+    if not a.no_cpu_baseline:
+        import oracle as O
+        og = O.Grid(pair.origin, pair.dims, pair.voxel, features=O.FEAT_COUNT | O.FEAT_ZVAR,
+                    nb_count=32, nb_zvar=32)
+        P0 = synth.level_poses(init, c2f["half"], c2f["samples"])
+        rng = np.random.default_rng(2)
+        Ps = P0[np.sort(rng.choice(len(P0), a.cpu_sample, replace=False))]
+        cores = len(os.sched_getaffinity(0))
+        O.eval_poses(og, pair.A, pair.B, Ps[:cores], nthreads=cores)
+        tc0 = time.perf_counter()
+        O.eval_poses(og, pair.A, pair.B, Ps, nthreads=cores)
+        tc = time.perf_counter() - tc0
+        cpu = {"value": len(Ps) / tc, "unit": "MI pose evals/s", "cores": cores, "kind": "oracle",
+               "sample": f"{len(Ps)} random poses of level 0 of the same workload, FP64 dense "
+                         f"oracle, {tc:.1f} s"}
+
+    out = {
+        "metric": "MI pose evals/s",
+        "value": value,
+        "unit": "evals/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "urban scan pair, 6-DOF coarse-to-fine: 2 x ~115k-point 64-ring "
+                               "scans, 0.5 m voxels 320x320x20, count + z-variance 32 bins, "
+                               "3 levels x 5^6 poses",
+                   "evals_per_step": evals_per_step, "n_b": int(n_b), "n_a": int(A.shape[1])},
+        "gpoint_transforms_per_s": gpts,
+        "roofline": roofline,
+        "plain_path": plain,
+        "cpu_baseline": cpu,
+        "result": {"pose": [float(v) for v in pose], "mi": best,
+                   "abs_err_vs_truth": [float(v) for v in err]},
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

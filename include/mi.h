@@ -1,0 +1,253 @@
+/*
+ * mi.h -- C ABI of libmi355.so: the MI355X (gfx950) hot path of
+ * mutual-information 3D scan alignment (Mehta, McBride, Pandey, "Robust and
+ * Fast 3D Scan Alignment using Mutual Information", arXiv 1709.06948).
+ *
+ * What the library computes (Sec. III-A, Eqs. 1-5, Alg. 1):
+ *   for each candidate pose eta = [tx, ty, tz, roll, pitch, yaw] it moves
+ *   scan B by eta, voxelizes it on the grid of scan A, computes per-voxel
+ *   features (point count, z-height variance; empty voxels keep their own
+ *   bin 0, the paper's phi value), builds the joint feature histogram over the
+ *   overlap box of the two scans and reduces it to
+ *   MI = H(X) + H(Y) - H(X,Y) (natural log).  The argmax over the poses is the
+ *   estimate of Eq. 1.
+ *
+ * Fixed readings where the paper is silent:
+ *   - R = Rz(yaw) Ry(pitch) Rx(roll); x' = R x + t maps B into A's frame.
+ *   - Voxel coordinate per axis u = fl(fl(w * s) + c) in FP64, w the rotated
+ *     point (rows summed left to right, no fused multiply-add), s = fl(1/voxel),
+ *     c = fl(fl(t - origin) * s); voxel index floor(u); half-open voxels.
+ *   - z-variance feature on q = floor(frac(u_z) * 2^20) with exact integer
+ *     sums: bin = 1 + #{j : n*S2 - S1^2 >= E_j * n^2}; count bin =
+ *     #{j : n >= e_j}.  Default edges: e_j = j (bins min(n, nb-1)); E_j =
+ *     ceil(e_j * (2^20/voxel)^2) for nb-2 edges e_j log-spaced from 1e-5 m^2
+ *     to voxel^2/4.
+ *   - A scan's extent is the index box of its in-grid points; the overlap
+ *     box is max of the lower / min of the upper bounds; empty overlap gives
+ *     MI = 0.
+ *   - Argmax is the smallest pose index within 1e-12 of the maximum.
+ *
+ * Conventions for every call:
+ *   - Points are float32 structure-of-arrays in device memory: x[0..n),
+ *     y[0..n), z[0..n) back to back.  Non-finite points are skipped and
+ *     counted; points outside the grid are counted and belong to no voxel.
+ *   - The caller owns every device buffer.  Device work memory comes from a
+ *     caller-provided workspace `ws` of at least the queried size (256-byte
+ *     aligned); the library never allocates device memory.  Host handles
+ *     (mi_grid, mi_ref, mi_plan) are malloc'd by the library and freed by the
+ *     matching destroy call; a mi_ref or mi_plan points into its workspace,
+ *     which must outlive it.
+ *   - `stream` is a hipStream_t passed as void* (NULL = default stream).  All
+ *     calls enqueue asynchronously on it, except where a call says it
+ *     synchronizes.
+ *   - Errors: argument and workspace errors are returned before anything is
+ *     enqueued.  MI_E_DEVICE reports a HIP launch or runtime failure.
+ *     mi_last_error() returns a thread-local message for the last failure.
+ *   - Handles are not thread-safe; distinct handles may be used from
+ *     distinct threads.
+ */
+#ifndef MI355_MI_H
+#define MI355_MI_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t mi_status;
+#define MI_OK 0
+#define MI_E_INVALID (-1)     /* bad argument */
+#define MI_E_WORKSPACE (-2)   /* workspace too small or misaligned */
+#define MI_E_DEVICE (-3)      /* HIP error */
+#define MI_E_UNSUPPORTED (-4) /* valid but outside the supported sizes */
+
+/* Feature bitmask (Sec. IV: MI-N and MI-VARZ). */
+#define MI_FEAT_COUNT 1u /* number of points in the voxel */
+#define MI_FEAT_ZVAR 2u  /* variance of z-height in the voxel */
+
+/* Evaluation flags for mi_plan_create / mi_eval_poses. */
+#define MI_EVAL_NEAR_FACE 1u /* count points within 1e-5 m of a voxel face (stats) */
+
+/* Limits. */
+#define MI_MAX_BINS 64
+#define MI_MAX_POINTS ((int64_t)1 << 20) /* per scan B when MI_FEAT_ZVAR is on */
+
+/* The voxel grid of resolution R_v that encompasses both scans (Sec. III-A)
+ * plus the feature description.  Axis-aligned in scan A's frame. */
+typedef struct mi_grid_desc {
+  double origin[3];             /* m, lower corner of voxel (0,0,0) */
+  int32_t dims[3];              /* voxels per axis, each >= 1, product < 2^31 */
+  double voxel;                 /* edge length R_v in m, > 0 */
+  uint32_t features;            /* MI_FEAT_* bitmask, non-zero */
+  int32_t nbins_count;          /* 2..64 when MI_FEAT_COUNT */
+  const uint32_t *count_edges;  /* host, nbins_count-1 ascending, first >= 1; NULL = default */
+  int32_t nbins_zvar;           /* 3..64 when MI_FEAT_ZVAR */
+  const uint64_t *zvar_edges;   /* host, nbins_zvar-2 ascending; NULL = default */
+} mi_grid_desc;
+
+typedef struct mi_grid mi_grid;
+typedef struct mi_ref mi_ref;
+typedef struct mi_plan mi_plan;
+
+/* Per-pose diagnostics (64 bytes). lo/hi: overlap box (lo > hi on some axis
+ * when it is empty); n_overlap = |O|; B points in the grid, outside it,
+ * non-finite; B points in the overlap within 1e-5 m of a voxel face (only
+ * with MI_EVAL_NEAR_FACE, else 0). */
+typedef struct mi_pose_stats {
+  int32_t lo[3], hi[3];
+  int64_t n_overlap, n_in_grid, n_out_of_grid, n_nonfinite, n_near_face;
+} mi_pose_stats;
+
+const char *mi_status_str(mi_status s);
+const char *mi_last_error(void);
+
+/* Launch shape of the batched evaluator (process-wide; read when a plan is
+ * created).  waves: 1..8 waves per workgroup, each owning one brick of the
+ * grid at a time; wave_bytes: LDS bytes per wave for its brick (multiple of
+ * 16); hist_copies: 1..8 privatized joint-histogram copies per workgroup.
+ * Every setting gives bit-identical histograms. */
+typedef struct mi_tuning {
+  int32_t waves;
+  int32_t wave_bytes;
+  int32_t hist_copies;
+  int32_t reserved;
+} mi_tuning;
+mi_status mi_tuning_set(const mi_tuning *t);
+mi_status mi_tuning_get(mi_tuning *t);
+
+/* Stage timing with HIP events (tracing; process-wide).  While enabled, every
+ * plan execution and plain evaluation records events around its frame build,
+ * evaluation and per-pose launches on the stream it runs on (so enabled
+ * timing is not for graph capture).  mi_profile_read synchronizes on the
+ * recorded events, returns the sums since the last read and resets them. */
+typedef struct mi_profile {
+  double frames_ms;        /* rotate + bucket scan B (all chunks) */
+  double eval_ms;          /* batched evaluator launches */
+  double plain_ms;         /* per-pose stage sequences of the plain path */
+  int64_t frame_launches;  /* frame-build sequences */
+  int64_t eval_launches;   /* evaluator launches */
+  int64_t plain_poses;     /* poses through the plain path */
+  int64_t poses;           /* poses through the evaluator */
+  int64_t point_poses;     /* sum over evaluated poses of the points of scan B */
+} mi_profile;
+mi_status mi_profile_enable(int32_t on);
+mi_status mi_profile_read(mi_profile *out);
+
+/* ------------------------------------------------------------------ grid */
+
+/* Validate a grid description and copy it, with its bin edges, into a host
+ * handle.  MI_E_INVALID for a bad description (dims < 1, V >= 2^31, voxel
+ * <= 0 or non-finite, unknown features, nbins out of range, edges not
+ * ascending, default z-variance edges undefined because voxel^2/4 <= 1e-5). */
+mi_status mi_grid_create(const mi_grid_desc *desc, mi_grid **out);
+void mi_grid_destroy(mi_grid *g);
+
+/* The bin edges in use (host arrays of nbins_count-1 / nbins_zvar-2; either
+ * pointer may be NULL). */
+mi_status mi_grid_edges(const mi_grid *g, uint32_t *count_edges, uint64_t *zvar_edges);
+
+/* The rotation and translation of pose eta as a row-major [R | t] (3x4), the
+ * exact doubles every kernel uses (Sec. III-A: T as a rigid transform). */
+mi_status mi_pose_to_matrix(const double eta[6], double rt[12]);
+
+/* ------------------------------------------------------------- reference */
+
+/* Workspace for mi_features_ref: the resident part (bins and per-bin
+ * summed-volume tables of scan A, read by every evaluation) followed by a
+ * transient part that is free again once the call has completed on the
+ * stream.  persistent_bytes (nullable) receives the resident size. */
+size_t mi_features_ref_workspace(const mi_grid *g, int64_t n_a, size_t *persistent_bytes);
+
+/* Alg. 1 initialisation: voxel ids of all points of scan A and A's feature
+ * map for all voxels (bin 0 = empty), A's index box and, per feature bin, a
+ * summed-volume table of A's occupied voxels (used to count A's voxels of each
+ * bin inside any overlap box).  xyz_a: device SoA [3][n_a], n_a >= 0.
+ * The grid must outlive the returned mi_ref. */
+mi_status mi_features_ref(const mi_grid *g, const float *xyz_a, int64_t n_a, void *ws,
+                          size_t ws_bytes, void *stream, mi_ref **out);
+void mi_ref_destroy(mi_ref *r);
+
+/* Device pointer to A's bin of every voxel for feature slot f (slot 0 = count
+ * when enabled, then z-variance), uint8 [dims z][y][x]. */
+mi_status mi_ref_bins(const mi_ref *r, int32_t feature_slot, const uint8_t **dev_bins);
+
+/* Synchronizes the stream, then reads back A's index box (lo[3], hi[3]) and
+ * counters (in-grid, out-of-grid, non-finite, occupied voxels). */
+mi_status mi_ref_summary(const mi_ref *r, void *stream, int32_t box[6], int64_t counters[4]);
+
+/* --------------------------------------------------------------- evaluate */
+
+/* Workspace for evaluating the poses (host [n_poses][6]) against a scan B of
+ * n_b points: pose tables, B's points rotated once per distinct rotation and
+ * bucketed by column of A's grid, and scratch.  When the rotated copies would
+ * exceed frame_budget_bytes (0 = 4 GiB) they are processed in chunks. */
+size_t mi_eval_poses_workspace(const mi_ref *r, int64_t n_b, const double *poses, int64_t n_poses,
+                               uint32_t flags, size_t frame_budget_bytes);
+
+/* Eqs. 1-5 for every pose: MI per feature and pose.
+ *   xyz_b      device SoA [3][n_b] (n_b < 2^20 when MI_FEAT_ZVAR is on)
+ *   poses      host [n_poses][6] = tx, ty, tz (m), roll, pitch, yaw (rad)
+ *   mi_out     device double [n_feat][n_poses]
+ *   argmax_out device int64 [n_feat] or NULL
+ *   hist_out   device uint32, feature f at offset sum_{f'<f} n_poses*nb_f'^2,
+ *              pose k at + k*nb_f^2, rows = A bin, cols = B bin; or NULL
+ *   stats_out  device mi_pose_stats [n_poses] or NULL
+ * Pose tables are staged through library-owned pinned host memory, so the
+ * host `poses` array may be reused as soon as the call returns. */
+mi_status mi_eval_poses(const mi_ref *r, const float *xyz_b, int64_t n_b, const double *poses,
+                        int64_t n_poses, uint32_t flags, double *mi_out, int64_t *argmax_out,
+                        uint32_t *hist_out, mi_pose_stats *stats_out, void *ws, size_t ws_bytes,
+                        void *stream);
+
+/* The paper-shaped path: for each pose in turn, one launch sequence of
+ * transform + voxel mapping + extent, scatter into a dense per-pose voxel grid
+ * in device memory, dense sweep of the overlap box into the joint histogram,
+ * entropy (Table III stages).  Same arguments and results as mi_eval_poses;
+ * kept as the per-pose baseline. */
+size_t mi_eval_poses_plain_workspace(const mi_ref *r, int64_t n_b, int64_t n_poses);
+mi_status mi_eval_poses_plain(const mi_ref *r, const float *xyz_b, int64_t n_b, const double *poses,
+                              int64_t n_poses, uint32_t flags, double *mi_out, int64_t *argmax_out,
+                              uint32_t *hist_out, mi_pose_stats *stats_out, void *ws,
+                              size_t ws_bytes, void *stream);
+
+/* Split form of mi_eval_poses for repeated launches (e.g. capture in a HIP
+ * graph): mi_plan_create uploads the pose tables (enqueued on `stream`);
+ * mi_plan_execute only launches kernels that read device tables, never
+ * allocates, copies from the host or synchronizes, so it can be captured and
+ * replayed.  The plan lives in `ws` (size from mi_eval_poses_workspace). */
+mi_status mi_plan_create(const mi_ref *r, int64_t n_b, const double *poses, int64_t n_poses,
+                         uint32_t flags, void *ws, size_t ws_bytes, size_t frame_budget_bytes,
+                         void *stream, mi_plan **out);
+mi_status mi_plan_execute(mi_plan *p, const float *xyz_b, double *mi_out, int64_t *argmax_out,
+                          uint32_t *hist_out, mi_pose_stats *stats_out, void *stream);
+void mi_plan_destroy(mi_plan *p);
+
+/* ------------------------------------------------------------- search */
+
+/* Coarse-to-fine grid search for Eq. 1 from the initial guess T_o = init
+ * (Alg. 1 outer loop, with the simplex update of Sec. III-B replaced by
+ * re-centring a shrinking pose grid on the best pose).  Level l evaluates, per
+ * axis, samples[a] nodes c + h*(-1 + 2j/(samples[a]-1)) (c alone when 1),
+ * row-major over (tx, ty, tz, roll, pitch, yaw), yaw fastest; the next level is
+ * centred on the argmax of feature slot `feature_slot` with h divided by
+ * `shrink`.  Synchronizes the stream once per level.  ws from
+ * mi_align_workspace. */
+typedef struct mi_c2f_desc {
+  double half_range[6];
+  int32_t samples[6];
+  int32_t levels;
+  double shrink;
+  int32_t feature_slot;
+} mi_c2f_desc;
+
+size_t mi_align_workspace(const mi_ref *r, int64_t n_b, const mi_c2f_desc *d);
+mi_status mi_align_coarse_to_fine(const mi_ref *r, const float *xyz_b, int64_t n_b,
+                                  const double init[6], const mi_c2f_desc *d, double pose_out[6],
+                                  double *mi_out, void *ws, size_t ws_bytes, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MI355_MI_H */

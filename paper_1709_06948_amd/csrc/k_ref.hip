@@ -1,0 +1,189 @@
+// k_ref.hip -- scan A's resident feature map (Alg. 1 initialisation).
+//
+// 1. scatter: voxel index of every A point (half-open voxels, FP64 in the
+//    fixed order u = fl(fl(x*s) + c0)), dense per-voxel n, S1 = sum q,
+//    S2 = sum q^2 with q = floor(frac(u_z) * 2^20); A's index box.
+// 2. bins: bin of every voxel per feature (0 = empty, the phi value).
+// 3. summed-volume table per feature and bin a >= 1, so that the number of
+//    A voxels of bin a inside any box is 8 lookups (used for the voxels of
+//    the overlap box that B leaves empty).
+#include "mi_device.h"
+#include "mi_internal.h"
+
+#pragma clang fp contract(off)
+
+namespace mi {
+
+__global__ void k_ref_init(RefDev rd) {
+  if (threadIdx.x < 3) {
+    rd.abox[threadIdx.x] = threadIdx.x == 0 ? rd.nx : (threadIdx.x == 1 ? rd.ny : rd.nz);
+    rd.abox[3 + threadIdx.x] = -1;
+  }
+  if (threadIdx.x < 4) rd.counters[threadIdx.x] = 0ull;
+}
+
+__global__ void __launch_bounds__(256) k_ref_scatter(RefDev rd, const float *__restrict__ xyz,
+                                                     int64_t n) {
+  const int nx = rd.nx, ny = rd.ny, nz = rd.nz;
+  int lo0 = nx, lo1 = ny, lo2 = nz, hi0 = -1, hi1 = -1, hi2 = -1;
+  unsigned long long nin = 0, nout = 0, nnf = 0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const float x = xyz[i], y = xyz[n + i], z = xyz[2 * n + i];
+    if (!isfinite(x) || !isfinite(y) || !isfinite(z)) { ++nnf; continue; }
+    const double ux = (double)x * rd.s + rd.c0[0];
+    const double uy = (double)y * rd.s + rd.c0[1];
+    const double uz = (double)z * rd.s + rd.c0[2];
+    const double fx = floor(ux), fy = floor(uy), fz = floor(uz);
+    if (!(fx >= 0.0 && fx < (double)nx && fy >= 0.0 && fy < (double)ny && fz >= 0.0 &&
+          fz < (double)nz)) {
+      ++nout;
+      continue;
+    }
+    const int ix = (int)fx, iy = (int)fy, iz = (int)fz;
+    const int64_t v = ((int64_t)iz * ny + iy) * nx + ix;
+    const unsigned long long q = (unsigned long long)floor((uz - fz) * kQScale);
+    atomicAdd(&rd.cnt[v], 1u);
+    atomicAdd(&rd.s1[v], q);
+    atomicAdd(&rd.s2[v], q * q);
+    ++nin;
+    lo0 = min(lo0, ix); lo1 = min(lo1, iy); lo2 = min(lo2, iz);
+    hi0 = max(hi0, ix); hi1 = max(hi1, iy); hi2 = max(hi2, iz);
+  }
+  lo0 = wave_min_i32(lo0); lo1 = wave_min_i32(lo1); lo2 = wave_min_i32(lo2);
+  hi0 = wave_max_i32(hi0); hi1 = wave_max_i32(hi1); hi2 = wave_max_i32(hi2);
+  nin = wave_sum_u64(nin); nout = wave_sum_u64(nout); nnf = wave_sum_u64(nnf);
+  if ((threadIdx.x & 63) == 0) {
+    if (hi0 >= 0) {
+      atomicMin(&rd.abox[0], lo0); atomicMin(&rd.abox[1], lo1); atomicMin(&rd.abox[2], lo2);
+      atomicMax(&rd.abox[3], hi0); atomicMax(&rd.abox[4], hi1); atomicMax(&rd.abox[5], hi2);
+    }
+    if (nin) atomicAdd(&rd.counters[0], nin);
+    if (nout) atomicAdd(&rd.counters[1], nout);
+    if (nnf) atomicAdd(&rd.counters[2], nnf);
+  }
+}
+
+__global__ void __launch_bounds__(256) k_ref_bins(RefDev rd) {
+  const int64_t V = (int64_t)rd.nx * rd.ny * rd.nz;
+  unsigned long long occ = 0;
+  for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < V;
+       v += (int64_t)gridDim.x * blockDim.x) {
+    const uint32_t n = rd.cnt[v];
+    if (n) ++occ;
+    for (int f = 0; f < rd.nf; ++f) {
+      const int b = rd.kind[f] == MI_FEAT_COUNT
+                        ? bin_count_dev(n, rd.nb[f], rd.count_edges)
+                        : bin_zvar_dev(n, rd.s1[v], rd.s2[v], rd.nb[f], rd.zvar_edges);
+      rd.bins[f][v] = (uint8_t)b;
+    }
+  }
+  occ = wave_sum_u64(occ);
+  if ((threadIdx.x & 63) == 0 && occ) atomicAdd(&rd.counters[3], occ);
+}
+
+// Pass 1 of the summed-volume tables: one thread per (a, yy, x) column of the
+// padded table, marks voxels of bin a and sums them along z.
+__global__ void __launch_bounds__(256) k_sat_z(const uint8_t *__restrict__ bins, uint32_t *S,
+                                               int nx, int ny, int nz, int nbm1) {
+  const int64_t cols = (int64_t)(ny + 1) * (nx + 1);
+  const int64_t plane = cols * (nz + 1);
+  const int64_t total = cols * nbm1;
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total;
+       t += (int64_t)gridDim.x * blockDim.x) {
+    const int a = (int)(t / cols) + 1;
+    const int64_t r = t % cols;
+    const int yy = (int)(r / (nx + 1)), x = (int)(r % (nx + 1));
+    uint32_t *col = S + (int64_t)(a - 1) * plane + r;
+    col[0] = 0;
+    uint32_t run = 0;
+    for (int zz = 1; zz <= nz; ++zz) {
+      if (yy > 0 && x > 0) run += bins[((int64_t)(zz - 1) * ny + (yy - 1)) * nx + (x - 1)] == a;
+      col[(int64_t)zz * cols] = run;
+    }
+  }
+}
+
+// Pass 2: prefix along y, one thread per (a, zz, x).
+__global__ void __launch_bounds__(256) k_sat_y(uint32_t *S, int nx, int ny, int nz, int nbm1) {
+  const int64_t cols = (int64_t)(ny + 1) * (nx + 1);
+  const int64_t plane = cols * (nz + 1);
+  const int64_t per_a = (int64_t)(nz + 1) * (nx + 1);
+  const int64_t total = per_a * nbm1;
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total;
+       t += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t a1 = t / per_a;
+    const int64_t r = t % per_a;
+    const int64_t zz = r / (nx + 1), x = r % (nx + 1);
+    uint32_t *p = S + a1 * plane + zz * cols + x;
+    uint32_t run = 0;
+    for (int yy = 0; yy <= ny; ++yy) {
+      run += p[(int64_t)yy * (nx + 1)];
+      p[(int64_t)yy * (nx + 1)] = run;
+    }
+  }
+}
+
+// Pass 3: prefix along x, one wave per row (a, zz, yy) with a wave scan.
+__global__ void __launch_bounds__(256) k_sat_x(uint32_t *S, int nx, int ny, int nz, int nbm1) {
+  const int lane = threadIdx.x & 63;
+  const int64_t rows = (int64_t)nbm1 * (nz + 1) * (ny + 1);
+  const int64_t wave0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+  for (int64_t row = wave0; row < rows; row += nwaves) {
+    uint32_t *p = S + row * (nx + 1);
+    uint32_t carry = 0;
+    for (int x0 = 0; x0 <= nx; x0 += 64) {
+      const int x = x0 + lane;
+      uint32_t v = x <= nx ? p[x] : 0u;
+#pragma unroll
+      for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t u = __shfl_up(v, o, 64);
+        if (lane >= o) v += u;
+      }
+      v += carry;
+      if (x <= nx) p[x] = v;
+      carry = __shfl(v, 63, 64);
+    }
+  }
+}
+
+static int grid_for(int64_t n, int block) {
+  int64_t g = (n + block - 1) / block;
+  if (g < 1) g = 1;
+  if (g > 65536) g = 65536;
+  return (int)g;
+}
+
+hipError_t launch_ref(const RefDev &rd, const RefDev *, const float *xyz, int64_t n,
+                      hipStream_t s) {
+  const int64_t V = (int64_t)rd.nx * rd.ny * rd.nz;
+  hipError_t e;
+  k_ref_init<<<1, 64, 0, s>>>(rd);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  if ((e = launch_fill_u32(rd.cnt, 0u, V, s)) != hipSuccess) return e;
+  if ((e = launch_fill_u32((uint32_t *)rd.s1, 0u, 2 * V, s)) != hipSuccess) return e;
+  if ((e = launch_fill_u32((uint32_t *)rd.s2, 0u, 2 * V, s)) != hipSuccess) return e;
+  if (n > 0) {
+    k_ref_scatter<<<grid_for(n, 256) > 4096 ? 4096 : grid_for(n, 256), 256, 0, s>>>(rd, xyz, n);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
+  k_ref_bins<<<grid_for(V, 256), 256, 0, s>>>(rd);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  for (int f = 0; f < rd.nf; ++f) {
+    const int nbm1 = rd.nb[f] - 1;
+    const int64_t cols = (int64_t)(rd.ny + 1) * (rd.nx + 1);
+    k_sat_z<<<grid_for(cols * nbm1, 256), 256, 0, s>>>(rd.bins[f], rd.sat[f], rd.nx, rd.ny,
+                                                       rd.nz, nbm1);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    k_sat_y<<<grid_for((int64_t)(rd.nz + 1) * (rd.nx + 1) * nbm1, 256), 256, 0, s>>>(
+        rd.sat[f], rd.nx, rd.ny, rd.nz, nbm1);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    const int64_t rows = (int64_t)nbm1 * (rd.nz + 1) * (rd.ny + 1);
+    k_sat_x<<<grid_for(rows * 64, 256), 256, 0, s>>>(rd.sat[f], rd.nx, rd.ny, rd.nz, nbm1);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+}  // namespace mi

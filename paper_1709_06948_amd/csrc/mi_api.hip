@@ -1,0 +1,1082 @@
+// mi_api.hip -- host side of the C ABI declared in include/mi.h.
+//
+// Validation, the pose -> [R | t] formula, rotation de-duplication into
+// frames, column grids and brick sizes, workspace carving, pinned staging of
+// the pose tables, chunked execution and the coarse-to-fine driver.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <unordered_map>
+#include <vector>
+
+#include "mi.h"
+#include "mi_internal.h"
+
+#pragma clang fp contract(off)
+
+using namespace mi;
+
+// ------------------------------------------------------------------ errors
+
+static thread_local std::string t_err;
+
+static mi_status fail(mi_status s, const char *fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  t_err = buf;
+  return s;
+}
+
+static mi_status dev_fail(hipError_t e, const char *where) {
+  return fail(MI_E_DEVICE, "%s: %s", where, hipGetErrorString(e));
+}
+
+#define HIP_TRY(expr, where)                   \
+  do {                                         \
+    hipError_t _e = (expr);                    \
+    if (_e != hipSuccess) return dev_fail(_e, where); \
+  } while (0)
+
+extern "C" const char *mi_status_str(mi_status s) {
+  switch (s) {
+    case MI_OK: return "ok";
+    case MI_E_INVALID: return "invalid argument";
+    case MI_E_WORKSPACE: return "workspace too small or misaligned";
+    case MI_E_DEVICE: return "device error";
+    case MI_E_UNSUPPORTED: return "unsupported size";
+    default: return "unknown status";
+  }
+}
+
+extern "C" const char *mi_last_error(void) { return t_err.c_str(); }
+
+// --------------------------------------------------------------- workspace
+
+namespace {
+
+struct Carver {
+  uintptr_t base, cur, end;
+  explicit Carver(void *p, size_t n)
+      : base((uintptr_t)p), cur((uintptr_t)p), end((uintptr_t)p + n) {}
+  template <class T>
+  T *take(size_t count) {
+    cur = (cur + 255) & ~(uintptr_t)255;
+    T *p = (T *)cur;
+    cur += count * sizeof(T);
+    return p;
+  }
+  size_t used() const { return (size_t)(cur - base); }
+  bool fits() const { return cur <= end; }
+};
+
+// Pinned host buffers for uploading tables; a buffer is reused once the copy
+// that read it has completed on its stream.
+struct Staging {
+  void *p = nullptr;
+  size_t cap = 0;
+  hipEvent_t ev = nullptr;
+  bool busy = false, inflight = false;
+};
+
+std::mutex g_staging_mu;
+std::vector<Staging *> g_staging;
+
+Staging *staging_acquire(size_t bytes, hipError_t *err) {
+  std::lock_guard<std::mutex> lk(g_staging_mu);
+  for (Staging *s : g_staging) {
+    if (s->busy || s->cap < bytes) continue;
+    if (s->inflight && hipEventQuery(s->ev) != hipSuccess) continue;
+    s->busy = true;
+    s->inflight = false;
+    return s;
+  }
+  Staging *s = new Staging();
+  s->cap = std::max<size_t>(bytes, 1 << 20);
+  *err = hipHostMalloc(&s->p, s->cap, hipHostMallocDefault);
+  if (*err != hipSuccess) { delete s; return nullptr; }
+  *err = hipEventCreateWithFlags(&s->ev, hipEventDisableTiming);
+  if (*err != hipSuccess) { hipHostFree(s->p); delete s; return nullptr; }
+  s->busy = true;
+  g_staging.push_back(s);
+  return s;
+}
+
+struct Upload {
+  void *dst;
+  size_t off, bytes;
+};
+
+// Enqueue the copies out of the pinned buffer, then record the event that
+// guards the buffer's reuse and hand the buffer back to the pool.
+hipError_t staging_upload(Staging *s, const Upload *ups, int n, hipStream_t st) {
+  hipError_t e = hipSuccess;
+  for (int i = 0; i < n && e == hipSuccess; ++i)
+    if (ups[i].bytes)
+      e = hipMemcpyAsync(ups[i].dst, (char *)s->p + ups[i].off, ups[i].bytes,
+                         hipMemcpyHostToDevice, st);
+  if (e == hipSuccess) e = hipEventRecord(s->ev, st);
+  std::lock_guard<std::mutex> lk(g_staging_mu);
+  s->busy = false;
+  s->inflight = (e == hipSuccess);
+  return e;
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------ tuning
+
+namespace {
+struct Tuning {
+  int32_t waves = 8;
+  int32_t wave_bytes = 17 * 1024;
+  int32_t hist_copies = 1;
+};
+Tuning g_tuning;
+std::mutex g_tuning_mu;
+
+int max_lds_per_block() {
+  static int v = -1;
+  if (v < 0) {
+    int dev = 0, x = 0;
+    if (hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&x, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess &&
+        x > 0)
+      v = x;
+    else
+      v = 160 * 1024;
+  }
+  return v;
+}
+}  // namespace
+
+extern "C" mi_status mi_tuning_set(const mi_tuning *t) {
+  if (!t) return fail(MI_E_INVALID, "mi_tuning_set: NULL");
+  if (t->waves < 1 || t->waves > 8) return fail(MI_E_INVALID, "waves must be 1..8");
+  if (t->wave_bytes < 2048 || t->wave_bytes > 160 * 1024 || (t->wave_bytes & 15))
+    return fail(MI_E_INVALID, "wave_bytes must be a multiple of 16 in [2 KiB, 160 KiB]");
+  if (t->hist_copies < 1 || t->hist_copies > 8) return fail(MI_E_INVALID, "hist_copies 1..8");
+  std::lock_guard<std::mutex> lk(g_tuning_mu);
+  g_tuning.waves = t->waves;
+  g_tuning.wave_bytes = t->wave_bytes;
+  g_tuning.hist_copies = t->hist_copies;
+  return MI_OK;
+}
+
+extern "C" mi_status mi_tuning_get(mi_tuning *t) {
+  if (!t) return fail(MI_E_INVALID, "mi_tuning_get: NULL");
+  std::lock_guard<std::mutex> lk(g_tuning_mu);
+  t->waves = g_tuning.waves;
+  t->wave_bytes = g_tuning.wave_bytes;
+  t->hist_copies = g_tuning.hist_copies;
+  t->reserved = 0;
+  return MI_OK;
+}
+
+static Tuning tuning_now() {
+  std::lock_guard<std::mutex> lk(g_tuning_mu);
+  return g_tuning;
+}
+
+// ---------------------------------------------------------------- profiling
+
+namespace {
+enum Stage { kStageFrames = 0, kStageEval = 1, kStagePlain = 2 };
+struct Span {
+  hipEvent_t a, b;
+  int stage;
+};
+std::mutex g_prof_mu;
+bool g_prof_on = false;
+std::vector<Span> g_spans;
+std::vector<hipEvent_t> g_event_pool;
+int64_t g_prof_counts[5] = {0, 0, 0, 0, 0};  // frame, eval launches, plain poses, poses, point-poses
+
+hipEvent_t prof_event() {
+  if (!g_event_pool.empty()) {
+    hipEvent_t e = g_event_pool.back();
+    g_event_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+// Records the start event of a stage on `s`; returns false when timing is off.
+bool prof_begin(hipStream_t s, hipEvent_t *a) {
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  if (!g_prof_on) return false;
+  *a = prof_event();
+  if (!*a) return false;
+  if (hipEventRecord(*a, s) != hipSuccess) {
+    g_event_pool.push_back(*a);
+    return false;
+  }
+  return true;
+}
+
+void prof_end(hipStream_t s, hipEvent_t a, int stage, int64_t poses, int64_t point_poses) {
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  hipEvent_t b = prof_event();
+  if (!b || hipEventRecord(b, s) != hipSuccess) return;
+  g_spans.push_back({a, b, stage});
+  if (stage == kStageFrames) g_prof_counts[0] += 1;
+  if (stage == kStageEval) {
+    g_prof_counts[1] += 1;
+    g_prof_counts[3] += poses;
+    g_prof_counts[4] += point_poses;
+  }
+  if (stage == kStagePlain) g_prof_counts[2] += poses;
+}
+}  // namespace
+
+extern "C" mi_status mi_profile_enable(int32_t on) {
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  for (auto &sp : g_spans) {
+    hipEventSynchronize(sp.b);
+    g_event_pool.push_back(sp.a);
+    g_event_pool.push_back(sp.b);
+  }
+  g_spans.clear();
+  for (auto &c : g_prof_counts) c = 0;
+  g_prof_on = on != 0;
+  return MI_OK;
+}
+
+extern "C" mi_status mi_profile_read(mi_profile *out) {
+  if (!out) return fail(MI_E_INVALID, "mi_profile_read: NULL");
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  double ms[3] = {0, 0, 0};
+  for (auto &sp : g_spans) {
+    HIP_TRY(hipEventSynchronize(sp.b), "profile sync");
+    float t = 0.f;
+    HIP_TRY(hipEventElapsedTime(&t, sp.a, sp.b), "profile elapsed");
+    ms[sp.stage] += t;
+    g_event_pool.push_back(sp.a);
+    g_event_pool.push_back(sp.b);
+  }
+  g_spans.clear();
+  out->frames_ms = ms[0];
+  out->eval_ms = ms[1];
+  out->plain_ms = ms[2];
+  out->frame_launches = g_prof_counts[0];
+  out->eval_launches = g_prof_counts[1];
+  out->plain_poses = g_prof_counts[2];
+  out->poses = g_prof_counts[3];
+  out->point_poses = g_prof_counts[4];
+  for (auto &c : g_prof_counts) c = 0;
+  return MI_OK;
+}
+
+// -------------------------------------------------------------------- grid
+
+struct mi_grid {
+  GridInfo gi;
+};
+
+// Default z-variance edges: nb-2 edges log-spaced from 1e-5 m^2 to voxel^2/4,
+// in units of (voxel/2^20)^2, rounded up.
+static int default_zvar_edges(double voxel, int nb, uint64_t *E) {
+  const int m = nb - 2;
+  const double lo = 1e-5, hi = voxel * voxel / 4.0;
+  if (m < 1 || !(hi > lo)) return -1;
+  const double scale = (1048576.0 / voxel) * (1048576.0 / voxel);
+  for (int j = 0; j < m; ++j) {
+    const double e = (m == 1) ? lo : lo * std::pow(hi / lo, (double)j / (double)(m - 1));
+    const double v = std::ceil(e * scale);
+    if (!(v < 1.8446744073709552e19)) return -1;
+    E[j] = (uint64_t)v;
+  }
+  return 0;
+}
+
+extern "C" mi_status mi_grid_create(const mi_grid_desc *d, mi_grid **out) {
+  if (!d || !out) return fail(MI_E_INVALID, "mi_grid_create: NULL argument");
+  *out = nullptr;
+  GridInfo gi;
+  memset(&gi, 0, sizeof gi);
+  for (int a = 0; a < 3; ++a) {
+    if (d->dims[a] < 1) return fail(MI_E_INVALID, "dims[%d] = %d < 1", a, d->dims[a]);
+    if (!std::isfinite(d->origin[a])) return fail(MI_E_INVALID, "origin not finite");
+    gi.origin[a] = d->origin[a];
+    gi.dims[a] = d->dims[a];
+  }
+  gi.V = (int64_t)d->dims[0] * d->dims[1] * d->dims[2];
+  if (gi.V >= ((int64_t)1 << 31)) return fail(MI_E_INVALID, "grid has %lld >= 2^31 voxels",
+                                              (long long)gi.V);
+  if (!(d->voxel > 0.0) || !std::isfinite(d->voxel)) return fail(MI_E_INVALID, "voxel <= 0");
+  gi.voxel = d->voxel;
+  gi.s = 1.0 / d->voxel;
+  if (d->features == 0 || (d->features & ~(MI_FEAT_COUNT | MI_FEAT_ZVAR)))
+    return fail(MI_E_INVALID, "features bitmask %u", d->features);
+  gi.features = d->features;
+  gi.nf = 0;
+  if (d->features & MI_FEAT_COUNT) {
+    const int nb = d->nbins_count;
+    if (nb < 2 || nb > kMaxBins) return fail(MI_E_INVALID, "nbins_count %d not in 2..64", nb);
+    if (d->count_edges) {
+      for (int j = 0; j < nb - 1; ++j) gi.count_edges[j] = d->count_edges[j];
+      if (gi.count_edges[0] < 1) return fail(MI_E_INVALID, "count_edges[0] must be >= 1");
+      for (int j = 1; j < nb - 1; ++j)
+        if (gi.count_edges[j] < gi.count_edges[j - 1])
+          return fail(MI_E_INVALID, "count_edges not ascending");
+    } else {
+      for (int j = 0; j < nb - 1; ++j) gi.count_edges[j] = (uint32_t)(j + 1);
+    }
+    gi.kind[gi.nf] = MI_FEAT_COUNT;
+    gi.nb[gi.nf] = nb;
+    gi.nf++;
+  }
+  if (d->features & MI_FEAT_ZVAR) {
+    const int nb = d->nbins_zvar;
+    if (nb < 3 || nb > kMaxBins) return fail(MI_E_INVALID, "nbins_zvar %d not in 3..64", nb);
+    if (d->zvar_edges) {
+      for (int j = 0; j < nb - 2; ++j) gi.zvar_edges[j] = d->zvar_edges[j];
+      for (int j = 1; j < nb - 2; ++j)
+        if (gi.zvar_edges[j] < gi.zvar_edges[j - 1])
+          return fail(MI_E_INVALID, "zvar_edges not ascending");
+    } else if (default_zvar_edges(d->voxel, nb, gi.zvar_edges)) {
+      return fail(MI_E_INVALID, "default z-variance edges need voxel^2/4 > 1e-5 m^2");
+    }
+    gi.kind[gi.nf] = MI_FEAT_ZVAR;
+    gi.nb[gi.nf] = nb;
+    gi.nf++;
+  }
+  mi_grid *g = (mi_grid *)malloc(sizeof(mi_grid));
+  if (!g) return fail(MI_E_INVALID, "out of host memory");
+  g->gi = gi;
+  *out = g;
+  return MI_OK;
+}
+
+extern "C" void mi_grid_destroy(mi_grid *g) { free(g); }
+
+extern "C" mi_status mi_grid_edges(const mi_grid *g, uint32_t *ce, uint64_t *ze) {
+  if (!g) return fail(MI_E_INVALID, "mi_grid_edges: NULL grid");
+  for (int f = 0; f < g->gi.nf; ++f) {
+    const int nb = g->gi.nb[f];
+    if (g->gi.kind[f] == MI_FEAT_COUNT && ce)
+      for (int j = 0; j < nb - 1; ++j) ce[j] = g->gi.count_edges[j];
+    if (g->gi.kind[f] == MI_FEAT_ZVAR && ze)
+      for (int j = 0; j < nb - 2; ++j) ze[j] = g->gi.zvar_edges[j];
+  }
+  return MI_OK;
+}
+
+// ---------------------------------------------------------------- pose
+
+// R = Rz(yaw) Ry(pitch) Rx(roll), each product and sum rounded on its own.
+static void pose_rotation(const double eta[6], double R[9]) {
+  const double cr = std::cos(eta[3]), sr = std::sin(eta[3]);
+  const double cp = std::cos(eta[4]), sp = std::sin(eta[4]);
+  const double cy = std::cos(eta[5]), sy = std::sin(eta[5]);
+  R[0] = cy * cp;
+  R[1] = (cy * sp) * sr - sy * cr;
+  R[2] = (cy * sp) * cr + sy * sr;
+  R[3] = sy * cp;
+  R[4] = (sy * sp) * sr + cy * cr;
+  R[5] = (sy * sp) * cr - cy * sr;
+  R[6] = -sp;
+  R[7] = cp * sr;
+  R[8] = cp * cr;
+}
+
+extern "C" mi_status mi_pose_to_matrix(const double eta[6], double rt[12]) {
+  if (!eta || !rt) return fail(MI_E_INVALID, "mi_pose_to_matrix: NULL");
+  double R[9];
+  pose_rotation(eta, R);
+  for (int r = 0; r < 3; ++r) {
+    for (int c = 0; c < 3; ++c) rt[4 * r + c] = R[3 * r + c];
+    rt[4 * r + 3] = eta[r];
+  }
+  return MI_OK;
+}
+
+// -------------------------------------------------------------- reference
+
+struct mi_ref {
+  const mi_grid *g;
+  RefDev rd;
+  int64_t n_a;
+};
+
+static size_t ref_layout(const GridInfo &gi, Carver &c, RefDev *rd) {
+  const int64_t V = gi.V;
+  const int64_t plane = (int64_t)(gi.dims[0] + 1) * (gi.dims[1] + 1) * (gi.dims[2] + 1);
+  uint8_t *bins[2] = {nullptr, nullptr};
+  uint32_t *sat[2] = {nullptr, nullptr};
+  for (int f = 0; f < gi.nf; ++f) bins[f] = c.take<uint8_t>((size_t)V);
+  for (int f = 0; f < gi.nf; ++f) sat[f] = c.take<uint32_t>((size_t)plane * (gi.nb[f] - 1));
+  int32_t *abox = c.take<int32_t>(8);
+  unsigned long long *ctr = c.take<unsigned long long>(4);
+  const size_t persistent = c.used();
+  uint32_t *cnt = c.take<uint32_t>((size_t)V);
+  unsigned long long *s1 = c.take<unsigned long long>((size_t)V);
+  unsigned long long *s2 = c.take<unsigned long long>((size_t)V);
+  if (rd) {
+    for (int f = 0; f < 2; ++f) { rd->bins[f] = bins[f]; rd->sat[f] = sat[f]; }
+    rd->abox = abox;
+    rd->counters = ctr;
+    rd->cnt = cnt;
+    rd->s1 = s1;
+    rd->s2 = s2;
+  }
+  return persistent;
+}
+
+extern "C" size_t mi_features_ref_workspace(const mi_grid *g, int64_t, size_t *persistent_bytes) {
+  if (!g) return 0;
+  Carver c(nullptr, 0);
+  const size_t pers = ref_layout(g->gi, c, nullptr);
+  if (persistent_bytes) *persistent_bytes = pers;
+  return c.used() + 256;
+}
+
+extern "C" mi_status mi_features_ref(const mi_grid *g, const float *xyz_a, int64_t n_a, void *ws,
+                                     size_t ws_bytes, void *stream, mi_ref **out) {
+  if (!g || !out) return fail(MI_E_INVALID, "mi_features_ref: NULL argument");
+  *out = nullptr;
+  if (n_a < 0 || (n_a > 0 && !xyz_a)) return fail(MI_E_INVALID, "bad scan A");
+  if (n_a >= ((int64_t)1 << 32)) return fail(MI_E_UNSUPPORTED, "n_a >= 2^32");
+  if (!ws || ((uintptr_t)ws & 255)) return fail(MI_E_WORKSPACE, "workspace NULL or not 256-aligned");
+  const GridInfo &gi = g->gi;
+  Carver c(ws, ws_bytes);
+  RefDev rd;
+  memset(&rd, 0, sizeof rd);
+  ref_layout(gi, c, &rd);
+  if (!c.fits()) return fail(MI_E_WORKSPACE, "features_ref workspace needs %zu bytes, got %zu",
+                             c.used(), ws_bytes);
+  rd.nx = gi.dims[0]; rd.ny = gi.dims[1]; rd.nz = gi.dims[2]; rd.nf = gi.nf;
+  for (int f = 0; f < 2; ++f) { rd.kind[f] = gi.kind[f]; rd.nb[f] = gi.nb[f]; }
+  rd.s = gi.s;
+  for (int a = 0; a < 3; ++a) rd.c0[a] = (0.0 - gi.origin[a]) * gi.s;
+  memcpy(rd.count_edges, gi.count_edges, sizeof rd.count_edges);
+  memcpy(rd.zvar_edges, gi.zvar_edges, sizeof rd.zvar_edges);
+  HIP_TRY(launch_ref(rd, nullptr, xyz_a, n_a, (hipStream_t)stream), "features_ref launch");
+  mi_ref *r = (mi_ref *)malloc(sizeof(mi_ref));
+  if (!r) return fail(MI_E_INVALID, "out of host memory");
+  r->g = g;
+  r->rd = rd;
+  r->n_a = n_a;
+  *out = r;
+  return MI_OK;
+}
+
+extern "C" void mi_ref_destroy(mi_ref *r) { free(r); }
+
+extern "C" mi_status mi_ref_bins(const mi_ref *r, int32_t f, const uint8_t **dev_bins) {
+  if (!r || !dev_bins || f < 0 || f >= r->g->gi.nf)
+    return fail(MI_E_INVALID, "mi_ref_bins: bad argument");
+  *dev_bins = r->rd.bins[f];
+  return MI_OK;
+}
+
+extern "C" mi_status mi_ref_summary(const mi_ref *r, void *stream, int32_t box[6],
+                                    int64_t counters[4]) {
+  if (!r || !box || !counters) return fail(MI_E_INVALID, "mi_ref_summary: NULL");
+  HIP_TRY(hipStreamSynchronize((hipStream_t)stream), "ref summary sync");
+  HIP_TRY(hipMemcpy(box, r->rd.abox, 6 * sizeof(int32_t), hipMemcpyDeviceToHost), "ref box");
+  unsigned long long c[4];
+  HIP_TRY(hipMemcpy(c, r->rd.counters, sizeof c, hipMemcpyDeviceToHost), "ref counters");
+  for (int i = 0; i < 4; ++i) counters[i] = (int64_t)c[i];
+  return MI_OK;
+}
+
+// ------------------------------------------------------------------ plans
+
+namespace {
+
+struct PoseTables {
+  int64_t K = 0;
+  int32_t F = 0;                     // distinct rotations
+  std::vector<double> R;             // [F][9]
+  std::vector<PoseDev> items;        // sorted by frame
+  int32_t gx = 0, gy = 0, ncx = 1, ncy = 1, zlo = 0, zhi = 0;
+};
+
+struct BitsKey {
+  uint64_t w[9];
+  bool operator==(const BitsKey &o) const { return memcmp(w, o.w, sizeof w) == 0; }
+};
+struct BitsHash {
+  size_t operator()(const BitsKey &k) const {
+    uint64_t h = 1469598103934665603ull;
+    for (int i = 0; i < 9; ++i) {
+      h ^= k.w[i];
+      h *= 1099511628211ull;
+    }
+    return (size_t)h;
+  }
+};
+
+// Distinct rotations, per-pose translation offsets c = fl(fl(t - origin) * s),
+// items sorted by frame, and the column grid covering every rotated position
+// from which some pose's offset reaches A's grid.
+int build_tables(const GridInfo &gi, const double *poses, int64_t K, PoseTables &T) {
+  T.K = K;
+  T.R.clear();
+  T.items.resize((size_t)K);
+  std::unordered_map<BitsKey, int32_t, BitsHash> seen;
+  seen.reserve((size_t)K * 2 + 1);
+  std::vector<int32_t> frame_of((size_t)K);
+  double cmin[3] = {INFINITY, INFINITY, INFINITY}, cmax[3] = {-INFINITY, -INFINITY, -INFINITY};
+  for (int64_t k = 0; k < K; ++k) {
+    const double *eta = poses + 6 * k;
+    for (int a = 0; a < 6; ++a)
+      if (!std::isfinite(eta[a])) return -1;
+    double R[9];
+    pose_rotation(eta, R);
+    BitsKey key;
+    memcpy(key.w, R, sizeof key.w);
+    auto it = seen.find(key);
+    int32_t fidx;
+    if (it == seen.end()) {
+      fidx = (int32_t)(T.R.size() / 9);
+      seen.emplace(key, fidx);
+      T.R.insert(T.R.end(), R, R + 9);
+    } else {
+      fidx = it->second;
+    }
+    frame_of[(size_t)k] = fidx;
+    PoseDev &p = T.items[(size_t)k];
+    p.pair = 0;
+    p.frame = fidx;
+    p.out_index = (int32_t)k;
+    p.pad = 0;
+    for (int a = 0; a < 3; ++a) {
+      p.c[a] = (eta[a] - gi.origin[a]) * gi.s;
+      cmin[a] = std::min(cmin[a], p.c[a]);
+      cmax[a] = std::max(cmax[a], p.c[a]);
+    }
+  }
+  T.F = (int32_t)(T.R.size() / 9);
+  std::stable_sort(T.items.begin(), T.items.end(),
+                   [](const PoseDev &a, const PoseDev &b) { return a.frame < b.frame; });
+  if (K == 0) { cmin[0] = cmin[1] = cmin[2] = cmax[0] = cmax[1] = cmax[2] = 0.0; }
+  // v in (-c - eps, dims - c + eps) for some pose: columns floor(v) within
+  // [floor(min(-c)) - 1, floor(max(dims - c)) + 1].
+  const double lo_x = std::floor(-cmax[0]) - 1.0, hi_x = std::floor(gi.dims[0] - cmin[0]) + 1.0;
+  const double lo_y = std::floor(-cmax[1]) - 1.0, hi_y = std::floor(gi.dims[1] - cmin[1]) + 1.0;
+  const double lo_z = std::floor(-cmax[2]) - 1.0, hi_z = std::floor(gi.dims[2] - cmin[2]) + 1.0;
+  if (!(hi_x - lo_x < 1e6 && hi_y - lo_y < 1e6 && std::fabs(lo_x) < 1e9 && std::fabs(lo_y) < 1e9 &&
+        std::fabs(lo_z) < 1e9 && std::fabs(hi_z) < 1e9))
+    return -2;
+  T.gx = (int32_t)lo_x;
+  T.gy = (int32_t)lo_y;
+  T.ncx = (int32_t)(hi_x - lo_x) + 1;
+  T.ncy = (int32_t)(hi_y - lo_y) + 1;
+  T.zlo = (int32_t)lo_z;
+  T.zhi = (int32_t)hi_z;
+  if ((int64_t)T.ncx * T.ncy >= ((int64_t)1 << 31)) return -2;
+  return 0;
+}
+
+struct BrickShape {
+  int bx, by, bpv;
+};
+
+// Largest near-square brick of full height whose sums (bpv bytes per voxel)
+// and occupied list (2 bytes per voxel) fit one wave's LDS slice.
+bool choose_brick(const GridInfo &gi, int wave_bytes, BrickShape &b) {
+  b.bpv = (gi.features & MI_FEAT_ZVAR) ? 16 : 4;
+  const int per_vox = b.bpv + 2;
+  int64_t bvox = (wave_bytes - eval_row_table_bytes()) / per_vox;
+  bvox = std::min<int64_t>(bvox, 65536);
+  const int nz = gi.dims[2];
+  int64_t cols = bvox / nz;
+  if (cols < 1) return false;
+  int by = (int)std::floor(std::sqrt((double)cols));
+  by = std::max(1, std::min(by, std::min(gi.dims[1], 61)));
+  int bx = (int)std::min<int64_t>(cols / by, gi.dims[0]);
+  if (bx < 1) return false;
+  // when x is the short side, give the rest to y
+  if (bx == gi.dims[0]) by = std::max(1, (int)std::min<int64_t>(cols / bx, std::min(gi.dims[1], 61)));
+  b.bx = bx;
+  b.by = by;
+  return true;
+}
+
+size_t frame_bytes(int64_t n_b, int64_t ncols) {
+  auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
+  return al((size_t)n_b * 3 * sizeof(double)) + al((size_t)(ncols + 1) * 4) + al((size_t)ncols * 4);
+}
+
+}  // namespace
+
+struct mi_plan {
+  const mi_ref *ref;
+  int64_t n_b, K;
+  uint32_t flags;
+  int32_t F, F_chunk, n_chunks;
+  int64_t ncols;
+  std::vector<int64_t> chunk_items;  // [n_chunks + 1] over the frame-sorted items
+  PoseDev *items_dev;
+  PairDev *pairs_dev;                // [n_chunks]
+  FrameDev *frames_dev;              // [F]
+  uint32_t *fcur;                    // cursor region of one chunk
+  unsigned long long *nonfinite;
+  EvalLaunch launch;
+};
+
+namespace {
+
+struct PlanLayout {
+  PoseDev *items;
+  PairDev *pairs;
+  FrameDev *frames;
+  double *fv;
+  uint32_t *foff, *fcur;
+  unsigned long long *nonfinite;
+};
+
+void plan_layout(int64_t K, int32_t F, int32_t F_chunk, int32_t n_chunks, int64_t n_b,
+                 int64_t ncols, Carver &c, PlanLayout *L) {
+  PoseDev *items = c.take<PoseDev>((size_t)std::max<int64_t>(K, 1));
+  PairDev *pairs = c.take<PairDev>((size_t)std::max(n_chunks, 1));
+  FrameDev *frames = c.take<FrameDev>((size_t)std::max(F, 1));
+  unsigned long long *nf = c.take<unsigned long long>(2);
+  const size_t nbp = (size_t)std::max<int64_t>(n_b, 1);
+  double *fv = c.take<double>((size_t)F_chunk * 3 * nbp);
+  uint32_t *foff = c.take<uint32_t>((size_t)F_chunk * (size_t)(ncols + 1));
+  uint32_t *fcur = c.take<uint32_t>((size_t)F_chunk * (size_t)ncols);
+  if (L) {
+    L->items = items; L->pairs = pairs; L->frames = frames; L->fv = fv;
+    L->foff = foff; L->fcur = fcur; L->nonfinite = nf;
+  }
+}
+
+int32_t chunk_frames(int32_t F, int64_t n_b, int64_t ncols, size_t budget) {
+  if (F <= 0) return 1;
+  if (budget == 0) budget = (size_t)4 << 30;
+  const size_t fb = frame_bytes(n_b, ncols);
+  int64_t fc = (int64_t)(budget / std::max<size_t>(fb, 1));
+  fc = std::max<int64_t>(1, std::min<int64_t>(fc, F));
+  return (int32_t)fc;
+}
+
+size_t plan_bytes(int64_t K, int32_t F, int64_t ncols, int64_t n_b, size_t budget) {
+  const int32_t fc = chunk_frames(F, n_b, ncols, budget);
+  const int32_t nch = F > 0 ? (F + fc - 1) / fc : 1;
+  Carver c(nullptr, 0);
+  plan_layout(K, F, fc, nch, n_b, ncols, c, nullptr);
+  return c.used() + 256;
+}
+
+}  // namespace
+
+extern "C" size_t mi_eval_poses_workspace(const mi_ref *r, int64_t n_b, const double *poses,
+                                          int64_t K, uint32_t, size_t budget) {
+  if (!r || K < 0 || n_b < 0 || (K > 0 && !poses)) return 0;
+  PoseTables T;
+  if (build_tables(r->g->gi, poses, K, T)) return 0;
+  return plan_bytes(K, T.F, (int64_t)T.ncx * T.ncy, n_b, budget);
+}
+
+extern "C" mi_status mi_plan_create(const mi_ref *r, int64_t n_b, const double *poses, int64_t K,
+                                    uint32_t flags, void *ws, size_t ws_bytes, size_t budget,
+                                    void *stream, mi_plan **out) {
+  if (!r || !out) return fail(MI_E_INVALID, "mi_plan_create: NULL argument");
+  *out = nullptr;
+  if (K < 0 || n_b < 0 || (K > 0 && !poses)) return fail(MI_E_INVALID, "bad pose set or scan B");
+  if (K >= ((int64_t)1 << 31)) return fail(MI_E_UNSUPPORTED, "more than 2^31 poses");
+  if (flags & ~(uint32_t)MI_EVAL_NEAR_FACE) return fail(MI_E_INVALID, "unknown flags");
+  const GridInfo &gi = r->g->gi;
+  if ((gi.features & MI_FEAT_ZVAR) && n_b >= MI_MAX_POINTS)
+    return fail(MI_E_UNSUPPORTED, "scan B has %lld >= 2^20 points with the z-variance feature",
+                (long long)n_b);
+  if (n_b >= ((int64_t)1 << 32)) return fail(MI_E_UNSUPPORTED, "scan B has >= 2^32 points");
+  if (!ws || ((uintptr_t)ws & 255)) return fail(MI_E_WORKSPACE, "workspace NULL or not 256-aligned");
+  PoseTables T;
+  const int bt = build_tables(gi, poses, K, T);
+  if (bt == -1) return fail(MI_E_INVALID, "non-finite pose");
+  if (bt) return fail(MI_E_UNSUPPORTED, "pose translations span too large a range");
+  const int64_t ncols = (int64_t)T.ncx * T.ncy;
+
+  const Tuning tu = tuning_now();
+  BrickShape bs;
+  if (!choose_brick(gi, tu.wave_bytes, bs))
+    return fail(MI_E_UNSUPPORTED, "grid height %d does not fit a brick of %d LDS bytes",
+                gi.dims[2], tu.wave_bytes);
+  EvalLaunch L;
+  L.waves = tu.waves;
+  L.wave_bytes = tu.wave_bytes;
+  L.hist_copies = tu.hist_copies;
+  L.hist_words = gi.nb[0] * gi.nb[0] + (gi.nf > 1 ? gi.nb[1] * gi.nb[1] : 0);
+  L.near_face = (flags & MI_EVAL_NEAR_FACE) != 0;
+  if ((int64_t)eval_lds_bytes(L) > max_lds_per_block())
+    return fail(MI_E_UNSUPPORTED, "tuning needs %zu LDS bytes per workgroup, device has %d",
+                eval_lds_bytes(L), max_lds_per_block());
+
+  // Frames per chunk: from the budget when given, else as many as fit the
+  // workspace (all of them when it was sized by mi_eval_poses_workspace).
+  int32_t fc = chunk_frames(T.F, n_b, ncols, budget);
+  if (budget == 0 && T.F > 0) {
+    int32_t lo = 1, hi = T.F;
+    while (lo < hi) {
+      const int32_t mid = lo + (hi - lo + 1) / 2;
+      Carver probe(nullptr, 0);
+      plan_layout(K, T.F, mid, (T.F + mid - 1) / mid, n_b, ncols, probe, nullptr);
+      if (probe.used() + 256 <= ws_bytes) lo = mid; else hi = mid - 1;
+    }
+    fc = lo;
+  }
+  const int32_t nch = T.F > 0 ? (T.F + fc - 1) / fc : 1;
+  Carver c(ws, ws_bytes);
+  PlanLayout PL;
+  plan_layout(K, T.F, fc, nch, n_b, ncols, c, &PL);
+  if (!c.fits())
+    return fail(MI_E_WORKSPACE, "eval workspace needs %zu bytes, got %zu", c.used() + 256,
+                ws_bytes);
+
+  mi_plan *p = new (std::nothrow) mi_plan();
+  if (!p) return fail(MI_E_INVALID, "out of host memory");
+  p->ref = r;
+  p->n_b = n_b;
+  p->K = K;
+  p->flags = flags;
+  p->F = T.F;
+  p->F_chunk = fc;
+  p->n_chunks = nch;
+  p->ncols = ncols;
+  p->items_dev = PL.items;
+  p->pairs_dev = PL.pairs;
+  p->frames_dev = PL.frames;
+  p->fcur = PL.fcur;
+  p->nonfinite = PL.nonfinite;
+  p->launch = L;
+  p->chunk_items.assign((size_t)nch + 1, K);
+  {
+    int64_t k = 0;
+    for (int32_t ch = 0; ch < nch; ++ch) {
+      p->chunk_items[(size_t)ch] = k;
+      const int32_t fend = std::min<int32_t>(T.F, (ch + 1) * fc);
+      while (k < K && T.items[(size_t)k].frame < fend) ++k;
+    }
+    p->chunk_items[(size_t)nch] = K;
+  }
+  for (auto &it : T.items) it.frame = it.frame % fc;
+
+  const RefDev &rd = r->rd;
+  const size_t nbp = (size_t)std::max<int64_t>(n_b, 1);
+  std::vector<PairDev> pairs((size_t)nch);
+  for (int32_t ch = 0; ch < nch; ++ch) {
+    PairDev &P = pairs[(size_t)ch];
+    memset(&P, 0, sizeof P);
+    P.nx = gi.dims[0]; P.ny = gi.dims[1]; P.nz = gi.dims[2]; P.nf = gi.nf;
+    for (int f = 0; f < 2; ++f) {
+      P.kind[f] = gi.kind[f];
+      P.nb[f] = gi.nb[f];
+      P.binA[f] = rd.bins[f];
+      P.sat[f] = rd.sat[f];
+    }
+    P.voxel = gi.voxel;
+    P.abox = rd.abox;
+    P.fv = PL.fv;
+    P.fstride = (int64_t)nbp;
+    P.foff = PL.foff;
+    P.gx = T.gx; P.gy = T.gy; P.ncx = T.ncx; P.ncy = T.ncy;
+    P.bx = bs.bx; P.by = bs.by;
+    P.nbx = (gi.dims[0] + bs.bx - 1) / bs.bx;
+    P.nby = (gi.dims[1] + bs.by - 1) / bs.by;
+    P.bpv = bs.bpv;
+    P.nonfinite = PL.nonfinite;
+    P.n_b = n_b;
+    P.K = K;
+    P.hist_off[0] = 0;
+    P.hist_off[1] = K * (int64_t)gi.nb[0] * gi.nb[0];
+    memcpy(P.count_edges, gi.count_edges, sizeof P.count_edges);
+    memcpy(P.zvar_edges, gi.zvar_edges, sizeof P.zvar_edges);
+  }
+  std::vector<FrameDev> frames((size_t)T.F);
+  for (int32_t f = 0; f < T.F; ++f) {
+    FrameDev &Fd = frames[(size_t)f];
+    memset(&Fd, 0, sizeof Fd);
+    memcpy(Fd.R, &T.R[(size_t)f * 9], sizeof Fd.R);
+    Fd.s = gi.s;
+    Fd.n = n_b;
+    Fd.gx = T.gx; Fd.gy = T.gy; Fd.ncx = T.ncx; Fd.ncy = T.ncy;
+    Fd.zlo = T.zlo; Fd.zhi = T.zhi;
+    const size_t slot = (size_t)(f % fc);
+    Fd.v = PL.fv + slot * 3 * nbp;
+    Fd.off = PL.foff + slot * (size_t)(ncols + 1);
+    Fd.cur = PL.fcur + slot * (size_t)ncols;
+  }
+  const size_t b_items = sizeof(PoseDev) * (size_t)K, b_pairs = sizeof(PairDev) * pairs.size(),
+               b_frames = sizeof(FrameDev) * frames.size();
+  hipError_t e = hipSuccess;
+  Staging *st = staging_acquire(b_items + b_pairs + b_frames + 64, &e);
+  if (!st) { delete p; return dev_fail(e, "pinned staging"); }
+  char *h = (char *)st->p;
+  if (b_items) memcpy(h, T.items.data(), b_items);
+  memcpy(h + b_items, pairs.data(), b_pairs);
+  if (b_frames) memcpy(h + b_items + b_pairs, frames.data(), b_frames);
+  const Upload ups[3] = {{PL.items, 0, b_items}, {PL.pairs, b_items, b_pairs},
+                         {PL.frames, b_items + b_pairs, b_frames}};
+  e = staging_upload(st, ups, 3, (hipStream_t)stream);
+  if (e != hipSuccess) { delete p; return dev_fail(e, "pose table upload"); }
+  *out = p;
+  return MI_OK;
+}
+
+extern "C" mi_status mi_plan_execute(mi_plan *p, const float *xyz_b, double *mi_out,
+                                     int64_t *argmax_out, uint32_t *hist_out,
+                                     mi_pose_stats *stats_out, void *stream) {
+  if (!p) return fail(MI_E_INVALID, "mi_plan_execute: NULL plan");
+  if (p->K > 0 && !mi_out) return fail(MI_E_INVALID, "mi_out is NULL");
+  if (p->n_b > 0 && !xyz_b) return fail(MI_E_INVALID, "xyz_b is NULL");
+  hipStream_t s = (hipStream_t)stream;
+  HIP_TRY(launch_bind(p->pairs_dev, p->n_chunks, p->frames_dev, p->F, xyz_b, mi_out, hist_out,
+                      stats_out, s), "bind");
+  HIP_TRY(launch_count_nonfinite(xyz_b, p->n_b, p->nonfinite, s), "count non-finite");
+  for (int32_t ch = 0; ch < p->n_chunks; ++ch) {
+    const int32_t f0 = ch * p->F_chunk;
+    const int32_t nfr = std::min(p->F_chunk, p->F - f0);
+    if (nfr > 0) {
+      hipEvent_t a = nullptr;
+      const bool timed = prof_begin(s, &a);
+      HIP_TRY(launch_fill_u32(p->fcur, 0u, (int64_t)nfr * p->ncols, s), "clear column counts");
+      HIP_TRY(launch_frames(p->frames_dev + f0, nfr, p->n_b, (int32_t)std::min<int64_t>(
+                            p->ncols, 0x7fffffff), s), "frames");
+      if (timed) prof_end(s, a, kStageFrames, 0, 0);
+    }
+    const int64_t i0 = p->chunk_items[(size_t)ch], i1 = p->chunk_items[(size_t)ch + 1];
+    hipEvent_t a = nullptr;
+    const bool timed = prof_begin(s, &a);
+    HIP_TRY(launch_eval(p->pairs_dev + ch, p->items_dev + i0, i1 - i0, p->launch, s), "eval");
+    if (timed) prof_end(s, a, kStageEval, i1 - i0, (i1 - i0) * p->n_b);
+  }
+  if (argmax_out && p->K > 0)
+    HIP_TRY(launch_argmax(mi_out, p->K, p->ref->g->gi.nf, argmax_out, nullptr, s), "argmax");
+  return MI_OK;
+}
+
+extern "C" void mi_plan_destroy(mi_plan *p) { delete p; }
+
+extern "C" mi_status mi_eval_poses(const mi_ref *r, const float *xyz_b, int64_t n_b,
+                                   const double *poses, int64_t K, uint32_t flags, double *mi_out,
+                                   int64_t *argmax_out, uint32_t *hist_out,
+                                   mi_pose_stats *stats_out, void *ws, size_t ws_bytes,
+                                   void *stream) {
+  mi_plan *p = nullptr;
+  mi_status st = mi_plan_create(r, n_b, poses, K, flags, ws, ws_bytes, 0, stream, &p);
+  if (st != MI_OK) return st;
+  st = mi_plan_execute(p, xyz_b, mi_out, argmax_out, hist_out, stats_out, stream);
+  mi_plan_destroy(p);
+  return st;
+}
+
+// ---------------------------------------------------------------- plain
+
+namespace {
+struct PlainLayout {
+  PlainDev pd;
+  double *rc;
+};
+
+void plain_layout(const GridInfo &gi, int64_t n_b, int64_t K, Carver &c, PlainLayout *L) {
+  const int64_t V = gi.V;
+  const size_t nbp = (size_t)std::max<int64_t>(n_b, 1);
+  uint32_t *dn = c.take<uint32_t>((size_t)V);
+  unsigned long long *ds1 = c.take<unsigned long long>((size_t)V);
+  unsigned long long *ds2 = c.take<unsigned long long>((size_t)V);
+  int32_t *lin = c.take<int32_t>(nbp);
+  uint32_t *q = c.take<uint32_t>(nbp);
+  uint8_t *near = c.take<uint8_t>(nbp);
+  int32_t *bbox = c.take<int32_t>(8);
+  unsigned long long *ctr = c.take<unsigned long long>(4);
+  uint32_t *hist = c.take<uint32_t>(2 * kMaxBins * kMaxBins);
+  double *rc = c.take<double>((size_t)std::max<int64_t>(K, 1) * 12);
+  if (L) {
+    L->pd.dn = dn; L->pd.ds1 = ds1; L->pd.ds2 = ds2; L->pd.lin = lin; L->pd.q = q;
+    L->pd.near = near; L->pd.bbox = bbox; L->pd.ctr = ctr; L->pd.hist = hist;
+    L->rc = rc;
+  }
+}
+}  // namespace
+
+extern "C" size_t mi_eval_poses_plain_workspace(const mi_ref *r, int64_t n_b, int64_t K) {
+  if (!r || n_b < 0 || K < 0) return 0;
+  Carver c(nullptr, 0);
+  plain_layout(r->g->gi, n_b, K, c, nullptr);
+  return c.used() + 256;
+}
+
+extern "C" mi_status mi_eval_poses_plain(const mi_ref *r, const float *xyz_b, int64_t n_b,
+                                         const double *poses, int64_t K, uint32_t flags,
+                                         double *mi_out, int64_t *argmax_out, uint32_t *hist_out,
+                                         mi_pose_stats *stats_out, void *ws, size_t ws_bytes,
+                                         void *stream) {
+  if (!r) return fail(MI_E_INVALID, "mi_eval_poses_plain: NULL ref");
+  if (K < 0 || n_b < 0 || (K > 0 && (!poses || !mi_out)) || (n_b > 0 && !xyz_b))
+    return fail(MI_E_INVALID, "bad arguments");
+  if (flags & ~(uint32_t)MI_EVAL_NEAR_FACE) return fail(MI_E_INVALID, "unknown flags");
+  if (n_b >= ((int64_t)1 << 31)) return fail(MI_E_UNSUPPORTED, "scan B too large");
+  if (!ws || ((uintptr_t)ws & 255)) return fail(MI_E_WORKSPACE, "workspace NULL or not 256-aligned");
+  const GridInfo &gi = r->g->gi;
+  Carver c(ws, ws_bytes);
+  PlainLayout PL;
+  memset(&PL, 0, sizeof PL);
+  plain_layout(gi, n_b, K, c, &PL);
+  if (!c.fits())
+    return fail(MI_E_WORKSPACE, "plain workspace needs %zu bytes, got %zu", c.used() + 256,
+                ws_bytes);
+  for (int64_t k = 0; k < K; ++k)
+    for (int a = 0; a < 6; ++a)
+      if (!std::isfinite(poses[6 * k + a])) return fail(MI_E_INVALID, "non-finite pose");
+  PlainDev &pd = PL.pd;
+  pd.nx = gi.dims[0]; pd.ny = gi.dims[1]; pd.nz = gi.dims[2]; pd.nf = gi.nf;
+  for (int f = 0; f < 2; ++f) {
+    pd.kind[f] = gi.kind[f];
+    pd.nb[f] = gi.nb[f];
+    pd.binA[f] = r->rd.bins[f];
+  }
+  pd.voxel = gi.voxel;
+  pd.s = gi.s;
+  pd.abox = r->rd.abox;
+  memcpy(pd.count_edges, gi.count_edges, sizeof pd.count_edges);
+  memcpy(pd.zvar_edges, gi.zvar_edges, sizeof pd.zvar_edges);
+  hipStream_t s = (hipStream_t)stream;
+  if (K == 0) return MI_OK;
+  hipError_t e = hipSuccess;
+  const size_t bytes = sizeof(double) * 12 * (size_t)K;
+  Staging *st = staging_acquire(bytes, &e);
+  if (!st) return dev_fail(e, "pinned staging");
+  double *h = (double *)st->p;
+  for (int64_t k = 0; k < K; ++k) {
+    const double *eta = poses + 6 * k;
+    pose_rotation(eta, h + 12 * k);
+    for (int a = 0; a < 3; ++a) h[12 * k + 9 + a] = (eta[a] - gi.origin[a]) * gi.s;
+  }
+  const Upload up = {PL.rc, 0, bytes};
+  HIP_TRY(staging_upload(st, &up, 1, s), "plain pose upload");
+  HIP_TRY(launch_plain_clear_dense(pd, s), "plain clear");
+  const int64_t hoff[2] = {0, K * (int64_t)gi.nb[0] * gi.nb[0]};
+  hipEvent_t a = nullptr;
+  const bool timed = prof_begin(s, &a);
+  for (int64_t k = 0; k < K; ++k)
+    HIP_TRY(launch_plain_pose(pd, nullptr, xyz_b, n_b, PL.rc, k, mi_out, K, hist_out, hoff,
+                              stats_out, (flags & MI_EVAL_NEAR_FACE) != 0, s),
+            "plain pose");
+  if (timed) prof_end(s, a, kStagePlain, K, K * n_b);
+  if (argmax_out) HIP_TRY(launch_argmax(mi_out, K, gi.nf, argmax_out, nullptr, s), "argmax");
+  return MI_OK;
+}
+
+// ------------------------------------------------------------ coarse-to-fine
+
+namespace {
+bool c2f_ok(const mi_c2f_desc *d, int nf) {
+  if (!d || d->levels < 1 || !(d->shrink > 0.0) || !std::isfinite(d->shrink)) return false;
+  if (d->feature_slot < 0 || d->feature_slot >= nf) return false;
+  for (int a = 0; a < 6; ++a)
+    if (d->samples[a] < 1 || d->samples[a] > 1024 || !std::isfinite(d->half_range[a]) ||
+        d->half_range[a] < 0.0)
+      return false;
+  return true;
+}
+
+int64_t c2f_count(const mi_c2f_desc *d) {
+  int64_t K = 1;
+  for (int a = 0; a < 6; ++a) K *= d->samples[a];
+  return K;
+}
+
+// One level's grid: per axis c + h*(-1 + 2j/(s-1)) (c when s = 1), row-major
+// over (tx, ty, tz, roll, pitch, yaw) with yaw fastest.
+void c2f_grid(const double c[6], const double h[6], const int32_t samples[6],
+              std::vector<double> &P) {
+  int64_t K = 1;
+  for (int a = 0; a < 6; ++a) K *= samples[a];
+  P.resize((size_t)K * 6);
+  for (int64_t k = 0; k < K; ++k) {
+    int64_t r = k;
+    int32_t j[6];
+    for (int a = 5; a >= 0; --a) {
+      j[a] = (int32_t)(r % samples[a]);
+      r /= samples[a];
+    }
+    for (int a = 0; a < 6; ++a) {
+      const int32_t sa = samples[a];
+      P[(size_t)k * 6 + a] =
+          sa == 1 ? c[a] : c[a] + h[a] * (-1.0 + (2.0 * j[a]) / (double)(sa - 1));
+    }
+  }
+}
+}  // namespace
+
+extern "C" size_t mi_align_workspace(const mi_ref *r, int64_t n_b, const mi_c2f_desc *d) {
+  if (!r || n_b < 0 || !c2f_ok(d, r->g->gi.nf)) return 0;
+  const GridInfo &gi = r->g->gi;
+  const int64_t K = c2f_count(d);
+  int64_t F = (int64_t)d->samples[3] * d->samples[4] * d->samples[5];
+  // column grid of the widest level (level 0), plus slack for its position
+  const double zero[6] = {0, 0, 0, 0, 0, 0};
+  std::vector<double> P;
+  c2f_grid(zero, d->half_range, d->samples, P);
+  PoseTables T;
+  if (build_tables(gi, P.data(), K, T)) return 0;
+  const int64_t ncols = (int64_t)(T.ncx + 2) * (T.ncy + 2);
+  Carver c(nullptr, 0);
+  c.take<double>((size_t)gi.nf * (size_t)K);
+  c.take<int64_t>(2 * 8);
+  return c.used() + plan_bytes(K, (int32_t)F, ncols, n_b, 0) + 512;
+}
+
+extern "C" mi_status mi_align_coarse_to_fine(const mi_ref *r, const float *xyz_b, int64_t n_b,
+                                             const double init[6], const mi_c2f_desc *d,
+                                             double pose_out[6], double *mi_best, void *ws,
+                                             size_t ws_bytes, void *stream) {
+  if (!r || !init || !pose_out) return fail(MI_E_INVALID, "mi_align_coarse_to_fine: NULL");
+  const GridInfo &gi = r->g->gi;
+  if (!c2f_ok(d, gi.nf)) return fail(MI_E_INVALID, "bad coarse-to-fine description");
+  for (int a = 0; a < 6; ++a)
+    if (!std::isfinite(init[a])) return fail(MI_E_INVALID, "non-finite initial pose");
+  if (!ws || ((uintptr_t)ws & 255)) return fail(MI_E_WORKSPACE, "workspace NULL or not 256-aligned");
+  const int64_t K = c2f_count(d);
+  Carver c(ws, ws_bytes);
+  double *mi_dev = c.take<double>((size_t)gi.nf * (size_t)K);
+  int64_t *am_dev = c.take<int64_t>(2);
+  double *mv_dev = c.take<double>(2);
+  c.take<char>(0);
+  if (!c.fits()) return fail(MI_E_WORKSPACE, "align workspace too small");
+  void *plan_ws = (void *)c.cur;
+  const size_t plan_room = ws_bytes - c.used();
+  hipStream_t s = (hipStream_t)stream;
+  double ctr[6], h[6];
+  for (int a = 0; a < 6; ++a) { ctr[a] = init[a]; h[a] = d->half_range[a]; }
+  std::vector<double> P;
+  double best = 0.0;
+  for (int32_t l = 0; l < d->levels; ++l) {
+    c2f_grid(ctr, h, d->samples, P);
+    mi_plan *p = nullptr;
+    mi_status st = mi_plan_create(r, n_b, P.data(), K, 0, plan_ws, plan_room, 0, stream, &p);
+    if (st != MI_OK) return st;
+    st = mi_plan_execute(p, xyz_b, mi_dev, nullptr, nullptr, nullptr, stream);
+    mi_plan_destroy(p);
+    if (st != MI_OK) return st;
+    HIP_TRY(launch_argmax(mi_dev + (int64_t)d->feature_slot * K, K, 1, am_dev, mv_dev, s),
+            "argmax");
+    int64_t kbest = 0;
+    double mv = 0.0;
+    HIP_TRY(hipMemcpyAsync(&kbest, am_dev, sizeof kbest, hipMemcpyDeviceToHost, s), "argmax D2H");
+    HIP_TRY(hipMemcpyAsync(&mv, mv_dev, sizeof mv, hipMemcpyDeviceToHost, s), "MI D2H");
+    HIP_TRY(hipStreamSynchronize(s), "level sync");
+    if (kbest < 0 || kbest >= K) return fail(MI_E_DEVICE, "argmax out of range");
+    for (int a = 0; a < 6; ++a) ctr[a] = P[(size_t)kbest * 6 + a];
+    best = mv;
+    for (int a = 0; a < 6; ++a) h[a] = h[a] / d->shrink;
+  }
+  for (int a = 0; a < 6; ++a) pose_out[a] = ctr[a];
+  if (mi_best) *mi_best = best;
+  return MI_OK;
+}

@@ -1,0 +1,81 @@
+// mi_device.h -- device helpers shared by the kernels of libmi355.so.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace mi {
+
+typedef unsigned __int128 u128;
+
+// Point-count feature (Sec. III-A, number of points in the voxel):
+// bin = #{j : n >= e[j]} over nb-1 non-decreasing edges (binary search).
+__device__ __forceinline__ int bin_count_dev(uint32_t n, int nb, const uint32_t *e) {
+  int lo = 0, hi = nb - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (n >= e[mid - 1]) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+// z-height variance feature (Sec. III-A, variance of z in the voxel) on the
+// fixed-point heights q: empty -> 0, else 1 + #{j : n*S2 - S1^2 >= E[j]*n^2}
+// over nb-2 non-decreasing edges, exact in 128-bit integers.
+__device__ __forceinline__ int bin_zvar_dev(uint32_t n, uint64_t s1, uint64_t s2, int nb,
+                                            const uint64_t *E) {
+  if (n == 0) return 0;
+  const u128 D = (u128)n * (u128)s2 - (u128)s1 * (u128)s1;
+  const u128 n2 = (u128)n * (u128)n;
+  int lo = 0, hi = nb - 2;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (D >= (u128)E[mid - 1] * n2) lo = mid; else hi = mid - 1;
+  }
+  return 1 + lo;
+}
+
+// Entropy term -p ln p for a count c out of N (0 ln 0 = 0), Eqs. 3-5.
+__device__ __forceinline__ double plogp_term(uint64_t c, double N) {
+  if (c == 0) return 0.0;
+  const double p = (double)c / N;
+  return -p * log(p);
+}
+
+__device__ __forceinline__ double wave_sum_f64(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+__device__ __forceinline__ int wave_min_i32(int v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o, 64));
+  return v;
+}
+
+__device__ __forceinline__ int wave_max_i32(int v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o, 64));
+  return v;
+}
+
+__device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// Box count of a summed-volume table with dims (nx+1)(ny+1)(nz+1):
+// number of marked voxels in [x0,x1] x [y0,y1] x [z0,z1] (inclusive).
+__device__ __forceinline__ uint32_t sat_box(const uint32_t *S, int nx, int ny, int x0, int y0,
+                                            int z0, int x1, int y1, int z1) {
+  const int64_t sx = 1, sy = nx + 1, sz = (int64_t)(nx + 1) * (ny + 1);
+  const int64_t X0 = x0, X1 = x1 + 1, Y0 = y0, Y1 = y1 + 1, Z0 = z0, Z1 = z1 + 1;
+  auto at = [&](int64_t x, int64_t y, int64_t z) { return (int64_t)S[z * sz + y * sy + x * sx]; };
+  const int64_t v = at(X1, Y1, Z1) - at(X0, Y1, Z1) - at(X1, Y0, Z1) - at(X1, Y1, Z0) +
+                    at(X0, Y0, Z1) + at(X0, Y1, Z0) + at(X1, Y0, Z0) - at(X0, Y0, Z0);
+  return (uint32_t)v;
+}
+
+}  // namespace mi

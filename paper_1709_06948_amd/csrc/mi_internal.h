@@ -1,0 +1,164 @@
+// mi_internal.h -- device-side tables and launch wrappers shared by the HIP
+// sources of libmi355.so.  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "mi.h"
+
+namespace mi {
+
+constexpr int kMaxBins = MI_MAX_BINS;
+constexpr int kXcds = 8;              // MI355X: 8 XCDs, workgroups dispatched round-robin
+constexpr double kColEps = 1e-6;      // padding (voxel units) of candidate column ranges
+constexpr double kQScale = 1048576.0; // 2^20: z quantum per voxel
+constexpr double kNearFace = 1e-5;    // m
+
+// Grid + feature description, host copy of the validated descriptor.
+struct GridInfo {
+  double origin[3];
+  int32_t dims[3];
+  double voxel;
+  double s;       // fl(1/voxel)
+  uint32_t features;
+  int32_t nf;     // number of enabled features (1 or 2)
+  uint32_t kind[2];
+  int32_t nb[2];
+  int64_t V;
+  uint32_t count_edges[kMaxBins];
+  uint64_t zvar_edges[kMaxBins];
+};
+
+// ------------------------------------------------------------------ reference
+
+struct RefDev {
+  int32_t nx, ny, nz, nf;
+  uint32_t kind[2];
+  int32_t nb[2];
+  double s;
+  double c0[3];              // fl(fl(0 - origin) * s)
+  uint32_t count_edges[kMaxBins];
+  uint64_t zvar_edges[kMaxBins];
+  // transient dense sums
+  uint32_t *cnt;
+  unsigned long long *s1, *s2;
+  // resident
+  uint8_t *bins[2];          // [V] per feature slot
+  uint32_t *sat[2];          // [(nb-1)][(nz+1)(ny+1)(nx+1)] per feature slot
+  int32_t *abox;             // lo[3], hi[3]
+  unsigned long long *counters; // in, out, nonfinite, occupied
+};
+
+hipError_t launch_ref(const RefDev &rd, const RefDev *rd_dev, const float *xyz, int64_t n,
+                      hipStream_t s);
+
+// ------------------------------------------------------------------- frames
+
+// One distinct rotation of scan B: the points rotated and scaled to voxel
+// units (v = fl(fl(R p) * s)), bucketed by column of A's grid.
+struct FrameDev {
+  double R[9];
+  double s;
+  const float *xyz;
+  int64_t n;                 // points of scan B
+  int32_t gx, gy, ncx, ncy;  // column grid: column (cx, cy) holds floor(v) = (gx + cx, gy + cy)
+  int32_t zlo, zhi;          // kept when zlo <= floor(v_z) <= zhi
+  double *v;                 // sorted SoA, stride n: x, y, z
+  uint32_t *off;             // [ncx*ncy + 1]
+  uint32_t *cur;             // [ncx*ncy] counts, then cursors
+};
+
+hipError_t launch_frames(const FrameDev *frames_dev, int32_t n_frames, int64_t max_points,
+                         int32_t max_cols, hipStream_t s);
+
+// --------------------------------------------------------------------- eval
+
+// One scan pair (A resident, B bucketed) for one chunk of frames.
+struct PairDev {
+  int32_t nx, ny, nz, nf;
+  uint32_t kind[2];
+  int32_t nb[2];
+  double voxel;
+  const uint8_t *binA[2];
+  const uint32_t *sat[2];
+  const int32_t *abox;
+  const double *fv;          // frame f of this chunk at fv + f * 3 * fstride
+  int64_t fstride;
+  const uint32_t *foff;      // frame f at foff + f * (ncols + 1)
+  int32_t gx, gy, ncx, ncy;
+  int32_t bx, by, nbx, nby;  // bricks: bx * by columns, full height
+  int32_t bpv;               // LDS bytes per brick voxel: 4 (count only) or 16
+  int32_t pad0;
+  const unsigned long long *nonfinite; // device counter
+  int64_t n_b;
+  double *mi_out;
+  int64_t K;                 // feature stride of mi_out
+  uint32_t *hist_out;
+  int64_t hist_off[2];
+  mi_pose_stats *stats_out;
+  uint32_t count_edges[kMaxBins];
+  uint64_t zvar_edges[kMaxBins];
+};
+
+struct PoseDev {
+  int32_t pair;
+  int32_t frame;             // frame index within the chunk
+  int32_t out_index;         // pose index in the caller's order
+  int32_t pad;
+  double c[3];               // fl(fl(t - origin) * s)
+};
+
+struct EvalLaunch {
+  int32_t waves;             // waves per workgroup
+  int32_t wave_bytes;        // LDS bytes per wave for its brick
+  int32_t hist_copies;       // privatized histogram copies per workgroup
+  int32_t hist_words;        // max over pairs of sum_f nb_f^2
+  bool near_face;
+};
+
+hipError_t launch_eval(const PairDev *pairs_dev, const PoseDev *items_dev, int64_t n_items,
+                       const EvalLaunch &cfg, hipStream_t s);
+size_t eval_lds_bytes(const EvalLaunch &cfg);
+int32_t eval_row_table_bytes();
+
+// -------------------------------------------------------------------- plain
+
+struct PlainDev {
+  int32_t nx, ny, nz, nf;
+  uint32_t kind[2];
+  int32_t nb[2];
+  double voxel, s;
+  const uint8_t *binA[2];
+  const int32_t *abox;
+  uint32_t count_edges[kMaxBins];
+  uint64_t zvar_edges[kMaxBins];
+  // scratch
+  uint32_t *dn;
+  unsigned long long *ds1, *ds2;
+  int32_t *lin;              // [n_b]
+  uint32_t *q;               // [n_b]
+  uint8_t *near;             // [n_b]
+  int32_t *bbox;             // [6] per pose (min lo / max hi)
+  unsigned long long *ctr;   // [4]: in-grid, nonfinite, near-in-overlap, pad
+  uint32_t *hist;            // [nf][nb*nb]
+};
+
+hipError_t launch_plain_pose(const PlainDev &pd, const PlainDev *pd_dev, const float *xyz,
+                             int64_t n, const double *rt_dev, int64_t pose_index, double *mi_out,
+                             int64_t K, uint32_t *hist_out, const int64_t hist_off[2],
+                             mi_pose_stats *stats_out, bool near_face, hipStream_t s);
+hipError_t launch_plain_clear_dense(const PlainDev &pd, hipStream_t s);
+
+// ------------------------------------------------------------------ utility
+
+hipError_t launch_fill_u32(uint32_t *p, uint32_t value, int64_t n, hipStream_t s);
+hipError_t launch_argmax(const double *mi, int64_t K, int32_t nf, int64_t *out, double *out_val,
+                         hipStream_t s);
+hipError_t launch_bind(PairDev *pairs, int32_t n_pairs, FrameDev *frames, int32_t n_frames,
+                       const float *xyz, double *mi_out, uint32_t *hist_out,
+                       mi_pose_stats *stats_out, hipStream_t s);
+hipError_t launch_count_nonfinite(const float *xyz, int64_t n, unsigned long long *out,
+                                  hipStream_t s);
+
+}  // namespace mi

@@ -1,0 +1,397 @@
+"""Python binding of libmi355.so (include/mi.h): argument marshalling only.
+
+Every step of the hot path runs in the library's HIP kernels; torch provides
+device memory (workspaces, inputs, outputs) and the current HIP stream.
+Importing this module loads the native library and raises if it is missing:
+there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libmi355.so")
+
+MI_OK, MI_E_INVALID, MI_E_WORKSPACE, MI_E_DEVICE, MI_E_UNSUPPORTED = 0, -1, -2, -3, -4
+FEAT_COUNT, FEAT_ZVAR = 1, 2
+EVAL_NEAR_FACE = 1
+MAX_POINTS = 1 << 20
+
+STATS_DTYPE = np.dtype([("lo", "<i4", 3), ("hi", "<i4", 3), ("n_overlap", "<i8"),
+                        ("n_in_grid", "<i8"), ("n_out_of_grid", "<i8"), ("n_nonfinite", "<i8"),
+                        ("n_near_face", "<i8")])
+assert STATS_DTYPE.itemsize == 64
+
+
+class MIError(RuntimeError):
+    def __init__(self, status: int, where: str, msg: str):
+        super().__init__(f"{where}: status {status}: {msg}")
+        self.status = status
+
+
+class _GridDesc(C.Structure):
+    _fields_ = [("origin", C.c_double * 3), ("dims", C.c_int32 * 3), ("voxel", C.c_double),
+                ("features", C.c_uint32), ("nbins_count", C.c_int32),
+                ("count_edges", C.POINTER(C.c_uint32)), ("nbins_zvar", C.c_int32),
+                ("zvar_edges", C.POINTER(C.c_uint64))]
+
+
+class _C2F(C.Structure):
+    _fields_ = [("half_range", C.c_double * 6), ("samples", C.c_int32 * 6), ("levels", C.c_int32),
+                ("shrink", C.c_double), ("feature_slot", C.c_int32)]
+
+
+class _Profile(C.Structure):
+    _fields_ = [("frames_ms", C.c_double), ("eval_ms", C.c_double), ("plain_ms", C.c_double),
+                ("frame_launches", C.c_int64), ("eval_launches", C.c_int64),
+                ("plain_poses", C.c_int64), ("poses", C.c_int64), ("point_poses", C.c_int64)]
+
+
+class _Tuning(C.Structure):
+    _fields_ = [("waves", C.c_int32), ("wave_bytes", C.c_int32), ("hist_copies", C.c_int32),
+                ("reserved", C.c_int32)]
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with `python -m "
+                          "paper_1709_06948_amd.build` (there is no fallback path)")
+    L = C.CDLL(LIB_PATH)
+    vp, i64, u32, sz, st = C.c_void_p, C.c_int64, C.c_uint32, C.c_size_t, C.c_int32
+    dp = C.POINTER(C.c_double)
+    sig = {
+        "mi_status_str": ([st], C.c_char_p),
+        "mi_last_error": ([], C.c_char_p),
+        "mi_tuning_set": ([C.POINTER(_Tuning)], st),
+        "mi_profile_enable": ([st], st),
+        "mi_profile_read": ([C.POINTER(_Profile)], st),
+        "mi_tuning_get": ([C.POINTER(_Tuning)], st),
+        "mi_grid_create": ([C.POINTER(_GridDesc), C.POINTER(vp)], st),
+        "mi_grid_destroy": ([vp], None),
+        "mi_grid_edges": ([vp, C.POINTER(C.c_uint32), C.POINTER(C.c_uint64)], st),
+        "mi_pose_to_matrix": ([dp, dp], st),
+        "mi_features_ref_workspace": ([vp, i64, C.POINTER(sz)], sz),
+        "mi_features_ref": ([vp, vp, i64, vp, sz, vp, C.POINTER(vp)], st),
+        "mi_ref_destroy": ([vp], None),
+        "mi_ref_bins": ([vp, st, C.POINTER(vp)], st),
+        "mi_ref_summary": ([vp, vp, C.POINTER(C.c_int32), C.POINTER(C.c_int64)], st),
+        "mi_eval_poses_workspace": ([vp, i64, dp, i64, u32, sz], sz),
+        "mi_eval_poses": ([vp, vp, i64, dp, i64, u32, vp, vp, vp, vp, vp, sz, vp], st),
+        "mi_eval_poses_plain_workspace": ([vp, i64, i64], sz),
+        "mi_eval_poses_plain": ([vp, vp, i64, dp, i64, u32, vp, vp, vp, vp, vp, sz, vp], st),
+        "mi_plan_create": ([vp, i64, dp, i64, u32, vp, sz, sz, vp, C.POINTER(vp)], st),
+        "mi_plan_execute": ([vp, vp, vp, vp, vp, vp, vp], st),
+        "mi_plan_destroy": ([vp], None),
+        "mi_align_workspace": ([vp, i64, C.POINTER(_C2F)], sz),
+        "mi_align_coarse_to_fine": ([vp, vp, i64, dp, C.POINTER(_C2F), dp, dp, vp, sz, vp], st),
+    }
+    for name, (args, res) in sig.items():
+        fn = getattr(L, name)
+        fn.argtypes = args
+        fn.restype = res
+    return L
+
+
+_lib = _load()
+EXPORTED = ("mi_status_str", "mi_last_error", "mi_tuning_set", "mi_tuning_get",
+            "mi_profile_enable", "mi_profile_read", "mi_grid_create",
+            "mi_grid_destroy", "mi_grid_edges", "mi_pose_to_matrix", "mi_features_ref_workspace",
+            "mi_features_ref", "mi_ref_destroy", "mi_ref_bins", "mi_ref_summary",
+            "mi_eval_poses_workspace", "mi_eval_poses", "mi_eval_poses_plain_workspace",
+            "mi_eval_poses_plain", "mi_plan_create", "mi_plan_execute", "mi_plan_destroy",
+            "mi_align_workspace", "mi_align_coarse_to_fine")
+
+
+def lib():
+    return _lib
+
+
+def _check(status: int, where: str):
+    if status != MI_OK:
+        raise MIError(status, where, (_lib.mi_last_error() or b"").decode())
+
+
+def _dptr(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _stream(stream=None):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+def _dev_points(xyz) -> torch.Tensor:
+    if not isinstance(xyz, torch.Tensor):
+        xyz = torch.from_numpy(np.ascontiguousarray(xyz, np.float32))
+    if xyz.dim() != 2 or xyz.shape[0] != 3:
+        raise ValueError("points must be SoA [3, n]")
+    return xyz.to(device="cuda", dtype=torch.float32).contiguous()
+
+
+def _workspace(nbytes: int) -> torch.Tensor:
+    # torch's caching allocator returns 256-byte-aligned blocks
+    t = torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device="cuda")
+    assert t.data_ptr() % 256 == 0
+    return t
+
+
+def _poses(poses) -> np.ndarray:
+    return np.ascontiguousarray(np.asarray(poses, np.float64).reshape(-1, 6))
+
+
+def status_str(s: int) -> str:
+    return _lib.mi_status_str(s).decode()
+
+
+# ------------------------------------------------------------------ tuning
+
+def tuning_get() -> dict:
+    t = _Tuning()
+    _check(_lib.mi_tuning_get(C.byref(t)), "mi_tuning_get")
+    return dict(waves=t.waves, wave_bytes=t.wave_bytes, hist_copies=t.hist_copies)
+
+
+def tuning_set(waves: int, wave_bytes: int, hist_copies: int = 1):
+    t = _Tuning(int(waves), int(wave_bytes), int(hist_copies), 0)
+    _check(_lib.mi_tuning_set(C.byref(t)), "mi_tuning_set")
+
+
+# --------------------------------------------------------------- profiling
+
+def profile_enable(on: bool = True):
+    _check(_lib.mi_profile_enable(1 if on else 0), "mi_profile_enable")
+
+
+def profile_read() -> dict:
+    p = _Profile()
+    _check(_lib.mi_profile_read(C.byref(p)), "mi_profile_read")
+    return {name: getattr(p, name) for name, _ in _Profile._fields_}
+
+
+# ------------------------------------------------------------------ grid
+
+class Grid:
+    """mi_grid: the voxel grid R_v and the features (Sec. III-A)."""
+
+    def __init__(self, origin, dims, voxel, features=FEAT_COUNT, nb_count=16, nb_zvar=32,
+                 count_edges=None, zvar_edges=None):
+        d = _GridDesc()
+        d.origin[:] = [float(v) for v in origin]
+        d.dims[:] = [int(v) for v in dims]
+        d.voxel = float(voxel)
+        d.features = int(features)
+        d.nbins_count = int(nb_count)
+        d.nbins_zvar = int(nb_zvar)
+        self._ce = None if count_edges is None else np.ascontiguousarray(count_edges, np.uint32)
+        self._ze = None if zvar_edges is None else np.ascontiguousarray(zvar_edges, np.uint64)
+        d.count_edges = None if self._ce is None else self._ce.ctypes.data_as(C.POINTER(C.c_uint32))
+        d.zvar_edges = None if self._ze is None else self._ze.ctypes.data_as(C.POINTER(C.c_uint64))
+        h = C.c_void_p()
+        _check(_lib.mi_grid_create(C.byref(d), C.byref(h)), "mi_grid_create")
+        self._h = h
+        self.origin = tuple(d.origin)
+        self.dims = tuple(d.dims)
+        self.voxel = d.voxel
+        self.features = d.features
+        self.nb_count = d.nbins_count
+        self.nb_zvar = d.nbins_zvar
+
+    def __del__(self):
+        if getattr(self, "_h", None) and _lib is not None:
+            _lib.mi_grid_destroy(self._h)
+            self._h = None
+
+    @property
+    def feature_list(self):
+        out = []
+        if self.features & FEAT_COUNT:
+            out.append((FEAT_COUNT, self.nb_count))
+        if self.features & FEAT_ZVAR:
+            out.append((FEAT_ZVAR, self.nb_zvar))
+        return out
+
+    @property
+    def nf(self):
+        return len(self.feature_list)
+
+    def edges(self):
+        ce = np.zeros(64, np.uint32)
+        ze = np.zeros(64, np.uint64)
+        _check(_lib.mi_grid_edges(self._h, ce.ctypes.data_as(C.POINTER(C.c_uint32)),
+                                  ze.ctypes.data_as(C.POINTER(C.c_uint64))), "mi_grid_edges")
+        return ce[:max(self.nb_count - 1, 0)], ze[:max(self.nb_zvar - 2, 0)]
+
+
+def pose_to_matrix(eta) -> np.ndarray:
+    e = np.ascontiguousarray(eta, np.float64)
+    rt = np.zeros(12, np.float64)
+    _check(_lib.mi_pose_to_matrix(e.ctypes.data_as(C.POINTER(C.c_double)),
+                                  rt.ctypes.data_as(C.POINTER(C.c_double))), "mi_pose_to_matrix")
+    return rt.reshape(3, 4)
+
+
+# ------------------------------------------------------------- reference
+
+class Ref:
+    """mi_ref: scan A's resident feature map (Alg. 1 initialisation)."""
+
+    def __init__(self, grid: Grid, xyz_a, stream=None):
+        self.grid = grid
+        self.xyz_a = _dev_points(xyz_a)
+        n = self.xyz_a.shape[1]
+        pers = C.c_size_t()
+        nbytes = _lib.mi_features_ref_workspace(grid._h, n, C.byref(pers))
+        self.ws = _workspace(nbytes)
+        self.persistent_bytes = pers.value
+        h = C.c_void_p()
+        _check(_lib.mi_features_ref(grid._h, _dptr(self.xyz_a), n, _dptr(self.ws), self.ws.numel(),
+                                    _stream(stream), C.byref(h)), "mi_features_ref")
+        self._h = h
+
+    def __del__(self):
+        if getattr(self, "_h", None) and _lib is not None:
+            _lib.mi_ref_destroy(self._h)
+            self._h = None
+
+    def bins(self, feature_slot: int) -> torch.Tensor:
+        p = C.c_void_p()
+        _check(_lib.mi_ref_bins(self._h, int(feature_slot), C.byref(p)), "mi_ref_bins")
+        off = p.value - self.ws.data_ptr()
+        V = self.grid.dims[0] * self.grid.dims[1] * self.grid.dims[2]
+        return self.ws[off:off + V]
+
+    def summary(self, stream=None):
+        box = np.zeros(6, np.int32)
+        ctr = np.zeros(4, np.int64)
+        _check(_lib.mi_ref_summary(self._h, _stream(stream),
+                                   box.ctypes.data_as(C.POINTER(C.c_int32)),
+                                   ctr.ctypes.data_as(C.POINTER(C.c_int64))), "mi_ref_summary")
+        return box, ctr
+
+
+# ------------------------------------------------------------- evaluate
+
+def _outputs(grid: Grid, K: int, want_hist: bool, want_stats: bool, want_argmax: bool):
+    mi = torch.empty((grid.nf, K), dtype=torch.float64, device="cuda")
+    am = torch.empty(grid.nf, dtype=torch.int64, device="cuda") if want_argmax else None
+    hist = None
+    if want_hist:
+        tot = sum(K * nb * nb for _, nb in grid.feature_list)
+        hist = torch.empty(max(tot, 1), dtype=torch.int32, device="cuda")
+    stats = torch.empty(max(K, 1) * 64, dtype=torch.uint8, device="cuda") if want_stats else None
+    return mi, am, hist, stats
+
+
+def _unpack(grid: Grid, K: int, mi, am, hist, stats):
+    out = {"mi": mi, "argmax": am}
+    if hist is not None:
+        hs, off = [], 0
+        for _, nb in grid.feature_list:
+            hs.append(hist[off:off + K * nb * nb].view(K, nb, nb))
+            off += K * nb * nb
+        out["hist"] = hs
+    if stats is not None:
+        out["stats_raw"] = stats
+    return out
+
+
+def stats_to_numpy(stats_raw: torch.Tensor, K: int) -> np.ndarray:
+    return stats_raw[:K * 64].cpu().numpy().view(STATS_DTYPE)
+
+
+def eval_poses(ref: Ref, xyz_b, poses, flags=0, want_hist=False, want_stats=False,
+               want_argmax=True, stream=None, frame_budget=0):
+    """mi_eval_poses: MI per feature of every pose (Eqs. 1-5)."""
+    xb = _dev_points(xyz_b)
+    P = _poses(poses)
+    K = P.shape[0]
+    pp = P.ctypes.data_as(C.POINTER(C.c_double))
+    nbytes = _lib.mi_eval_poses_workspace(ref._h, xb.shape[1], pp, K, flags, frame_budget)
+    if nbytes == 0:
+        raise MIError(MI_E_INVALID, "mi_eval_poses_workspace", "bad arguments")
+    ws = _workspace(nbytes)
+    mi, am, hist, stats = _outputs(ref.grid, K, want_hist, want_stats, want_argmax)
+    _check(_lib.mi_eval_poses(ref._h, _dptr(xb), xb.shape[1], pp, K, flags, _dptr(mi), _dptr(am),
+                              _dptr(hist), _dptr(stats), _dptr(ws), ws.numel(), _stream(stream)),
+           "mi_eval_poses")
+    out = _unpack(ref.grid, K, mi, am, hist, stats)
+    out["_keep"] = (xb, ws)
+    return out
+
+
+def eval_poses_plain(ref: Ref, xyz_b, poses, flags=0, want_hist=False, want_stats=False,
+                     want_argmax=True, stream=None):
+    """mi_eval_poses_plain: the per-pose stage sequence (same results)."""
+    xb = _dev_points(xyz_b)
+    P = _poses(poses)
+    K = P.shape[0]
+    nbytes = _lib.mi_eval_poses_plain_workspace(ref._h, xb.shape[1], K)
+    ws = _workspace(nbytes)
+    mi, am, hist, stats = _outputs(ref.grid, K, want_hist, want_stats, want_argmax)
+    _check(_lib.mi_eval_poses_plain(ref._h, _dptr(xb), xb.shape[1],
+                                    P.ctypes.data_as(C.POINTER(C.c_double)), K, flags, _dptr(mi),
+                                    _dptr(am), _dptr(hist), _dptr(stats), _dptr(ws), ws.numel(),
+                                    _stream(stream)), "mi_eval_poses_plain")
+    out = _unpack(ref.grid, K, mi, am, hist, stats)
+    out["_keep"] = (xb, ws)
+    return out
+
+
+class Plan:
+    """mi_plan: pose tables uploaded once; execute() only launches kernels
+    (capturable in a HIP graph)."""
+
+    def __init__(self, ref: Ref, n_b: int, poses, flags=0, stream=None, frame_budget=0):
+        self.ref = ref
+        P = _poses(poses)
+        self.K = P.shape[0]
+        self.n_b = int(n_b)
+        pp = P.ctypes.data_as(C.POINTER(C.c_double))
+        nbytes = _lib.mi_eval_poses_workspace(ref._h, self.n_b, pp, self.K, flags, frame_budget)
+        if nbytes == 0:
+            raise MIError(MI_E_INVALID, "mi_eval_poses_workspace", "bad arguments")
+        self.ws = _workspace(nbytes)
+        h = C.c_void_p()
+        _check(_lib.mi_plan_create(ref._h, self.n_b, pp, self.K, flags, _dptr(self.ws),
+                                   self.ws.numel(), frame_budget, _stream(stream), C.byref(h)),
+               "mi_plan_create")
+        self._h = h
+
+    def execute(self, xyz_b: torch.Tensor, mi: torch.Tensor, argmax=None, hist=None, stats=None,
+                stream=None):
+        _check(_lib.mi_plan_execute(self._h, _dptr(xyz_b), _dptr(mi), _dptr(argmax), _dptr(hist),
+                                    _dptr(stats), _stream(stream)), "mi_plan_execute")
+
+    def __del__(self):
+        if getattr(self, "_h", None) and _lib is not None:
+            _lib.mi_plan_destroy(self._h)
+            self._h = None
+
+
+def align_coarse_to_fine(ref: Ref, xyz_b, init, half_range, samples, levels, shrink,
+                         feature_slot=0, stream=None):
+    """mi_align_coarse_to_fine: shrinking grid search for Eq. 1 from T_o."""
+    xb = _dev_points(xyz_b)
+    d = _C2F()
+    d.half_range[:] = [float(v) for v in half_range]
+    d.samples[:] = [int(v) for v in samples]
+    d.levels = int(levels)
+    d.shrink = float(shrink)
+    d.feature_slot = int(feature_slot)
+    nbytes = _lib.mi_align_workspace(ref._h, xb.shape[1], C.byref(d))
+    if nbytes == 0:
+        raise MIError(MI_E_INVALID, "mi_align_workspace", "bad arguments")
+    ws = _workspace(nbytes)
+    i0 = np.ascontiguousarray(init, np.float64)
+    out = np.zeros(6, np.float64)
+    best = np.zeros(1, np.float64)
+    _check(_lib.mi_align_coarse_to_fine(ref._h, _dptr(xb), xb.shape[1],
+                                        i0.ctypes.data_as(C.POINTER(C.c_double)), C.byref(d),
+                                        out.ctypes.data_as(C.POINTER(C.c_double)),
+                                        best.ctypes.data_as(C.POINTER(C.c_double)), _dptr(ws),
+                                        ws.numel(), _stream(stream)), "mi_align_coarse_to_fine")
+    return out, float(best[0])

@@ -327,6 +327,16 @@ def urban_pair(seed=None, max_offset=5.0, max_yaw_deg=15.0) -> Pair:
     return Pair(as_soa32(A), as_soa32(B), eta, (-80.0, -80.0, -1.0), (320, 320, 20), 0.5)
 
 
+def level_poses(center, half, samples) -> np.ndarray:
+    """A pose grid around center (per axis samples[a] values spanning
+    +-half[a]), row-major with the last axis fastest -- used to draw sample
+    poses of a search level as inputs."""
+    axes = [np.array([center[a]]) if samples[a] == 1 else
+            np.linspace(center[a] - half[a], center[a] + half[a], int(samples[a])) for a in range(6)]
+    mesh = np.meshgrid(*axes, indexing="ij")
+    return np.stack([m.reshape(-1) for m in mesh], axis=1)
+
+
 def urban_c2f_params():
     """3-level coarse-to-fine search of 5^6 poses per level: level-0 half-ranges
     (5, 5, 0.5 m, 2, 2, 15 deg), shrink 4x per level."""
