@@ -104,15 +104,16 @@ const char *mi_status_str(mi_status s);
 const char *mi_last_error(void);
 
 /* Launch shape of the batched evaluator (process-wide; read when a plan is
- * created).  waves: 1..8 waves per workgroup, each owning one brick of the
- * grid at a time; wave_bytes: LDS bytes per wave for its brick (multiple of
- * 16); hist_copies: 1..8 privatized joint-histogram copies per workgroup.
- * Every setting gives bit-identical histograms. */
+ * created).  waves: 1..16 waves per workgroup (one workgroup per pose);
+ * hash_bytes: LDS bytes for the voxel sums of one brick (the slot count is the
+ * largest power of two that fits); hist_copies: 1..8 privatized joint
+ * histograms; stripe_rows: 1..62 voxel rows per stripe of bricks.  Every
+ * setting gives bit-identical histograms. */
 typedef struct mi_tuning {
   int32_t waves;
-  int32_t wave_bytes;
+  int32_t hash_bytes;
   int32_t hist_copies;
-  int32_t reserved;
+  int32_t stripe_rows;
 } mi_tuning;
 mi_status mi_tuning_set(const mi_tuning *t);
 mi_status mi_tuning_get(mi_tuning *t);

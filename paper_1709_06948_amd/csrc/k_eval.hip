@@ -1,21 +1,29 @@
 // k_eval.hip -- MI of one candidate pose per workgroup (Eqs. 1-5, Alg. 1 loop
 // body), on scan B's points already rotated once per distinct rotation.
 //
-// A's grid is tiled into bricks of bx * by columns at full height.  Each wave
-// owns one brick at a time, so every voxel's sums (n, S1, S2) are complete in
-// the wave's slice of LDS without any merge across waves or workgroups:
-//   1. candidate points: the columns of the rotated cloud whose points can land
-//      in the brick under this pose's translation (one padded column of slack
-//      per side); their row ranges come from the column offsets;
-//   2. per candidate: u = fl(v + c), voxel floor(u); points inside the brick
-//      add to the voxel's LDS sums (first touch appends the voxel to the
-//      wave's occupied list) and to the pose's extent of B;
-//   3. per occupied voxel inside A's index box (which, with B's extent, is the
-//      overlap box): its B bin and A's bin add one to the joint histogram.
-// After all bricks: overlap box O = A box x B extent; the cells of voxels that
-// B leaves empty come from A's per-bin summed-volume tables (H[a][0] = A's
-// voxels of bin a in O minus those B occupies; H[0][0] closes the mass |O|);
-// then H(X), H(Y), H(X,Y) and MI.
+// Ownership: A's grid is cut into bricks (pieces of stripes of stripe_h voxel
+// rows, full height).  All waves of the workgroup work on one brick at a time
+// and every B point that lands in the brick is aggregated there, so each
+// voxel's sums (n, S1, S2) are complete in LDS without any merge across
+// workgroups.  The sums live in an LDS hash keyed by the voxel.  Bricks are
+// tried optimistically: once a brick holds more distinct voxels than half the
+// slots, the waves stop inserting (the hash keeps room for one more step of
+// every wave, so probing always ends), the brick is cleared without touching
+// the histogram and is retried in halves; a single x piece is retried one voxel
+// row at a time, which always fits.
+//
+// Per pose:
+//  plan   for a group of stripes, one parallel round of loads reads the column
+//         offsets of every candidate row at the stripe's piece cuts, so brick
+//         boundaries and candidate ranges are known without further round trips;
+//  bricks the rest of the stripe first, halved on overflow;
+//  points 64 consecutive candidates of one column row per wave step: u = fl(v+c),
+//         voxel floor(u); in-brick points insert their voxel into the hash and add
+//         n, S1, S2 (LDS atomics), and extend B's extent;
+//  sweep  every occupied voxel inside A's index box (with B's extent this is the
+//         overlap box) adds one to the joint histogram at (A's bin, B's bin);
+//  finish overlap box O; the cells of voxels that B leaves empty come from A's
+//         per-bin summed-volume tables; entropies and MI.
 #include "mi_device.h"
 #include "mi_internal.h"
 
@@ -23,36 +31,55 @@
 
 namespace mi {
 
+static constexpr uint32_t kEmpty = 0xffffffffu;
+
 struct EvalCfgDev {
-  int32_t hist_copies;
-  int32_t hist_words;
-  int32_t wave_bytes;
-  int32_t misc_bytes;
+  int32_t hist_copies, hist_words;
+  int32_t cap_log2;
+  int32_t load_max;           // distinct voxels per brick before it counts as overflowed
+  int32_t plan_stripes;
+  int32_t plan_entries;       // per stripe: rows * (pieces + 1)
+  int32_t off_cnta, off_edges, off_wave, off_plan, off_hash, pad;
 };
 
-static constexpr int kRowTableBytes = 512;  // 64 row starts + 64 row prefixes
+struct Layout {
+  int off_cnta, off_edges, off_wave, off_plan, off_hash, total;
+};
 
-// LDS layout: hist copies (rounded to 16 B) | cntA[2][64] u32 | count edges 64 u32 |
-// z-variance edges 64 u64 | wave boxes [W][8] i32 | wave counts [W][2] u64 | next
-// brick counter; then one slice of wave_bytes per wave.
-__host__ __device__ constexpr int hist_region_bytes(int hist_copies, int hist_words) {
-  return (hist_copies * hist_words * 4 + 15) & ~15;
+__host__ __device__ inline int al16(int x) { return (x + 15) & ~15; }
+
+__host__ __device__ inline Layout eval_layout(int waves, int hist_copies, int hist_words,
+                                              int plan_stripes, int plan_entries, int cap,
+                                              bool zvar) {
+  Layout L;
+  int o = al16(hist_copies * hist_words * 4);
+  L.off_cnta = o;   o += 512;                   // cntA[2][64]
+  L.off_edges = o;  o += 256 + 512;             // 64 u32 + 64 u64
+  L.off_wave = o;   o += al16(waves * 48 + 16); // box [W][8] i32, counts [W][2] u64, occ counters
+  L.off_plan = o;   o += al16(plan_stripes * plan_entries * 8);
+  o = (o + 255) & ~255;
+  L.off_hash = o;   o += cap * (4 + (zvar ? 16 : 4)) + 2 * cap;  // keys, sums, occupied list (u16)
+  L.total = al16(o);
+  return L;
 }
 
-__host__ __device__ constexpr int misc_bytes_for(int waves, int hist_copies, int hist_words) {
-  return ((hist_region_bytes(hist_copies, hist_words) + 512 + 256 + 512 + waves * 32 +
-           waves * 16 + 16) + 255) & ~255;
+__device__ __forceinline__ int cut_x(int q, int nx, int Q) { return (int)(((int64_t)q * nx) / Q); }
+
+// Column rows [r0, r0 + nrows) of the rotated cloud that can reach voxel rows [y0, y1).
+__device__ __forceinline__ void rows_for(int y0, int y1, double cy, int gy, int ncy, int *r0,
+                                         int *nrows) {
+  int a = (int)floor((double)y0 - cy - kColEps) - gy;
+  int b = (int)floor((double)y1 - cy + kColEps) - gy;
+  a = max(a, 0);
+  b = min(b, ncy - 1);
+  *r0 = a;
+  *nrows = b >= a ? b - a + 1 : 0;
 }
 
-__device__ __forceinline__ void wave_fence() {
-  __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-}
-
-template <bool NEAR>
-__global__ void __launch_bounds__(512) k_eval(const PairDev *__restrict__ pairs,
-                                              const PoseDev *__restrict__ items, int64_t n_items,
-                                              int64_t per_xcd, EvalCfgDev cfg) {
+template <bool NEAR, bool ZVAR>
+__global__ void __launch_bounds__(1024) k_eval(const PairDev *__restrict__ pairs,
+                                               const PoseDev *__restrict__ items, int64_t n_items,
+                                               int64_t per_xcd, EvalCfgDev cfg) {
   extern __shared__ __align__(16) unsigned char smem[];
   // XCD-aware mapping: consecutive workgroup ids go round-robin over the XCDs,
   // so each XCD walks a contiguous run of the frame-sorted items and keeps the
@@ -62,174 +89,281 @@ __global__ void __launch_bounds__(512) k_eval(const PairDev *__restrict__ pairs,
   const PoseDev pose = items[item];
   const PairDev &P = pairs[pose.pair];
 
-  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6, W = blockDim.x >> 6;
+  const int T = blockDim.x, tid = threadIdx.x, lane = tid & 63, W = T >> 6;
+  const int wid = __builtin_amdgcn_readfirstlane(tid >> 6);
   uint32_t *hist = (uint32_t *)smem;
-  uint32_t *cntA = (uint32_t *)(smem + hist_region_bytes(cfg.hist_copies, cfg.hist_words));
-  uint32_t *cedge = cntA + 128;
+  uint32_t *cntA = (uint32_t *)(smem + cfg.off_cnta);
+  uint32_t *cedge = (uint32_t *)(smem + cfg.off_edges);
   uint64_t *zedge = (uint64_t *)(cedge + 64);
-  int *wbox = (int *)(zedge + 64);
+  int *wbox = (int *)(smem + cfg.off_wave);
   unsigned long long *wcnt = (unsigned long long *)(wbox + 8 * W);
-  uint32_t *next = (uint32_t *)(wcnt + 2 * W);
-  unsigned char *wreg = smem + cfg.misc_bytes + (size_t)wid * cfg.wave_bytes;
-  uint32_t *rstart = (uint32_t *)wreg;
-  uint32_t *rpre = rstart + 64;
-  unsigned char *agg = wreg + kRowTableBytes;
-  uint32_t *agg32 = (uint32_t *)agg;
-  unsigned long long *agg64 = (unsigned long long *)agg;
+  uint32_t *occn = (uint32_t *)(wcnt + 2 * W);
+  uint2 *plan = (uint2 *)(smem + cfg.off_plan);
+  const int cap = 1 << cfg.cap_log2;
+  uint32_t *hkey = (uint32_t *)(smem + cfg.off_hash);
+  unsigned long long *hv1 = (unsigned long long *)(hkey + cap);   // ZVAR: n<<44 | S1
+  unsigned long long *hv2 = hv1 + cap;                            // ZVAR: S2
+  uint32_t *hcnt = hkey + cap;                                    // count only
+  uint16_t *occ = (uint16_t *)(smem + cfg.off_hash + cap * (4 + (ZVAR ? 16 : 4)));
 
-  const int nx = P.nx, ny = P.ny, nz = P.nz, nf = P.nf, bx = P.bx, by = P.by, bpv = P.bpv;
-  const int bvox = nz * by * bx;
-  uint16_t *occ = (uint16_t *)(agg + (size_t)bvox * bpv);
+  const int nx = P.nx, ny = P.ny, nz = P.nz, nf = P.nf;
   const int nb0 = P.nb[0], nb1 = nf > 1 ? P.nb[1] : 0;
   const int hoff1 = nb0 * nb0;
 
-  for (int i = tid; i < cfg.hist_copies * cfg.hist_words; i += blockDim.x) hist[i] = 0u;
-  for (int i = tid; i < 64; i += blockDim.x) {
+  for (int i = tid; i < cfg.hist_copies * cfg.hist_words; i += T) hist[i] = 0u;
+  for (int i = tid; i < 64; i += T) {
     cedge[i] = P.count_edges[i];
     zedge[i] = P.zvar_edges[i];
   }
-  for (int i = lane; i < bvox * bpv / 4; i += 64) agg32[i] = 0u;
-  if (tid == 0) *next = 0u;
+  for (int i = tid; i < cap; i += T) {
+    hkey[i] = kEmpty;
+    if (ZVAR) { hv1[i] = 0ull; hv2[i] = 0ull; } else { hcnt[i] = 0u; }
+  }
+  if (tid < 2) occn[tid] = 0u;
   __syncthreads();
 
   const double cx = pose.c[0], cy = pose.c[1], cz = pose.c[2];
   const double *fvx = P.fv + (int64_t)pose.frame * 3 * P.fstride;
   const double *fvy = fvx + P.fstride;
   const double *fvz = fvy + P.fstride;
-  const int64_t ncols = (int64_t)P.ncx * P.ncy;
-  const uint32_t *off = P.foff + (int64_t)pose.frame * (ncols + 1);
+  const int ncx = P.ncx, ncy = P.ncy, gx = P.gx, gy = P.gy;
+  const uint32_t *off = P.foff + (int64_t)pose.frame * ((int64_t)ncx * ncy + 1);
   const int alo0 = P.abox[0], alo1 = P.abox[1], alo2 = P.abox[2];
   const int ahi0 = P.abox[3], ahi1 = P.abox[4], ahi2 = P.abox[5];
   uint32_t *myhist = hist + (wid % cfg.hist_copies) * cfg.hist_words;
   const uint32_t kind0 = P.kind[0], kind1 = P.kind[1];
   const uint8_t *binA0 = P.binA[0], *binA1 = P.binA[1];
+  const int BY = P.stripe_h, NS = P.n_stripes, Q = P.pieces, RM = BY + 2;
+  const int kxb = P.kx_bits, kyb = P.ky_bits;
+  const uint32_t kxm = (1u << kxb) - 1u, kym = (1u << kyb) - 1u;
+  const int G = cfg.plan_stripes;
+  const int PE = RM * (Q + 1);  // plan entries per stripe
 
   int lo0 = nx, lo1 = ny, lo2 = nz, hi0 = -1, hi1 = -1, hi2 = -1;
   unsigned long long nin = 0, nnear = 0;
-  const int nbricks = P.nbx * P.nby;
+  int parity = 0;
 
-  for (;;) {
-    uint32_t bi = 0;
-    if (lane == 0) bi = atomicAdd(next, 1u);
-    bi = __builtin_amdgcn_readfirstlane(bi);
-    if ((int)bi >= nbricks) break;
-    const int bxi = (int)bi % P.nbx, byi = (int)bi / P.nbx;
-    const int X0 = bxi * bx, X1 = min(X0 + bx, nx), Y0 = byi * by, Y1 = min(Y0 + by, ny);
-    int c0 = (int)floor((double)X0 - cx - kColEps) - P.gx;
-    int c1 = (int)floor((double)X1 - cx + kColEps) - P.gx;
-    int r0 = (int)floor((double)Y0 - cy - kColEps) - P.gy;
-    int r1 = (int)floor((double)Y1 - cy + kColEps) - P.gy;
-    c0 = max(c0, 0); c1 = min(c1, P.ncx - 1);
-    r0 = max(r0, 0); r1 = min(r1, P.ncy - 1);
-    if (c1 < c0 || r1 < r0) continue;
-    const int nrows = r1 - r0 + 1;
-    uint32_t st = 0, len = 0;
-    if (lane < nrows) {
-      const uint32_t *orow = off + (int64_t)(r0 + lane) * P.ncx;
-      st = orow[c0];
-      len = orow[c1 + 1] - st;
+  for (int s0 = 0; s0 < NS; s0 += G) {
+    const int gn = min(G, NS - s0);
+    // ---- plan: offsets of every candidate row at every piece cut
+    for (int e = tid; e < gn * PE; e += T) {
+      const int q = e % (Q + 1);
+      const int t1 = e / (Q + 1);
+      const int r = t1 % RM, sl = t1 / RM;
+      const int Y0 = (s0 + sl) * BY, Y1 = min(Y0 + BY, ny);
+      int r0, nrows;
+      rows_for(Y0, Y1, cy, gy, ncy, &r0, &nrows);
+      uint2 v = make_uint2(0u, 0u);
+      if (r < nrows) {
+        int K = (int)floor((double)cut_x(q, nx, Q) - cx - kColEps) - gx;
+        K = min(max(K, 0), ncx - 1);
+        const uint32_t *orow = off + (int64_t)(r0 + r) * ncx;
+        v.x = ldg(orow + K);
+        v.y = ldg(orow + min(K + 2, ncx));
+      }
+      plan[sl * PE + r * (Q + 1) + q] = v;
     }
-    uint32_t inc = len;
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-      const uint32_t t = __shfl_up(inc, o, 64);
-      if (lane >= o) inc += t;
-    }
-    const uint32_t total = __shfl(inc, nrows - 1, 64);
-    if (total == 0) continue;
-    if (lane < nrows) {
-      rstart[lane] = st;
-      rpre[lane] = inc - len;
-    }
-    wave_fence();
+    __syncthreads();
 
-    int nocc = 0;
-    for (uint32_t j0 = 0; j0 < total; j0 += 64) {
-      const uint32_t j = j0 + lane;
-      bool first = false;
-      int loc = 0;
-      if (j < total) {
-        int lo = 0, hi = nrows - 1;
-        while (lo < hi) {
-          const int mid = (lo + hi + 1) >> 1;
-          if (rpre[mid] <= j) lo = mid; else hi = mid - 1;
-        }
-        const uint32_t idx = rstart[lo] + (j - rpre[lo]);
-        const double ux = fvx[idx] + cx, uy = fvy[idx] + cy, uz = fvz[idx] + cz;
-        const double fx = floor(ux), fy = floor(uy), fz = floor(uz);
-        if (fx >= (double)X0 && fx < (double)X1 && fy >= (double)Y0 && fy < (double)Y1 &&
-            fz >= 0.0 && fz < (double)nz) {
-          const int ix = (int)fx, iy = (int)fy, iz = (int)fz;
-          loc = (iz * by + (iy - Y0)) * bx + (ix - X0);
-          if (bpv == 4) {
-            first = atomicAdd(&agg32[loc], 1u) == 0u;
-          } else {
-            const unsigned long long q = (unsigned long long)floor((uz - fz) * kQScale);
-            const unsigned long long old = atomicAdd(&agg64[2 * loc], (1ull << 44) | q);
-            atomicAdd(&agg64[2 * loc + 1], q * q);
-            first = (old >> 44) == 0ull;
-          }
-          ++nin;
-          lo0 = min(lo0, ix); lo1 = min(lo1, iy); lo2 = min(lo2, iz);
-          hi0 = max(hi0, ix); hi1 = max(hi1, iy); hi2 = max(hi2, iz);
-          if (NEAR && ix >= alo0 && ix <= ahi0 && iy >= alo1 && iy <= ahi1 && iz >= alo2 &&
-              iz <= ahi2) {
-            double d = 1.0;
-            const double fr[3] = {ux - fx, uy - fy, uz - fz};
-#pragma unroll
-            for (int a = 0; a < 3; ++a) {
-              const double up = 1.0 - fr[a];
-              const double m = fr[a] < up ? fr[a] : up;
-              if (m < d) d = m;
+    // ---- bricks of each stripe (every thread takes the same decisions)
+    for (int sl = 0; sl < gn; ++sl) {
+      const int SY0 = (s0 + sl) * BY, SY1 = min(SY0 + BY, ny);
+      int sr0, snrows;
+      rows_for(SY0, SY1, cy, gy, ncy, &sr0, &snrows);
+      if (snrows <= 0) continue;
+      const uint2 *ps = plan + sl * PE;
+      int qa = 0;
+      while (qa < Q) {
+        int qe = Q;
+        for (;;) {
+          const bool whole = qe > qa;  // false: piece qa voxel row by voxel row
+          const int qend = whole ? qe : qa + 1;
+          const int X0 = cut_x(qa, nx, Q), X1 = cut_x(qend, nx, Q);
+          const int nsub = whole ? 1 : (SY1 - SY0);
+          bool all_ok = true;
+          for (int sub = 0; sub < nsub; ++sub) {
+            const int Y0 = whole ? SY0 : SY0 + sub, Y1 = whole ? SY1 : Y0 + 1;
+            int ra = 0, nr = snrows;
+            if (!whole) {
+              int rr0, rn;
+              rows_for(Y0, Y1, cy, gy, ncy, &rr0, &rn);
+              ra = rr0 - sr0;
+              nr = rn;
             }
-            if (d * P.voxel < kNearFace) ++nnear;
+            // this brick's candidate rows, one per lane: start, length, chunk prefix
+            uint32_t my_st = 0, my_len = 0;
+            if (lane < nr) {
+              my_st = ps[(ra + lane) * (Q + 1) + qa].x;
+              my_len = ps[(ra + lane) * (Q + 1) + qend].y - my_st;
+            }
+            const uint32_t my_c = (my_len + 63u) >> 6;
+            uint32_t inc = my_c;
+#pragma unroll
+            for (int o = 1; o < 64; o <<= 1) {
+              const uint32_t t = __shfl_up(inc, o, 64);
+              if (lane >= o) inc += t;
+            }
+            const uint32_t my_cpre = inc - my_c;
+            const int nch = nr > 0 ? (int)__shfl(inc, nr - 1, 64) : 0;
+            if (nch == 0) continue;
+            int64_t ncand = 0;
+            for (int r = 0; r < nr; ++r) ncand += __shfl(my_len, r, 64);
+            const int64_t bvox = (int64_t)(X1 - X0) * (Y1 - Y0) * nz;
+            const bool guaranteed = (ncand < bvox ? ncand : bvox) <= cfg.load_max;
+            const int p = parity;
+            int blo0 = nx, blo1 = ny, blo2 = nz, bhi0 = -1, bhi1 = -1, bhi2 = -1;
+            unsigned long long bnin = 0, bnear = 0;
+            // chunk k -> (candidate index of this lane, valid)
+            auto chunk_idx = [&](int k, bool *valid) -> uint32_t {
+              const unsigned long long mk = __ballot(lane < nr && my_cpre <= (uint32_t)k);
+              const int row = __popcll(mk) - 1;
+              const uint32_t st = __builtin_amdgcn_readlane(my_st, row);
+              const uint32_t len = __builtin_amdgcn_readlane(my_len, row);
+              const uint32_t cpre = __builtin_amdgcn_readlane(my_cpre, row);
+              const uint32_t idx = st + ((uint32_t)k - cpre) * 64u + (uint32_t)lane;
+              *valid = idx < st + len;
+              return idx;
+            };
+            int k = wid;
+            bool cval = false;
+            double cvx = 0.0, cvy = 0.0, cvz = 0.0;
+            if (k < nch) {
+              const uint32_t idx = chunk_idx(k, &cval);
+              if (cval) { cvx = ldg(fvx + idx); cvy = ldg(fvy + idx); cvz = ldg(fvz + idx); }
+            }
+            for (; k < nch; k += W) {
+              // prefetch the wave's next chunk while this one is processed
+              bool nval = false;
+              double nvx = 0.0, nvy = 0.0, nvz = 0.0;
+              if (k + W < nch) {
+                const uint32_t idx = chunk_idx(k + W, &nval);
+                if (nval) { nvx = ldg(fvx + idx); nvy = ldg(fvy + idx); nvz = ldg(fvz + idx); }
+              }
+              if (!guaranteed &&
+                  __atomic_load_n(&occn[p], __ATOMIC_RELAXED) > (uint32_t)cfg.load_max)
+                break;
+              bool ins = false;
+              uint32_t slot = 0;
+              if (cval) {
+                const double ux = cvx + cx, uy = cvy + cy, uz = cvz + cz;
+                const double fx = floor(ux), fy = floor(uy), fz = floor(uz);
+                if (fx >= (double)X0 && fx < (double)X1 && fy >= (double)Y0 && fy < (double)Y1 &&
+                    fz >= 0.0 && fz < (double)nz) {
+                  const int ix = (int)fx, iy = (int)fy, iz = (int)fz;
+                  const uint32_t key = ((uint32_t)iz << (kxb + kyb)) |
+                                       ((uint32_t)(iy - SY0) << kxb) | (uint32_t)ix;
+                  uint32_t h = (key * 2654435761u) >> (32 - cfg.cap_log2);
+                  for (;;) {
+                    const uint32_t k0 = __atomic_load_n(&hkey[h], __ATOMIC_RELAXED);
+                    if (k0 == key) break;
+                    if (k0 == kEmpty) {
+                      const uint32_t old = atomicCAS(&hkey[h], kEmpty, key);
+                      if (old == kEmpty) { ins = true; break; }
+                      if (old == key) break;
+                    }
+                    h = (h + 1u) & (uint32_t)(cap - 1);
+                  }
+                  slot = h;
+                  if (ZVAR) {
+                    const unsigned long long q = (unsigned long long)floor((uz - fz) * kQScale);
+                    atomicAdd(&hv1[h], (1ull << 44) | q);
+                    atomicAdd(&hv2[h], q * q);
+                  } else {
+                    atomicAdd(&hcnt[h], 1u);
+                  }
+                  ++bnin;
+                  blo0 = min(blo0, ix); blo1 = min(blo1, iy); blo2 = min(blo2, iz);
+                  bhi0 = max(bhi0, ix); bhi1 = max(bhi1, iy); bhi2 = max(bhi2, iz);
+                  if (NEAR && ix >= alo0 && ix <= ahi0 && iy >= alo1 && iy <= ahi1 &&
+                      iz >= alo2 && iz <= ahi2) {
+                    double d = 1.0;
+                    const double fr[3] = {ux - fx, uy - fy, uz - fz};
+#pragma unroll
+                    for (int a = 0; a < 3; ++a) {
+                      const double up = 1.0 - fr[a];
+                      const double m = fr[a] < up ? fr[a] : up;
+                      if (m < d) d = m;
+                    }
+                    if (d * P.voxel < kNearFace) ++bnear;
+                  }
+                }
+              }
+              const unsigned long long m = __ballot(ins);
+              if (m) {
+                uint32_t base_slot = 0;
+                if (lane == 0) base_slot = atomicAdd(&occn[p], (uint32_t)__popcll(m));
+                base_slot = __shfl(base_slot, 0, 64);
+                if (ins) {
+                  const uint32_t pos = base_slot + __builtin_amdgcn_mbcnt_hi(
+                                                       (uint32_t)(m >> 32),
+                                                       __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+                  occ[pos] = (uint16_t)slot;
+                }
+              }
+              cval = nval;
+              cvx = nvx;
+              cvy = nvy;
+              cvz = nvz;
+            }
+            __syncthreads();
+            const int nocc = (int)occn[p];
+            const bool overflow = nocc > cfg.load_max;
+            if (tid == 0) occn[p ^ 1] = 0u;
+            for (int i = tid; i < nocc; i += T) {
+              const uint32_t h = occ[i];
+              const uint32_t key = hkey[h];
+              const int ix = (int)(key & kxm);
+              const int iy = SY0 + (int)((key >> kxb) & kym);
+              const int iz = (int)(key >> (kxb + kyb));
+              uint32_t n;
+              unsigned long long s1 = 0, s2 = 0;
+              if (ZVAR) {
+                const unsigned long long a = hv1[h];
+                n = (uint32_t)(a >> 44);
+                s1 = a & ((1ull << 44) - 1);
+                s2 = hv2[h];
+                hv1[h] = 0ull;
+                hv2[h] = 0ull;
+              } else {
+                n = hcnt[h];
+                hcnt[h] = 0u;
+              }
+              hkey[h] = kEmpty;
+              if (!overflow && ix >= alo0 && ix <= ahi0 && iy >= alo1 && iy <= ahi1 &&
+                  iz >= alo2 && iz <= ahi2) {
+                const int64_t lin = ((int64_t)iz * ny + iy) * nx + ix;
+                {
+                  const int a = ldg(binA0 + lin);
+                  const int b = kind0 == MI_FEAT_COUNT ? bin_count_dev(n, nb0, cedge)
+                                                       : bin_zvar_dev(n, s1, s2, nb0, zedge);
+                  atomicAdd(&myhist[a * nb0 + b], 1u);
+                }
+                if (nf > 1) {
+                  const int a = ldg(binA1 + lin);
+                  const int b = kind1 == MI_FEAT_COUNT ? bin_count_dev(n, nb1, cedge)
+                                                       : bin_zvar_dev(n, s1, s2, nb1, zedge);
+                  atomicAdd(&myhist[hoff1 + a * nb1 + b], 1u);
+                }
+              }
+            }
+            __syncthreads();
+            parity ^= 1;
+            if (overflow) {
+              all_ok = false;
+              break;
+            }
+            nin += bnin;
+            nnear += bnear;
+            lo0 = min(lo0, blo0); lo1 = min(lo1, blo1); lo2 = min(lo2, blo2);
+            hi0 = max(hi0, bhi0); hi1 = max(hi1, bhi1); hi2 = max(hi2, bhi2);
           }
-        }
-      }
-      const unsigned long long m = __ballot(first);
-      if (first) {
-        const int slot = nocc + (int)__builtin_amdgcn_mbcnt_hi(
-                                    (uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
-        occ[slot] = (uint16_t)loc;
-      }
-      nocc += __popcll(m);
-    }
-    wave_fence();
-
-    for (int i = lane; i < nocc; i += 64) {
-      const int loc = occ[i];
-      const int lx = loc % bx, t2 = loc / bx, ly = t2 % by, lz = t2 / by;
-      const int ix = X0 + lx, iy = Y0 + ly, iz = lz;
-      uint32_t n;
-      unsigned long long s1 = 0, s2 = 0;
-      if (bpv == 4) {
-        n = agg32[loc];
-        agg32[loc] = 0u;
-      } else {
-        const unsigned long long a = agg64[2 * loc];
-        n = (uint32_t)(a >> 44);
-        s1 = a & ((1ull << 44) - 1);
-        s2 = agg64[2 * loc + 1];
-        agg64[2 * loc] = 0ull;
-        agg64[2 * loc + 1] = 0ull;
-      }
-      if (ix >= alo0 && ix <= ahi0 && iy >= alo1 && iy <= ahi1 && iz >= alo2 && iz <= ahi2) {
-        const int64_t lin = ((int64_t)iz * ny + iy) * nx + ix;
-        {
-          const int a = binA0[lin];
-          const int b = kind0 == MI_FEAT_COUNT ? bin_count_dev(n, nb0, cedge)
-                                               : bin_zvar_dev(n, s1, s2, nb0, zedge);
-          atomicAdd(&myhist[a * nb0 + b], 1u);
-        }
-        if (nf > 1) {
-          const int a = binA1[lin];
-          const int b = kind1 == MI_FEAT_COUNT ? bin_count_dev(n, nb1, cedge)
-                                               : bin_zvar_dev(n, s1, s2, nb1, zedge);
-          atomicAdd(&myhist[hoff1 + a * nb1 + b], 1u);
+          if (all_ok) { qa = qend; break; }
+          // overflow: halve the run of pieces; a single piece goes row by row
+          qe = qe - qa > 1 ? qa + (qe - qa) / 2 : qa;
         }
       }
     }
-    wave_fence();
+    __syncthreads();
   }
 
   // ---------------------------------------------------------- pose reduction
@@ -245,7 +379,7 @@ __global__ void __launch_bounds__(512) k_eval(const PairDev *__restrict__ pairs,
   }
   __syncthreads();
   if (cfg.hist_copies > 1) {
-    for (int i = tid; i < cfg.hist_words; i += blockDim.x) {
+    for (int i = tid; i < cfg.hist_words; i += T) {
       uint32_t s = 0;
       for (int d = 1; d < cfg.hist_copies; ++d) s += hist[d * cfg.hist_words + i];
       hist[i] += s;
@@ -278,7 +412,7 @@ __global__ void __launch_bounds__(512) k_eval(const PairDev *__restrict__ pairs,
 
   if (nonempty) {
     const int64_t plane = (int64_t)(nx + 1) * (ny + 1) * (nz + 1);
-    for (int t = tid; t < nf * 64; t += blockDim.x) {
+    for (int t = tid; t < nf * 64; t += T) {
       const int f = t >> 6, a = t & 63;
       if (a >= 1 && a < P.nb[f])
         cntA[t] = sat_box(P.sat[f] + (int64_t)(a - 1) * plane, nx, ny, olo[0], olo[1], olo[2],
@@ -287,7 +421,7 @@ __global__ void __launch_bounds__(512) k_eval(const PairDev *__restrict__ pairs,
   }
   __syncthreads();
   if (nonempty) {
-    for (int t = tid; t < nf * 64; t += blockDim.x) {
+    for (int t = tid; t < nf * 64; t += T) {
       const int f = t >> 6, a = t & 63, nb = P.nb[f];
       if (a >= 1 && a < nb) {
         uint32_t *row = hist + (f ? hoff1 : 0) + a * nb;
@@ -345,39 +479,51 @@ __global__ void __launch_bounds__(512) k_eval(const PairDev *__restrict__ pairs,
   }
 }
 
-size_t eval_lds_bytes(const EvalLaunch &cfg) {
-  return (size_t)misc_bytes_for(cfg.waves, cfg.hist_copies, cfg.hist_words) +
-         (size_t)cfg.waves * cfg.wave_bytes;
+int32_t eval_hash_slot_bytes(bool zvar) { return 4 + (zvar ? 16 : 4) + 2; }
+
+size_t eval_lds_bytes(const EvalLaunch &c) {
+  return (size_t)eval_layout(c.waves, c.hist_copies, c.hist_words, c.plan_stripes,
+                             c.plan_entries, 1 << c.cap_log2, c.zvar)
+      .total;
 }
 
-int32_t eval_row_table_bytes() { return kRowTableBytes; }
-
-hipError_t launch_eval(const PairDev *pairs_dev, const PoseDev *items_dev, int64_t n_items,
-                       const EvalLaunch &cfg, hipStream_t s) {
-  if (n_items <= 0) return hipSuccess;
-  EvalCfgDev c;
-  c.hist_copies = cfg.hist_copies;
-  c.hist_words = cfg.hist_words;
-  c.wave_bytes = cfg.wave_bytes;
-  c.misc_bytes = misc_bytes_for(cfg.waves, cfg.hist_copies, cfg.hist_words);
-  const size_t lds = eval_lds_bytes(cfg);
+template <bool NEAR, bool ZVAR>
+static hipError_t launch_one(const PairDev *pairs_dev, const PoseDev *items_dev, int64_t n_items,
+                             const EvalLaunch &c, hipStream_t s) {
+  const Layout L = eval_layout(c.waves, c.hist_copies, c.hist_words, c.plan_stripes,
+                               c.plan_entries, 1 << c.cap_log2, c.zvar);
+  EvalCfgDev d;
+  d.hist_copies = c.hist_copies;
+  d.hist_words = c.hist_words;
+  d.cap_log2 = c.cap_log2;
+  d.load_max = (1 << c.cap_log2) / 2;
+  d.plan_stripes = c.plan_stripes;
+  d.plan_entries = c.plan_entries;
+  d.off_cnta = L.off_cnta;
+  d.off_edges = L.off_edges;
+  d.off_wave = L.off_wave;
+  d.off_plan = L.off_plan;
+  d.off_hash = L.off_hash;
+  d.pad = 0;
   const int64_t per_xcd = (n_items + kXcds - 1) / kXcds;
   const int64_t grid = per_xcd * kXcds;
   if (grid > 0x7fffffff) return hipErrorInvalidValue;
-  if (cfg.near_face) {
-    hipError_t e = hipFuncSetAttribute((const void *)k_eval<true>,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    if (e != hipSuccess) return e;
-    k_eval<true><<<(unsigned)grid, cfg.waves * 64, lds, s>>>(pairs_dev, items_dev, n_items,
-                                                             per_xcd, c);
-  } else {
-    hipError_t e = hipFuncSetAttribute((const void *)k_eval<false>,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    if (e != hipSuccess) return e;
-    k_eval<false><<<(unsigned)grid, cfg.waves * 64, lds, s>>>(pairs_dev, items_dev, n_items,
-                                                              per_xcd, c);
-  }
+  hipError_t e = hipFuncSetAttribute((const void *)k_eval<NEAR, ZVAR>,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, L.total);
+  if (e != hipSuccess) return e;
+  k_eval<NEAR, ZVAR><<<(unsigned)grid, c.waves * 64, (size_t)L.total, s>>>(pairs_dev, items_dev,
+                                                                           n_items, per_xcd, d);
   return hipGetLastError();
+}
+
+hipError_t launch_eval(const PairDev *pairs_dev, const PoseDev *items_dev, int64_t n_items,
+                       const EvalLaunch &c, hipStream_t s) {
+  if (n_items <= 0) return hipSuccess;
+  if (c.near_face)
+    return c.zvar ? launch_one<true, true>(pairs_dev, items_dev, n_items, c, s)
+                  : launch_one<true, false>(pairs_dev, items_dev, n_items, c, s);
+  return c.zvar ? launch_one<false, true>(pairs_dev, items_dev, n_items, c, s)
+                : launch_one<false, false>(pairs_dev, items_dev, n_items, c, s);
 }
 
 }  // namespace mi

@@ -65,7 +65,23 @@ __global__ void __launch_bounds__(256) k_plain_map(PlainDev pd, const float *__r
   hi0 = wave_max_i32(hi0); hi1 = wave_max_i32(hi1); hi2 = wave_max_i32(hi2);
   nin = wave_sum_u64(nin);
   nnf = wave_sum_u64(nnf);
+  // one set of global atomics per block, not per wave
+  __shared__ int sb[4][6];
+  __shared__ unsigned long long sc[4][2];
+  const int w = threadIdx.x >> 6;
   if ((threadIdx.x & 63) == 0) {
+    sb[w][0] = lo0; sb[w][1] = lo1; sb[w][2] = lo2; sb[w][3] = hi0; sb[w][4] = hi1; sb[w][5] = hi2;
+    sc[w][0] = nin;
+    sc[w][1] = nnf;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int k = 1; k < (int)(blockDim.x >> 6); ++k) {
+      lo0 = min(lo0, sb[k][0]); lo1 = min(lo1, sb[k][1]); lo2 = min(lo2, sb[k][2]);
+      hi0 = max(hi0, sb[k][3]); hi1 = max(hi1, sb[k][4]); hi2 = max(hi2, sb[k][5]);
+      nin += sc[k][0];
+      nnf += sc[k][1];
+    }
     if (hi0 >= 0) {
       atomicMin(&pd.bbox[0], lo0); atomicMin(&pd.bbox[1], lo1); atomicMin(&pd.bbox[2], lo2);
       atomicMax(&pd.bbox[3], hi0); atomicMax(&pd.bbox[4], hi1); atomicMax(&pd.bbox[5], hi2);

@@ -137,9 +137,10 @@ hipError_t staging_upload(Staging *s, const Upload *ups, int n, hipStream_t st) 
 
 namespace {
 struct Tuning {
-  int32_t waves = 8;
-  int32_t wave_bytes = 17 * 1024;
-  int32_t hist_copies = 1;
+  int32_t waves = 16;
+  int32_t hash_bytes = 96 * 1024;
+  int32_t hist_copies = 2;
+  int32_t stripe_rows = 8;
 };
 Tuning g_tuning;
 std::mutex g_tuning_mu;
@@ -161,14 +162,16 @@ int max_lds_per_block() {
 
 extern "C" mi_status mi_tuning_set(const mi_tuning *t) {
   if (!t) return fail(MI_E_INVALID, "mi_tuning_set: NULL");
-  if (t->waves < 1 || t->waves > 8) return fail(MI_E_INVALID, "waves must be 1..8");
-  if (t->wave_bytes < 2048 || t->wave_bytes > 160 * 1024 || (t->wave_bytes & 15))
-    return fail(MI_E_INVALID, "wave_bytes must be a multiple of 16 in [2 KiB, 160 KiB]");
+  if (t->waves < 1 || t->waves > 16) return fail(MI_E_INVALID, "waves must be 1..16");
+  if (t->hash_bytes < 1024 || t->hash_bytes > 160 * 1024)
+    return fail(MI_E_INVALID, "hash_bytes must be in [1 KiB, 160 KiB]");
   if (t->hist_copies < 1 || t->hist_copies > 8) return fail(MI_E_INVALID, "hist_copies 1..8");
+  if (t->stripe_rows < 1 || t->stripe_rows > 62) return fail(MI_E_INVALID, "stripe_rows 1..62");
   std::lock_guard<std::mutex> lk(g_tuning_mu);
   g_tuning.waves = t->waves;
-  g_tuning.wave_bytes = t->wave_bytes;
+  g_tuning.hash_bytes = t->hash_bytes;
   g_tuning.hist_copies = t->hist_copies;
+  g_tuning.stripe_rows = t->stripe_rows;
   return MI_OK;
 }
 
@@ -176,9 +179,9 @@ extern "C" mi_status mi_tuning_get(mi_tuning *t) {
   if (!t) return fail(MI_E_INVALID, "mi_tuning_get: NULL");
   std::lock_guard<std::mutex> lk(g_tuning_mu);
   t->waves = g_tuning.waves;
-  t->wave_bytes = g_tuning.wave_bytes;
+  t->hash_bytes = g_tuning.hash_bytes;
   t->hist_copies = g_tuning.hist_copies;
-  t->reserved = 0;
+  t->stripe_rows = g_tuning.stripe_rows;
   return MI_OK;
 }
 
@@ -581,30 +584,50 @@ int build_tables(const GridInfo &gi, const double *poses, int64_t K, PoseTables 
   return 0;
 }
 
-struct BrickShape {
-  int bx, by, bpv;
+int bits_for(int64_t n) {  // bits to hold 0..n-1
+  int b = 0;
+  while (((int64_t)1 << b) < n) ++b;
+  return b;
+}
+
+// Stripes, plan pieces, hash capacity and key packing of one pair under a
+// tuning (see k_eval.hip for how the evaluator uses them).
+struct StripeShape {
+  int stripe_h, n_stripes, pieces, kx_bits, ky_bits, cap_log2, plan_stripes, plan_entries;
+  bool zvar;
 };
 
-// Largest near-square brick of full height whose sums (bpv bytes per voxel)
-// and occupied list (2 bytes per voxel) fit one wave's LDS slice.
-bool choose_brick(const GridInfo &gi, int wave_bytes, BrickShape &b) {
-  b.bpv = (gi.features & MI_FEAT_ZVAR) ? 16 : 4;
-  const int per_vox = b.bpv + 2;
-  int64_t bvox = (wave_bytes - eval_row_table_bytes()) / per_vox;
-  bvox = std::min<int64_t>(bvox, 65536);
-  const int nz = gi.dims[2];
-  int64_t cols = bvox / nz;
-  if (cols < 1) return false;
-  int by = (int)std::floor(std::sqrt((double)cols));
-  by = std::max(1, std::min(by, std::min(gi.dims[1], 61)));
-  int bx = (int)std::min<int64_t>(cols / by, gi.dims[0]);
-  if (bx < 1) return false;
-  // when x is the short side, give the rest to y
-  if (bx == gi.dims[0]) by = std::max(1, (int)std::min<int64_t>(cols / bx, std::min(gi.dims[1], 61)));
-  b.bx = bx;
-  b.by = by;
+bool choose_stripes(const GridInfo &gi, const Tuning &tu, StripeShape &S, const char **why) {
+  S.zvar = (gi.features & MI_FEAT_ZVAR) != 0;
+  const int slot = eval_hash_slot_bytes(S.zvar);
+  int cl = 6;
+  while (cl < 16 && ((int64_t)1 << (cl + 1)) * slot <= tu.hash_bytes) ++cl;
+  if (((int64_t)1 << cl) * slot > tu.hash_bytes) { *why = "hash_bytes too small"; return false; }
+  S.cap_log2 = cl;
+  // a brick counts as overflowed past half the slots; every wave may insert one
+  // more step of 64 voxels before it sees that, and probing needs a free slot
+  const int64_t load_max = ((int64_t)1 << cl) / 2;
+  if ((int64_t)tu.waves * 64 >= load_max) { *why = "voxel hash too small for the waves"; return false; }
+  const int nx = gi.dims[0], ny = gi.dims[1], nz = gi.dims[2];
+  const int64_t wmax = load_max / nz;  // widest x piece whose single voxel row always fits
+  if (wmax < 1) { *why = "grid height exceeds the voxel hash"; return false; }
+  S.stripe_h = std::max(1, std::min(tu.stripe_rows, std::min(ny, 62)));
+  S.n_stripes = (ny + S.stripe_h - 1) / S.stripe_h;
+  int64_t Q = std::max<int64_t>(8, (nx + wmax - 1) / wmax);
+  if (Q > 1024) { *why = "grid too wide for the plan"; return false; }
+  S.pieces = (int)Q;
+  S.kx_bits = bits_for(nx);
+  S.ky_bits = bits_for(S.stripe_h);
+  if (S.kx_bits + S.ky_bits + bits_for(nz) > 31) { *why = "grid dims exceed the voxel key"; return false; }
+  S.plan_entries = (S.stripe_h + 2) * (S.pieces + 1);
+  S.plan_stripes = (int)std::max<int64_t>(1, std::min<int64_t>(S.n_stripes,
+                                                                16384 / (S.plan_entries * 8)));
   return true;
 }
+
+}  // namespace
+
+namespace {
 
 size_t frame_bytes(int64_t n_b, int64_t ncols) {
   auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
@@ -703,15 +726,17 @@ extern "C" mi_status mi_plan_create(const mi_ref *r, int64_t n_b, const double *
   const int64_t ncols = (int64_t)T.ncx * T.ncy;
 
   const Tuning tu = tuning_now();
-  BrickShape bs;
-  if (!choose_brick(gi, tu.wave_bytes, bs))
-    return fail(MI_E_UNSUPPORTED, "grid height %d does not fit a brick of %d LDS bytes",
-                gi.dims[2], tu.wave_bytes);
+  StripeShape SS;
+  const char *why = "";
+  if (!choose_stripes(gi, tu, SS, &why)) return fail(MI_E_UNSUPPORTED, "evaluator: %s", why);
   EvalLaunch L;
   L.waves = tu.waves;
-  L.wave_bytes = tu.wave_bytes;
+  L.cap_log2 = SS.cap_log2;
   L.hist_copies = tu.hist_copies;
   L.hist_words = gi.nb[0] * gi.nb[0] + (gi.nf > 1 ? gi.nb[1] * gi.nb[1] : 0);
+  L.plan_stripes = SS.plan_stripes;
+  L.plan_entries = SS.plan_entries;
+  L.zvar = SS.zvar;
   L.near_face = (flags & MI_EVAL_NEAR_FACE) != 0;
   if ((int64_t)eval_lds_bytes(L) > max_lds_per_block())
     return fail(MI_E_UNSUPPORTED, "tuning needs %zu LDS bytes per workgroup, device has %d",
@@ -785,10 +810,11 @@ extern "C" mi_status mi_plan_create(const mi_ref *r, int64_t n_b, const double *
     P.fstride = (int64_t)nbp;
     P.foff = PL.foff;
     P.gx = T.gx; P.gy = T.gy; P.ncx = T.ncx; P.ncy = T.ncy;
-    P.bx = bs.bx; P.by = bs.by;
-    P.nbx = (gi.dims[0] + bs.bx - 1) / bs.bx;
-    P.nby = (gi.dims[1] + bs.by - 1) / bs.by;
-    P.bpv = bs.bpv;
+    P.stripe_h = SS.stripe_h;
+    P.n_stripes = SS.n_stripes;
+    P.pieces = SS.pieces;
+    P.kx_bits = SS.kx_bits;
+    P.ky_bits = SS.ky_bits;
     P.nonfinite = PL.nonfinite;
     P.n_b = n_b;
     P.K = K;

@@ -8,6 +8,13 @@ namespace mi {
 
 typedef unsigned __int128 u128;
 
+// Load through the global address space (tables reached through pointers held
+// in memory are otherwise generic, and generic loads also hold up LDS waits).
+template <class T>
+__device__ __forceinline__ T ldg(const T *p) {
+  return *(const __attribute__((address_space(1))) T *)p;
+}
+
 // Point-count feature (Sec. III-A, number of points in the voxel):
 // bin = #{j : n >= e[j]} over nb-1 non-decreasing edges (binary search).
 __device__ __forceinline__ int bin_count_dev(uint32_t n, int nb, const uint32_t *e) {
@@ -72,7 +79,7 @@ __device__ __forceinline__ uint32_t sat_box(const uint32_t *S, int nx, int ny, i
                                             int z0, int x1, int y1, int z1) {
   const int64_t sx = 1, sy = nx + 1, sz = (int64_t)(nx + 1) * (ny + 1);
   const int64_t X0 = x0, X1 = x1 + 1, Y0 = y0, Y1 = y1 + 1, Z0 = z0, Z1 = z1 + 1;
-  auto at = [&](int64_t x, int64_t y, int64_t z) { return (int64_t)S[z * sz + y * sy + x * sx]; };
+  auto at = [&](int64_t x, int64_t y, int64_t z) { return (int64_t)ldg(S + (z * sz + y * sy + x * sx)); };
   const int64_t v = at(X1, Y1, Z1) - at(X0, Y1, Z1) - at(X1, Y0, Z1) - at(X1, Y1, Z0) +
                     at(X0, Y0, Z1) + at(X0, Y1, Z0) + at(X1, Y0, Z0) - at(X0, Y0, Z0);
   return (uint32_t)v;

@@ -87,8 +87,10 @@ struct PairDev {
   int64_t fstride;
   const uint32_t *foff;      // frame f at foff + f * (ncols + 1)
   int32_t gx, gy, ncx, ncy;
-  int32_t bx, by, nbx, nby;  // bricks: bx * by columns, full height
-  int32_t bpv;               // LDS bytes per brick voxel: 4 (count only) or 16
+  int32_t stripe_h;          // voxel rows per stripe (bricks are pieces of stripes)
+  int32_t n_stripes;
+  int32_t pieces;            // x pieces per stripe in the plan
+  int32_t kx_bits, ky_bits;  // hash key: iz << (kx+ky) | (iy - stripe y0) << kx | ix
   int32_t pad0;
   const unsigned long long *nonfinite; // device counter
   int64_t n_b;
@@ -109,18 +111,22 @@ struct PoseDev {
   double c[3];               // fl(fl(t - origin) * s)
 };
 
+// Launch shape of the evaluator (one workgroup per pose).
 struct EvalLaunch {
-  int32_t waves;             // waves per workgroup
-  int32_t wave_bytes;        // LDS bytes per wave for its brick
-  int32_t hist_copies;       // privatized histogram copies per workgroup
+  int32_t waves;             // waves per workgroup (1..16)
+  int32_t cap_log2;          // LDS voxel-hash slots = 1 << cap_log2
+  int32_t hist_copies;       // privatized joint-histogram copies
   int32_t hist_words;        // max over pairs of sum_f nb_f^2
+  int32_t plan_stripes;      // stripes planned per round
+  int32_t plan_entries;      // max rows * (pieces + 1) per stripe over pairs
+  bool zvar;                 // 16-byte voxel sums (else 4-byte counts)
   bool near_face;
 };
 
 hipError_t launch_eval(const PairDev *pairs_dev, const PoseDev *items_dev, int64_t n_items,
                        const EvalLaunch &cfg, hipStream_t s);
 size_t eval_lds_bytes(const EvalLaunch &cfg);
-int32_t eval_row_table_bytes();
+int32_t eval_hash_slot_bytes(bool zvar);
 
 // -------------------------------------------------------------------- plain
 

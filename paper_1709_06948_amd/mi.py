@@ -52,8 +52,8 @@ class _Profile(C.Structure):
 
 
 class _Tuning(C.Structure):
-    _fields_ = [("waves", C.c_int32), ("wave_bytes", C.c_int32), ("hist_copies", C.c_int32),
-                ("reserved", C.c_int32)]
+    _fields_ = [("waves", C.c_int32), ("hash_bytes", C.c_int32), ("hist_copies", C.c_int32),
+                ("stripe_rows", C.c_int32)]
 
 
 def _load():
@@ -152,11 +152,12 @@ def status_str(s: int) -> str:
 def tuning_get() -> dict:
     t = _Tuning()
     _check(_lib.mi_tuning_get(C.byref(t)), "mi_tuning_get")
-    return dict(waves=t.waves, wave_bytes=t.wave_bytes, hist_copies=t.hist_copies)
+    return dict(waves=t.waves, hash_bytes=t.hash_bytes, hist_copies=t.hist_copies,
+                stripe_rows=t.stripe_rows)
 
 
-def tuning_set(waves: int, wave_bytes: int, hist_copies: int = 1):
-    t = _Tuning(int(waves), int(wave_bytes), int(hist_copies), 0)
+def tuning_set(waves: int, hash_bytes: int, hist_copies: int = 2, stripe_rows: int = 8):
+    t = _Tuning(int(waves), int(hash_bytes), int(hist_copies), int(stripe_rows))
     _check(_lib.mi_tuning_set(C.byref(t)), "mi_tuning_set")
 
 

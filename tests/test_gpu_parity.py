@@ -212,9 +212,11 @@ def test_chunked_frames_and_tuning_variants_identical(M):
     bmi = base["mi"].cpu().numpy()
     orig = M.tuning_get()
     try:
-        for waves, wb, hc in [(4, 17408, 1), (8, 8192, 2), (2, 36864, 1), (8, 14336, 4), (1, 65536, 1)]:
-            _say("tuning", waves, wb, hc)
-            M.tuning_set(waves, wb, hc)
+        for waves, hb, hc, sr in [(4, 98304, 1, 8), (8, 49152, 2, 4), (2, 36864, 1, 16),
+                                  (16, 98304, 4, 1), (1, 65536, 1, 3), (1, 8192, 2, 62),
+                                  (3, 16384, 2, 40)]:
+            _say("tuning", waves, hb, hc, sr)
+            M.tuning_set(waves, hb, hc, sr)
             r = M.eval_poses(ref, p.B, P, want_hist=True)
             torch.cuda.synchronize()
             for f in range(2):
