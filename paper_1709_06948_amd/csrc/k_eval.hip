@@ -5,23 +5,26 @@
 // rows, full height).  All waves of the workgroup work on one brick at a time
 // and every B point that lands in the brick is aggregated there, so each
 // voxel's sums (n, S1, S2) are complete in LDS without any merge across
-// workgroups.  The sums live in an LDS hash keyed by the voxel.  Bricks are
-// tried optimistically: once a brick holds more distinct voxels than half the
-// slots, the waves stop inserting (the hash keeps room for one more step of
-// every wave, so probing always ends), the brick is cleared without touching
-// the histogram and is retried in halves; a single x piece is retried one voxel
-// row at a time, which always fits.
+// workgroups.  The sums live in an LDS hash keyed by the voxel (linear probing).
+// Bricks are tried optimistically: a point whose probe sequence exceeds
+// kMaxProbe slots (the table is close to full) marks the brick as overflowed;
+// the brick is then cleared without touching the histogram and retried in
+// halves; a single x piece is retried one voxel row at a time, whose voxels
+// never exceed a quarter of the slots.
 //
 // Per pose:
 //  plan   for a group of stripes, one parallel round of loads reads the column
 //         offsets of every candidate row at the stripe's piece cuts, so brick
 //         boundaries and candidate ranges are known without further round trips;
 //  bricks the rest of the stripe first, halved on overflow;
-//  points 64 consecutive candidates of one column row per wave step: u = fl(v+c),
-//         voxel floor(u); in-brick points insert their voxel into the hash and add
-//         n, S1, S2 (LDS atomics), and extend B's extent;
-//  sweep  every occupied voxel inside A's index box (with B's extent this is the
-//         overlap box) adds one to the joint histogram at (A's bin, B's bin);
+//  points four candidates per lane per wave step, branch-free: u = fl(v+c),
+//         voxel floor(u); in-brick points find or insert their voxel (one probe
+//         read and one compare-and-swap each, all four in flight together),
+//         newly claimed slots are appended to the brick's occupied list, and
+//         n, S1, S2 are added with LDS atomics that return nothing;
+//  sweep  every slot on the brick's occupied list: B's extent and point
+//         count, and, for voxels inside A's index box (with B's extent this is
+//         the overlap box), one count in the joint histogram at (A's bin, B's bin);
 //  finish overlap box O; the cells of voxels that B leaves empty come from A's
 //         per-bin summed-volume tables; entropies and MI.
 #include "mi_device.h"
@@ -32,11 +35,13 @@
 namespace mi {
 
 static constexpr uint32_t kEmpty = 0xffffffffu;
+static constexpr uint32_t kNever = 0xfffffffeu;  // never a key, never empty
+static constexpr int kMaxProbe = 32;
 
 struct EvalCfgDev {
   int32_t hist_copies, hist_words;
   int32_t cap_log2;
-  int32_t load_max;           // distinct voxels per brick before it counts as overflowed
+  int32_t load_max;           // voxels of a brick that is known to fit (a quarter of the slots)
   int32_t plan_stripes;
   int32_t plan_entries;       // per stripe: rows * (pieces + 1)
   int32_t off_cnta, off_edges, off_wave, off_plan, off_hash, pad;
@@ -55,10 +60,11 @@ __host__ __device__ inline Layout eval_layout(int waves, int hist_copies, int hi
   int o = al16(hist_copies * hist_words * 4);
   L.off_cnta = o;   o += 512;                   // cntA[2][64]
   L.off_edges = o;  o += 256 + 512;             // 64 u32 + 64 u64
-  L.off_wave = o;   o += al16(waves * 48 + 16); // box [W][8] i32, counts [W][2] u64, occ counters
+  L.off_wave = o;   o += al16(waves * 48 + 16); // box [W][8] i32, counts [W][2] u64, flags
+  o += 64 * 4 + 64 * 16;                        // dummy targets of masked lanes
   L.off_plan = o;   o += al16(plan_stripes * plan_entries * 8);
   o = (o + 255) & ~255;
-  L.off_hash = o;   o += cap * (4 + (zvar ? 16 : 4)) + 2 * cap;  // keys, sums, occupied list (u16)
+  L.off_hash = o;   o += cap * (4 + (zvar ? 16 : 4)) + 2 * cap;  // keys, sums, occupied list
   L.total = al16(o);
   return L;
 }
@@ -97,14 +103,17 @@ __global__ void __launch_bounds__(1024) k_eval(const PairDev *__restrict__ pairs
   uint64_t *zedge = (uint64_t *)(cedge + 64);
   int *wbox = (int *)(smem + cfg.off_wave);
   unsigned long long *wcnt = (unsigned long long *)(wbox + 8 * W);
-  uint32_t *occn = (uint32_t *)(wcnt + 2 * W);
+  uint32_t *ovf = (uint32_t *)(wcnt + 2 * W);   // [2] overflow flags by brick parity
+  uint32_t *occn = ovf + 2;                     // [2] occupied-slot counts by brick parity
+  uint32_t *dkey = (uint32_t *)(smem + cfg.off_wave + al16(W * 48 + 16));
+  unsigned long long *dval = (unsigned long long *)(dkey + 64);
   uint2 *plan = (uint2 *)(smem + cfg.off_plan);
   const int cap = 1 << cfg.cap_log2;
   uint32_t *hkey = (uint32_t *)(smem + cfg.off_hash);
   unsigned long long *hv1 = (unsigned long long *)(hkey + cap);   // ZVAR: n<<44 | S1
   unsigned long long *hv2 = hv1 + cap;                            // ZVAR: S2
   uint32_t *hcnt = hkey + cap;                                    // count only
-  uint16_t *occ = (uint16_t *)(smem + cfg.off_hash + cap * (4 + (ZVAR ? 16 : 4)));
+  uint16_t *occ = (uint16_t *)(hkey + cap * (ZVAR ? 5 : 2));      // slots in insertion order
 
   const int nx = P.nx, ny = P.ny, nz = P.nz, nf = P.nf;
   const int nb0 = P.nb[0], nb1 = nf > 1 ? P.nb[1] : 0;
@@ -119,7 +128,7 @@ __global__ void __launch_bounds__(1024) k_eval(const PairDev *__restrict__ pairs
     hkey[i] = kEmpty;
     if (ZVAR) { hv1[i] = 0ull; hv2[i] = 0ull; } else { hcnt[i] = 0u; }
   }
-  if (tid < 2) occn[tid] = 0u;
+  if (tid < 4) ovf[tid] = 0u;
   __syncthreads();
 
   const double cx = pose.c[0], cy = pose.c[1], cz = pose.c[2];
@@ -206,109 +215,160 @@ __global__ void __launch_bounds__(1024) k_eval(const PairDev *__restrict__ pairs
             const uint32_t my_cpre = inc - my_c;
             const int nch = nr > 0 ? (int)__shfl(inc, nr - 1, 64) : 0;
             if (nch == 0) continue;
-            int64_t ncand = 0;
-            for (int r = 0; r < nr; ++r) ncand += __shfl(my_len, r, 64);
-            const int64_t bvox = (int64_t)(X1 - X0) * (Y1 - Y0) * nz;
-            const bool guaranteed = (ncand < bvox ? ncand : bvox) <= cfg.load_max;
             const int p = parity;
-            int blo0 = nx, blo1 = ny, blo2 = nz, bhi0 = -1, bhi1 = -1, bhi2 = -1;
-            unsigned long long bnin = 0, bnear = 0;
-            // chunk k -> (candidate index of this lane, valid)
+            unsigned long long bnear = 0;
+            // a brick with at most a quarter of the slots in voxels always has an
+            // empty slot: it probes without limit and cannot overflow (single
+            // voxel rows of a piece are always such bricks)
+            const bool fits = (int64_t)(X1 - X0) * (Y1 - Y0) * nz <= cfg.load_max;
+            const int max_probe = fits ? cap : kMaxProbe;
+            // chunk k -> candidate of this lane.  A row of len candidates takes
+            // c = ceil(len/64) chunks; its candidates are cut into 4 runs of 16*c and
+            // step j of the row gives lane l candidate (l/16)*16c + 16j + l%16:
+            // 4 cache lines per load as for 64 consecutive candidates, but lanes of
+            // one step lie in 4 different parts of the row, which spreads the hot
+            // voxels (dense ground near the sensor) over fewer lanes per atomic.
             auto chunk_idx = [&](int k, bool *valid) -> uint32_t {
               const unsigned long long mk = __ballot(lane < nr && my_cpre <= (uint32_t)k);
               const int row = __popcll(mk) - 1;
               const uint32_t st = __builtin_amdgcn_readlane(my_st, row);
               const uint32_t len = __builtin_amdgcn_readlane(my_len, row);
               const uint32_t cpre = __builtin_amdgcn_readlane(my_cpre, row);
-              const uint32_t idx = st + ((uint32_t)k - cpre) * 64u + (uint32_t)lane;
-              *valid = idx < st + len;
-              return idx;
+              const uint32_t c = (len + 63u) >> 6;
+              const uint32_t j = (uint32_t)k - cpre;
+              const uint32_t off_in_row = ((uint32_t)lane >> 4) * (c << 4) + (j << 4) +
+                                          ((uint32_t)lane & 15u);
+              *valid = off_in_row < len;
+              return st + off_in_row;
             };
-            int k = wid;
-            bool cval = false;
-            double cvx = 0.0, cvy = 0.0, cvz = 0.0;
-            if (k < nch) {
-              const uint32_t idx = chunk_idx(k, &cval);
-              if (cval) { cvx = ldg(fvx + idx); cvy = ldg(fvy + idx); cvz = ldg(fvz + idx); }
-            }
-            for (; k < nch; k += W) {
-              // prefetch the wave's next chunk while this one is processed
-              bool nval = false;
-              double nvx = 0.0, nvy = 0.0, nvz = 0.0;
-              if (k + W < nch) {
-                const uint32_t idx = chunk_idx(k + W, &nval);
-                if (nval) { nvx = ldg(fvx + idx); nvy = ldg(fvy + idx); nvz = ldg(fvz + idx); }
-              }
-              if (!guaranteed &&
-                  __atomic_load_n(&occn[p], __ATOMIC_RELAXED) > (uint32_t)cfg.load_max)
-                break;
-              bool ins = false;
-              uint32_t slot = 0;
-              if (cval) {
-                const double ux = cvx + cx, uy = cvy + cy, uz = cvz + cz;
-                const double fx = floor(ux), fy = floor(uy), fz = floor(uz);
-                if (fx >= (double)X0 && fx < (double)X1 && fy >= (double)Y0 && fy < (double)Y1 &&
-                    fz >= 0.0 && fz < (double)nz) {
-                  const int ix = (int)fx, iy = (int)fy, iz = (int)fz;
-                  const uint32_t key = ((uint32_t)iz << (kxb + kyb)) |
-                                       ((uint32_t)(iy - SY0) << kxb) | (uint32_t)ix;
-                  uint32_t h = (key * 2654435761u) >> (32 - cfg.cap_log2);
-                  for (;;) {
-                    const uint32_t k0 = __atomic_load_n(&hkey[h], __ATOMIC_RELAXED);
-                    if (k0 == key) break;
-                    if (k0 == kEmpty) {
-                      const uint32_t old = atomicCAS(&hkey[h], kEmpty, key);
-                      if (old == kEmpty) { ins = true; break; }
-                      if (old == key) break;
-                    }
-                    h = (h + 1u) & (uint32_t)(cap - 1);
-                  }
-                  slot = h;
-                  if (ZVAR) {
-                    const unsigned long long q = (unsigned long long)floor((uz - fz) * kQScale);
-                    atomicAdd(&hv1[h], (1ull << 44) | q);
-                    atomicAdd(&hv2[h], q * q);
-                  } else {
-                    atomicAdd(&hcnt[h], 1u);
-                  }
-                  ++bnin;
-                  blo0 = min(blo0, ix); blo1 = min(blo1, iy); blo2 = min(blo2, iz);
-                  bhi0 = max(bhi0, ix); bhi1 = max(bhi1, iy); bhi2 = max(bhi2, iz);
-                  if (NEAR && ix >= alo0 && ix <= ahi0 && iy >= alo1 && iy <= ahi1 &&
-                      iz >= alo2 && iz <= ahi2) {
-                    double d = 1.0;
-                    const double fr[3] = {ux - fx, uy - fy, uz - fz};
+            // Four candidates per lane, branch-free up to the rare collisions.
+            auto step4 = [&](const bool (&val)[4], const double (&vx)[4], const double (&vy)[4],
+                             const double (&vz)[4]) {
+              bool inb[4];
+              uint32_t key[4], h[4], q[4];
 #pragma unroll
-                    for (int a = 0; a < 3; ++a) {
-                      const double up = 1.0 - fr[a];
-                      const double m = fr[a] < up ? fr[a] : up;
-                      if (m < d) d = m;
+              for (int i = 0; i < 4; ++i) {
+                const double ux = vx[i] + cx, uy = vy[i] + cy, uz = vz[i] + cz;
+                const double fx = floor(ux), fy = floor(uy), fz = floor(uz);
+                // v_cvt_i32_f64 saturates, so far-away points stay out of range
+                const int ix = (int)fx, iy = (int)fy, iz = (int)fz;
+                inb[i] = val[i] && (uint32_t)(ix - X0) < (uint32_t)(X1 - X0) &&
+                         (uint32_t)(iy - Y0) < (uint32_t)(Y1 - Y0) && (uint32_t)iz < (uint32_t)nz;
+                key[i] = ((uint32_t)iz << (kxb + kyb)) | ((uint32_t)(iy - SY0) << kxb) |
+                         (uint32_t)ix;
+                h[i] = (key[i] * 2654435761u) >> (32 - cfg.cap_log2);
+                q[i] = ZVAR ? (uint32_t)floor((uz - fz) * kQScale) : 0u;
+                if (NEAR && inb[i] && ix >= alo0 && ix <= ahi0 && iy >= alo1 && iy <= ahi1 &&
+                    iz >= alo2 && iz <= ahi2) {
+                  double d = 1.0;
+                  const double fr[3] = {ux - fx, uy - fy, uz - fz};
+#pragma unroll
+                  for (int a = 0; a < 3; ++a) {
+                    const double up = 1.0 - fr[a];
+                    const double m = fr[a] < up ? fr[a] : up;
+                    if (m < d) d = m;
+                  }
+                  if (d * P.voxel < kNearFace) ++bnear;
+                }
+              }
+              uint32_t k0[4];
+#pragma unroll
+              for (int i = 0; i < 4; ++i) k0[i] = __atomic_load_n(&hkey[h[i]], __ATOMIC_RELAXED);
+              bool coll[4], fresh[4];
+#pragma unroll
+              for (int i = 0; i < 4; ++i) {
+                // masked lanes swap on their own dummy word with a value that never matches
+                const bool want = inb[i] && k0[i] == kEmpty;
+                uint32_t *a = want ? &hkey[h[i]] : &dkey[lane];
+                const uint32_t old = atomicCAS(a, want ? kEmpty : kNever, key[i]);
+                const bool got = want ? (old == kEmpty || old == key[i]) : (k0[i] == key[i]);
+                fresh[i] = want && old == kEmpty;
+                coll[i] = inb[i] && !got;
+              }
+              if (coll[0] || coll[1] || coll[2] || coll[3]) {
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                  if (!coll[i]) continue;
+                  uint32_t hh = h[i];
+                  bool ok = false;
+                  for (int pr = 1; pr < max_probe; ++pr) {
+                    hh = (hh + 1u) & (uint32_t)(cap - 1);
+                    uint32_t k1 = __atomic_load_n(&hkey[hh], __ATOMIC_RELAXED);
+                    if (k1 == kEmpty) {
+                      k1 = atomicCAS(&hkey[hh], kEmpty, key[i]);
+                      if (k1 == kEmpty) fresh[i] = true;
                     }
-                    if (d * P.voxel < kNearFace) ++bnear;
+                    if (k1 == kEmpty || k1 == key[i]) { ok = true; break; }
+                  }
+                  if (ok) h[i] = hh;
+                  else { ovf[p] = 1u; inb[i] = false; }
+                }
+              }
+              // newly claimed slots go on the brick's occupied list (one LDS atomic per wave)
+              {
+                unsigned long long m[4];
+                uint32_t tot = 0;
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                  m[i] = __ballot(fresh[i]);
+                  tot += (uint32_t)__popcll(m[i]);
+                }
+                if (tot) {
+                  uint32_t base = 0;
+                  if (lane == 0) base = atomicAdd(&occn[p], tot);
+                  base = __shfl(base, 0, 64);
+#pragma unroll
+                  for (int i = 0; i < 4; ++i) {
+                    if (fresh[i]) {
+                      const uint32_t r = __builtin_amdgcn_mbcnt_hi(
+                          (uint32_t)(m[i] >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m[i], 0u));
+                      occ[base + r] = (uint16_t)h[i];
+                    }
+                    base += (uint32_t)__popcll(m[i]);
                   }
                 }
               }
-              const unsigned long long m = __ballot(ins);
-              if (m) {
-                uint32_t base_slot = 0;
-                if (lane == 0) base_slot = atomicAdd(&occn[p], (uint32_t)__popcll(m));
-                base_slot = __shfl(base_slot, 0, 64);
-                if (ins) {
-                  const uint32_t pos = base_slot + __builtin_amdgcn_mbcnt_hi(
-                                                       (uint32_t)(m >> 32),
-                                                       __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
-                  occ[pos] = (uint16_t)slot;
+#pragma unroll
+              for (int i = 0; i < 4; ++i) {
+                if (ZVAR) {
+                  unsigned long long *a1 = inb[i] ? &hv1[h[i]] : &dval[lane];
+                  unsigned long long *a2 = inb[i] ? &hv2[h[i]] : &dval[64 + lane];
+                  atomicAdd(a1, (1ull << 44) | (unsigned long long)q[i]);
+                  atomicAdd(a2, (unsigned long long)q[i] * q[i]);
+                } else {
+                  atomicAdd(inb[i] ? &hcnt[h[i]] : &dkey[lane], 1u);
                 }
               }
-              cval = nval;
-              cvx = nvx;
-              cvy = nvy;
-              cvz = nvz;
+            };
+            // Four chunks per wave step: the twelve loads are issued together, then
+            // the four candidates of each lane go through step4 together.  Lanes
+            // past a row's end load index 0 (always valid) and are masked off.
+            for (int k = wid; k < nch; k += 4 * W) {
+              bool v[4];
+              uint32_t ii[4];
+              ii[0] = chunk_idx(k, &v[0]);
+#pragma unroll
+              for (int i = 1; i < 4; ++i) {
+                v[i] = false;
+                ii[i] = 0u;
+                if (k + i * W < nch) ii[i] = chunk_idx(k + i * W, &v[i]);
+              }
+              double x[4], y[4], z[4];
+#pragma unroll
+              for (int i = 0; i < 4; ++i) {
+                const uint32_t j = v[i] ? ii[i] : 0u;
+                x[i] = ldg(fvx + j);
+                y[i] = ldg(fvy + j);
+                z[i] = ldg(fvz + j);
+              }
+              step4(v, x, y, z);
             }
             __syncthreads();
+            const bool overflow = ovf[p] != 0u;
             const int nocc = (int)occn[p];
-            const bool overflow = nocc > cfg.load_max;
-            if (tid == 0) occn[p ^ 1] = 0u;
+            if (tid == 0) { ovf[p ^ 1] = 0u; occn[p ^ 1] = 0u; }
+            int blo0 = nx, blo1 = ny, blo2 = nz, bhi0 = -1, bhi1 = -1, bhi2 = -1;
+            unsigned long long bnin = 0;
             for (int i = tid; i < nocc; i += T) {
               const uint32_t h = occ[i];
               const uint32_t key = hkey[h];
@@ -329,6 +389,9 @@ __global__ void __launch_bounds__(1024) k_eval(const PairDev *__restrict__ pairs
                 hcnt[h] = 0u;
               }
               hkey[h] = kEmpty;
+              bnin += n;
+              blo0 = min(blo0, ix); blo1 = min(blo1, iy); blo2 = min(blo2, iz);
+              bhi0 = max(bhi0, ix); bhi1 = max(bhi1, iy); bhi2 = max(bhi2, iz);
               if (!overflow && ix >= alo0 && ix <= ahi0 && iy >= alo1 && iy <= ahi1 &&
                   iz >= alo2 && iz <= ahi2) {
                 const int64_t lin = ((int64_t)iz * ny + iy) * nx + ix;
@@ -496,7 +559,7 @@ static hipError_t launch_one(const PairDev *pairs_dev, const PoseDev *items_dev,
   d.hist_copies = c.hist_copies;
   d.hist_words = c.hist_words;
   d.cap_log2 = c.cap_log2;
-  d.load_max = (1 << c.cap_log2) / 2;
+  d.load_max = (1 << c.cap_log2) / 4;
   d.plan_stripes = c.plan_stripes;
   d.plan_entries = c.plan_entries;
   d.off_cnta = L.off_cnta;

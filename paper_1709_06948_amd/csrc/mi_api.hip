@@ -137,8 +137,8 @@ hipError_t staging_upload(Staging *s, const Upload *ups, int n, hipStream_t st) 
 
 namespace {
 struct Tuning {
-  int32_t waves = 16;
-  int32_t hash_bytes = 96 * 1024;
+  int32_t waves = 8;
+  int32_t hash_bytes = 48 * 1024;
   int32_t hist_copies = 2;
   int32_t stripe_rows = 8;
 };
@@ -604,10 +604,9 @@ bool choose_stripes(const GridInfo &gi, const Tuning &tu, StripeShape &S, const 
   while (cl < 16 && ((int64_t)1 << (cl + 1)) * slot <= tu.hash_bytes) ++cl;
   if (((int64_t)1 << cl) * slot > tu.hash_bytes) { *why = "hash_bytes too small"; return false; }
   S.cap_log2 = cl;
-  // a brick counts as overflowed past half the slots; every wave may insert one
-  // more step of 64 voxels before it sees that, and probing needs a free slot
-  const int64_t load_max = ((int64_t)1 << cl) / 2;
-  if ((int64_t)tu.waves * 64 >= load_max) { *why = "voxel hash too small for the waves"; return false; }
+  // bricks of at most a quarter of the slots in voxels always fit; single voxel
+  // rows of an x piece must be such bricks
+  const int64_t load_max = ((int64_t)1 << cl) / 4;
   const int nx = gi.dims[0], ny = gi.dims[1], nz = gi.dims[2];
   const int64_t wmax = load_max / nz;  // widest x piece whose single voxel row always fits
   if (wmax < 1) { *why = "grid height exceeds the voxel hash"; return false; }

@@ -28,17 +28,36 @@ __device__ __forceinline__ int bin_count_dev(uint32_t n, int nb, const uint32_t 
 
 // z-height variance feature (Sec. III-A, variance of z in the voxel) on the
 // fixed-point heights q: empty -> 0, else 1 + #{j : n*S2 - S1^2 >= E[j]*n^2}
-// over nb-2 non-decreasing edges, exact in 128-bit integers.
-__device__ __forceinline__ int bin_zvar_dev(uint32_t n, uint64_t s1, uint64_t s2, int nb,
-                                            const uint64_t *E) {
-  if (n == 0) return 0;
-  const u128 D = (u128)n * (u128)s2 - (u128)s1 * (u128)s1;
-  const u128 n2 = (u128)n * (u128)n;
-  int lo = 0, hi = nb - 2;
+// over nb-2 non-decreasing edges, decided exactly in 128-bit integers.
+// The search runs on r = D / n^2 in FP64 (relative error below 2^-50) against
+// the edges as doubles (exact: edges stay below 2^53); only when an edge lies
+// within a relative 2^-30 of r is the count redone with the exact comparison.
+__device__ __forceinline__ int bin_zvar_exact(u128 D, u128 n2, int m, const uint64_t *E) {
+  int lo = 0, hi = m;
   while (lo < hi) {
     const int mid = (lo + hi + 1) >> 1;
     if (D >= (u128)E[mid - 1] * n2) lo = mid; else hi = mid - 1;
   }
+  return lo;
+}
+
+__device__ __forceinline__ int bin_zvar_dev(uint32_t n, uint64_t s1, uint64_t s2, int nb,
+                                            const uint64_t *E) {
+  if (n == 0) return 0;
+  const u128 D = (u128)n * (u128)s2 - (u128)s1 * (u128)s1;
+  const double nd = (double)n;
+  const double r = ((double)(uint64_t)(D >> 64) * 18446744073709551616.0 + (double)(uint64_t)D) /
+                   (nd * nd);
+  const int m = nb - 2;
+  int lo = 0, hi = m;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (r >= (double)E[mid - 1]) lo = mid; else hi = mid - 1;
+  }
+  const double tol = 0x1p-30;
+  const bool near_lo = lo > 0 && r - (double)E[lo - 1] <= tol * (double)E[lo - 1];
+  const bool near_hi = lo < m && (double)E[lo] - r <= tol * (double)E[lo];
+  if (near_lo || near_hi) lo = bin_zvar_exact(D, (u128)n * (u128)n, m, E);
   return 1 + lo;
 }
 
