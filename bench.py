@@ -51,8 +51,8 @@ def _args():
 def main():
     a = _args()
     if a.gpus != 1:
-        print(json.dumps({"error": "this benchmark runs on one GPU; multi-GPU runs are not part "
-                                   "of this build (pose sharding is described in DESIGN.md)",
+        print(json.dumps({"error": "this benchmark runs on one GPU only; pose sets are not "
+                                   "sharded over several GPUs",
                           "n_gpus": a.gpus}), flush=True)
         sys.exit(2)
     import torch

@@ -225,6 +225,46 @@ mi_status mi_plan_execute(mi_plan *p, const float *xyz_b, double *mi_out, int64_
                           uint32_t *hist_out, mi_pose_stats *stats_out, void *stream);
 void mi_plan_destroy(mi_plan *p);
 
+/* ------------------------------------------------------------ batches */
+
+/* One scan pair and its pose set in a batch (Eq. 1 evaluated for every pose
+ * of every item).  All pointers except `poses` are device memory owned by the
+ * caller and must stay valid while the batch is executed.  Items may share a
+ * reference or a scan B; grids, voxel sizes, bins and point counts may differ
+ * from item to item. */
+typedef struct mi_work_item {
+  const mi_ref *ref;          /* scan A's reference features and grid */
+  const float *xyz_b;         /* scan B, SoA [3][n_b] */
+  int64_t n_b;
+  const double *poses;        /* host [K][6] (read during mi_batch_create only) */
+  int64_t K;
+  double *mi_out;             /* [nf][K] */
+  int64_t *argmax_out;        /* [nf] or NULL */
+  uint32_t *hist_out;         /* [nf][K][nb_f][nb_f] or NULL */
+  mi_pose_stats *stats_out;   /* [K] or NULL */
+} mi_work_item;
+
+/* The poses of many scan pairs evaluated as one schedule: every pair's
+ * rotated frames are built together and a single evaluator launch per frame
+ * chunk covers the poses of all pairs, so pairs of uneven size share the
+ * device.  Results per item are those mi_eval_poses gives for the item alone
+ * (bit-identical histograms and MI).  mi_batch_workspace sizes `ws`
+ * (frame_budget_bytes as for mi_eval_poses_workspace; 0 on bad items).
+ * mi_batch_create validates every item (MI_E_INVALID / MI_E_UNSUPPORTED name
+ * the item in mi_last_error) and uploads the tables on `stream`;
+ * mi_batch_execute only enqueues kernels (capturable in a HIP graph and
+ * replayable; the items' buffers are fixed at creation).  The z-variance
+ * feature in any item limits every item of the batch to n_b < 2^20.
+ * mi_eval_batch = create + execute + destroy. */
+size_t mi_batch_workspace(const mi_work_item *items, int64_t n_items, uint32_t flags,
+                          size_t frame_budget_bytes);
+mi_status mi_batch_create(const mi_work_item *items, int64_t n_items, uint32_t flags, void *ws,
+                          size_t ws_bytes, size_t frame_budget_bytes, void *stream,
+                          mi_plan **out);
+mi_status mi_batch_execute(mi_plan *p, void *stream);
+mi_status mi_eval_batch(const mi_work_item *items, int64_t n_items, uint32_t flags, void *ws,
+                        size_t ws_bytes, void *stream);
+
 /* ------------------------------------------------------------- search */
 
 /* Coarse-to-fine grid search for Eq. 1 from the initial guess T_o = init

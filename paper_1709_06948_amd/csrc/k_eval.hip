@@ -42,8 +42,6 @@ struct EvalCfgDev {
   int32_t hist_copies, hist_words;
   int32_t cap_log2;
   int32_t load_max;           // voxels of a brick that is known to fit (a quarter of the slots)
-  int32_t plan_stripes;
-  int32_t plan_entries;       // per stripe: rows * (pieces + 1)
   int32_t off_cnta, off_edges, off_wave, off_plan, off_hash, pad;
 };
 
@@ -54,15 +52,14 @@ struct Layout {
 __host__ __device__ inline int al16(int x) { return (x + 15) & ~15; }
 
 __host__ __device__ inline Layout eval_layout(int waves, int hist_copies, int hist_words,
-                                              int plan_stripes, int plan_entries, int cap,
-                                              bool zvar) {
+                                              int plan_bytes, int cap, bool zvar) {
   Layout L;
   int o = al16(hist_copies * hist_words * 4);
   L.off_cnta = o;   o += 512;                   // cntA[2][64]
   L.off_edges = o;  o += 256 + 512;             // 64 u32 + 64 u64
   L.off_wave = o;   o += al16(waves * 48 + 16); // box [W][8] i32, counts [W][2] u64, flags
   o += 64 * 4 + 64 * 16;                        // dummy targets of masked lanes
-  L.off_plan = o;   o += al16(plan_stripes * plan_entries * 8);
+  L.off_plan = o;   o += al16(plan_bytes);
   o = (o + 255) & ~255;
   L.off_hash = o;   o += cap * (4 + (zvar ? 16 : 4)) + 2 * cap;  // keys, sums, occupied list
   L.total = al16(o);
@@ -84,6 +81,7 @@ __device__ __forceinline__ void rows_for(int y0, int y1, double cy, int gy, int 
 
 template <bool NEAR, bool ZVAR>
 __global__ void __launch_bounds__(1024) k_eval(const PairDev *__restrict__ pairs,
+                                               const FrameDev *__restrict__ frames,
                                                const PoseDev *__restrict__ items, int64_t n_items,
                                                int64_t per_xcd, EvalCfgDev cfg) {
   extern __shared__ __align__(16) unsigned char smem[];
@@ -94,6 +92,7 @@ __global__ void __launch_bounds__(1024) k_eval(const PairDev *__restrict__ pairs
   if (item >= n_items) return;
   const PoseDev pose = items[item];
   const PairDev &P = pairs[pose.pair];
+  const FrameDev &Fr = frames[pose.frame];
 
   const int T = blockDim.x, tid = threadIdx.x, lane = tid & 63, W = T >> 6;
   const int wid = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -132,11 +131,11 @@ __global__ void __launch_bounds__(1024) k_eval(const PairDev *__restrict__ pairs
   __syncthreads();
 
   const double cx = pose.c[0], cy = pose.c[1], cz = pose.c[2];
-  const double *fvx = P.fv + (int64_t)pose.frame * 3 * P.fstride;
-  const double *fvy = fvx + P.fstride;
-  const double *fvz = fvy + P.fstride;
-  const int ncx = P.ncx, ncy = P.ncy, gx = P.gx, gy = P.gy;
-  const uint32_t *off = P.foff + (int64_t)pose.frame * ((int64_t)ncx * ncy + 1);
+  const double *fvx = Fr.v;
+  const double *fvy = fvx + Fr.n;
+  const double *fvz = fvy + Fr.n;
+  const int ncx = Fr.ncx, ncy = Fr.ncy, gx = Fr.gx, gy = Fr.gy;
+  const uint32_t *off = Fr.off;
   const int alo0 = P.abox[0], alo1 = P.abox[1], alo2 = P.abox[2];
   const int ahi0 = P.abox[3], ahi1 = P.abox[4], ahi2 = P.abox[5];
   uint32_t *myhist = hist + (wid % cfg.hist_copies) * cfg.hist_words;
@@ -145,7 +144,7 @@ __global__ void __launch_bounds__(1024) k_eval(const PairDev *__restrict__ pairs
   const int BY = P.stripe_h, NS = P.n_stripes, Q = P.pieces, RM = BY + 2;
   const int kxb = P.kx_bits, kyb = P.ky_bits;
   const uint32_t kxm = (1u << kxb) - 1u, kym = (1u << kyb) - 1u;
-  const int G = cfg.plan_stripes;
+  const int G = P.plan_stripes;
   const int PE = RM * (Q + 1);  // plan entries per stripe
 
   int lo0 = nx, lo1 = ny, lo2 = nz, hi0 = -1, hi1 = -1, hi2 = -1;
@@ -545,23 +544,22 @@ __global__ void __launch_bounds__(1024) k_eval(const PairDev *__restrict__ pairs
 int32_t eval_hash_slot_bytes(bool zvar) { return 4 + (zvar ? 16 : 4) + 2; }
 
 size_t eval_lds_bytes(const EvalLaunch &c) {
-  return (size_t)eval_layout(c.waves, c.hist_copies, c.hist_words, c.plan_stripes,
-                             c.plan_entries, 1 << c.cap_log2, c.zvar)
+  return (size_t)eval_layout(c.waves, c.hist_copies, c.hist_words, c.plan_bytes, 1 << c.cap_log2,
+                             c.zvar)
       .total;
 }
 
 template <bool NEAR, bool ZVAR>
-static hipError_t launch_one(const PairDev *pairs_dev, const PoseDev *items_dev, int64_t n_items,
-                             const EvalLaunch &c, hipStream_t s) {
-  const Layout L = eval_layout(c.waves, c.hist_copies, c.hist_words, c.plan_stripes,
-                               c.plan_entries, 1 << c.cap_log2, c.zvar);
+static hipError_t launch_one(const PairDev *pairs_dev, const FrameDev *frames_dev,
+                             const PoseDev *items_dev, int64_t n_items, const EvalLaunch &c,
+                             hipStream_t s) {
+  const Layout L = eval_layout(c.waves, c.hist_copies, c.hist_words, c.plan_bytes,
+                               1 << c.cap_log2, c.zvar);
   EvalCfgDev d;
   d.hist_copies = c.hist_copies;
   d.hist_words = c.hist_words;
   d.cap_log2 = c.cap_log2;
   d.load_max = (1 << c.cap_log2) / 4;
-  d.plan_stripes = c.plan_stripes;
-  d.plan_entries = c.plan_entries;
   d.off_cnta = L.off_cnta;
   d.off_edges = L.off_edges;
   d.off_wave = L.off_wave;
@@ -574,19 +572,20 @@ static hipError_t launch_one(const PairDev *pairs_dev, const PoseDev *items_dev,
   hipError_t e = hipFuncSetAttribute((const void *)k_eval<NEAR, ZVAR>,
                                      hipFuncAttributeMaxDynamicSharedMemorySize, L.total);
   if (e != hipSuccess) return e;
-  k_eval<NEAR, ZVAR><<<(unsigned)grid, c.waves * 64, (size_t)L.total, s>>>(pairs_dev, items_dev,
-                                                                           n_items, per_xcd, d);
+  k_eval<NEAR, ZVAR><<<(unsigned)grid, c.waves * 64, (size_t)L.total, s>>>(
+      pairs_dev, frames_dev, items_dev, n_items, per_xcd, d);
   return hipGetLastError();
 }
 
-hipError_t launch_eval(const PairDev *pairs_dev, const PoseDev *items_dev, int64_t n_items,
-                       const EvalLaunch &c, hipStream_t s) {
+hipError_t launch_eval(const PairDev *pairs_dev, const FrameDev *frames_dev,
+                       const PoseDev *items_dev, int64_t n_items, const EvalLaunch &c,
+                       hipStream_t s) {
   if (n_items <= 0) return hipSuccess;
   if (c.near_face)
-    return c.zvar ? launch_one<true, true>(pairs_dev, items_dev, n_items, c, s)
-                  : launch_one<true, false>(pairs_dev, items_dev, n_items, c, s);
-  return c.zvar ? launch_one<false, true>(pairs_dev, items_dev, n_items, c, s)
-                : launch_one<false, false>(pairs_dev, items_dev, n_items, c, s);
+    return c.zvar ? launch_one<true, true>(pairs_dev, frames_dev, items_dev, n_items, c, s)
+                  : launch_one<true, false>(pairs_dev, frames_dev, items_dev, n_items, c, s);
+  return c.zvar ? launch_one<false, true>(pairs_dev, frames_dev, items_dev, n_items, c, s)
+                : launch_one<false, false>(pairs_dev, frames_dev, items_dev, n_items, c, s);
 }
 
 }  // namespace mi

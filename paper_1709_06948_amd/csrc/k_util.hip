@@ -76,23 +76,23 @@ hipError_t launch_count_nonfinite(const float *xyz, int64_t n, unsigned long lon
   return hipGetLastError();
 }
 
-// Writes the per-execution pointers (scan B, outputs) into the device tables,
-// so that an execution enqueues kernels only.
-__global__ void k_bind(PairDev *pairs, int32_t n_pairs, FrameDev *frames, int32_t n_frames,
-                       const float *xyz, double *mi_out, uint32_t *hist_out,
-                       mi_pose_stats *stats_out) {
-  for (int i = threadIdx.x; i < n_pairs; i += blockDim.x) {
-    pairs[i].mi_out = mi_out;
-    pairs[i].hist_out = hist_out;
-    pairs[i].stats_out = stats_out;
+// Writes the per-execution pointers (scan B, outputs) of the single pair of a
+// reusable plan into the device tables on the stream, so that an execution
+// enqueues kernels only and a captured graph picks up each execution's buffers.
+__global__ void k_bind(PairDev *pair, FrameDev *frames, int32_t n_frames, const float *xyz,
+                       double *mi_out, uint32_t *hist_out, mi_pose_stats *stats_out) {
+  if (threadIdx.x == 0) {
+    pair->mi_out = mi_out;
+    pair->hist_out = hist_out;
+    pair->stats_out = stats_out;
   }
   for (int i = threadIdx.x; i < n_frames; i += blockDim.x) frames[i].xyz = xyz;
 }
 
-hipError_t launch_bind(PairDev *pairs, int32_t n_pairs, FrameDev *frames, int32_t n_frames,
-                       const float *xyz, double *mi_out, uint32_t *hist_out,
-                       mi_pose_stats *stats_out, hipStream_t s) {
-  k_bind<<<1, 256, 0, s>>>(pairs, n_pairs, frames, n_frames, xyz, mi_out, hist_out, stats_out);
+hipError_t launch_bind(PairDev *pair, FrameDev *frames, int32_t n_frames, const float *xyz,
+                       double *mi_out, uint32_t *hist_out, mi_pose_stats *stats_out,
+                       hipStream_t s) {
+  k_bind<<<1, 256, 0, s>>>(pair, frames, n_frames, xyz, mi_out, hist_out, stats_out);
   return hipGetLastError();
 }
 

@@ -11,6 +11,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <memory>
 #include <mutex>
 #include <string>
 #include <unordered_map>
@@ -597,8 +598,9 @@ struct StripeShape {
   bool zvar;
 };
 
-bool choose_stripes(const GridInfo &gi, const Tuning &tu, StripeShape &S, const char **why) {
-  S.zvar = (gi.features & MI_FEAT_ZVAR) != 0;
+bool choose_stripes(const GridInfo &gi, const Tuning &tu, bool zvar, StripeShape &S,
+                    const char **why) {
+  S.zvar = zvar;
   const int slot = eval_hash_slot_bytes(S.zvar);
   int cl = 6;
   while (cl < 16 && ((int64_t)1 << (cl + 1)) * slot <= tu.hash_bytes) ++cl;
@@ -626,175 +628,306 @@ bool choose_stripes(const GridInfo &gi, const Tuning &tu, StripeShape &S, const 
 
 }  // namespace
 
-namespace {
-
-size_t frame_bytes(int64_t n_b, int64_t ncols) {
-  auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
-  return al((size_t)n_b * 3 * sizeof(double)) + al((size_t)(ncols + 1) * 4) + al((size_t)ncols * 4);
-}
-
-}  // namespace
+// One scan pair of a plan as the host keeps it.
+struct PairHost {
+  const mi_ref *ref;
+  const float *xyz;          // scan B (fixed at creation for batches, bound per execution else)
+  int64_t n_b, K;
+  double *mi_out;
+  int64_t *argmax_out;
+};
 
 struct mi_plan {
-  const mi_ref *ref;
-  int64_t n_b, K;
-  uint32_t flags;
-  int32_t F, F_chunk, n_chunks;
-  int64_t ncols;
-  std::vector<int64_t> chunk_items;  // [n_chunks + 1] over the frame-sorted items
+  bool bind_per_execution;           // single-pair plan: buffers given to mi_plan_execute
+  std::vector<PairHost> pairs;
+  int64_t n_items;
+  int32_t F;
+  std::vector<int32_t> chunk_frame;  // [n_chunks + 1] over the frame table
+  std::vector<int64_t> chunk_item;   // [n_chunks + 1] over the frame-sorted items
+  std::vector<int64_t> chunk_cur_words;
+  std::vector<int64_t> chunk_max_n;  // most points of a frame in the chunk
+  std::vector<int64_t> chunk_point_poses;
+  std::vector<uint32_t *> chunk_cur; // contiguous column cursors of each chunk's frames
   PoseDev *items_dev;
-  PairDev *pairs_dev;                // [n_chunks]
-  FrameDev *frames_dev;              // [F]
-  uint32_t *fcur;                    // cursor region of one chunk
-  unsigned long long *nonfinite;
+  PairDev *pairs_dev;
+  FrameDev *frames_dev;
+  unsigned long long *nonfinite;     // [pairs][2]
   EvalLaunch launch;
 };
 
 namespace {
 
-struct PlanLayout {
-  PoseDev *items;
-  PairDev *pairs;
-  FrameDev *frames;
-  double *fv;
-  uint32_t *foff, *fcur;
-  unsigned long long *nonfinite;
+size_t al256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+// Device bytes of one frame inside a chunk's storage: rotated points, column
+// offsets, and the frame's share of the chunk's contiguous cursor region.
+struct FrameBytes {
+  size_t v, off, cur;
+};
+FrameBytes frame_bytes(int64_t n_b, int64_t ncols) {
+  return {al256((size_t)std::max<int64_t>(n_b, 1) * 3 * sizeof(double)),
+          al256((size_t)(ncols + 1) * 4), (size_t)ncols * 4};
+}
+
+// Everything a plan needs before any device memory is touched: per-pair pose
+// tables and evaluator shapes, the launch, and the frame table order (pairs in
+// the caller's order, each pair's frames in first-use order).
+struct BatchTables {
+  std::vector<PoseTables> T;
+  std::vector<StripeShape> SS;
+  std::vector<int32_t> frame_base;   // [pairs + 1]
+  EvalLaunch L;
+  int64_t n_items = 0;
+  int32_t F = 0;
 };
 
-void plan_layout(int64_t K, int32_t F, int32_t F_chunk, int32_t n_chunks, int64_t n_b,
-                 int64_t ncols, Carver &c, PlanLayout *L) {
-  PoseDev *items = c.take<PoseDev>((size_t)std::max<int64_t>(K, 1));
-  PairDev *pairs = c.take<PairDev>((size_t)std::max(n_chunks, 1));
-  FrameDev *frames = c.take<FrameDev>((size_t)std::max(F, 1));
-  unsigned long long *nf = c.take<unsigned long long>(2);
-  const size_t nbp = (size_t)std::max<int64_t>(n_b, 1);
-  double *fv = c.take<double>((size_t)F_chunk * 3 * nbp);
-  uint32_t *foff = c.take<uint32_t>((size_t)F_chunk * (size_t)(ncols + 1));
-  uint32_t *fcur = c.take<uint32_t>((size_t)F_chunk * (size_t)ncols);
-  if (L) {
-    L->items = items; L->pairs = pairs; L->frames = frames; L->fv = fv;
-    L->foff = foff; L->fcur = fcur; L->nonfinite = nf;
-  }
-}
-
-int32_t chunk_frames(int32_t F, int64_t n_b, int64_t ncols, size_t budget) {
-  if (F <= 0) return 1;
-  if (budget == 0) budget = (size_t)4 << 30;
-  const size_t fb = frame_bytes(n_b, ncols);
-  int64_t fc = (int64_t)(budget / std::max<size_t>(fb, 1));
-  fc = std::max<int64_t>(1, std::min<int64_t>(fc, F));
-  return (int32_t)fc;
-}
-
-size_t plan_bytes(int64_t K, int32_t F, int64_t ncols, int64_t n_b, size_t budget) {
-  const int32_t fc = chunk_frames(F, n_b, ncols, budget);
-  const int32_t nch = F > 0 ? (F + fc - 1) / fc : 1;
-  Carver c(nullptr, 0);
-  plan_layout(K, F, fc, nch, n_b, ncols, c, nullptr);
-  return c.used() + 256;
-}
-
-}  // namespace
-
-extern "C" size_t mi_eval_poses_workspace(const mi_ref *r, int64_t n_b, const double *poses,
-                                          int64_t K, uint32_t, size_t budget) {
-  if (!r || K < 0 || n_b < 0 || (K > 0 && !poses)) return 0;
-  PoseTables T;
-  if (build_tables(r->g->gi, poses, K, T)) return 0;
-  return plan_bytes(K, T.F, (int64_t)T.ncx * T.ncy, n_b, budget);
-}
-
-extern "C" mi_status mi_plan_create(const mi_ref *r, int64_t n_b, const double *poses, int64_t K,
-                                    uint32_t flags, void *ws, size_t ws_bytes, size_t budget,
-                                    void *stream, mi_plan **out) {
-  if (!r || !out) return fail(MI_E_INVALID, "mi_plan_create: NULL argument");
-  *out = nullptr;
-  if (K < 0 || n_b < 0 || (K > 0 && !poses)) return fail(MI_E_INVALID, "bad pose set or scan B");
-  if (K >= ((int64_t)1 << 31)) return fail(MI_E_UNSUPPORTED, "more than 2^31 poses");
+mi_status prepare_batch(const mi_work_item *w, int64_t n, uint32_t flags, BatchTables &B) {
+  if (n < 0 || (n > 0 && !w)) return fail(MI_E_INVALID, "bad work item list");
+  if (n >= ((int64_t)1 << 20)) return fail(MI_E_UNSUPPORTED, "more than 2^20 work items");
   if (flags & ~(uint32_t)MI_EVAL_NEAR_FACE) return fail(MI_E_INVALID, "unknown flags");
-  const GridInfo &gi = r->g->gi;
-  if ((gi.features & MI_FEAT_ZVAR) && n_b >= MI_MAX_POINTS)
-    return fail(MI_E_UNSUPPORTED, "scan B has %lld >= 2^20 points with the z-variance feature",
-                (long long)n_b);
-  if (n_b >= ((int64_t)1 << 32)) return fail(MI_E_UNSUPPORTED, "scan B has >= 2^32 points");
-  if (!ws || ((uintptr_t)ws & 255)) return fail(MI_E_WORKSPACE, "workspace NULL or not 256-aligned");
-  PoseTables T;
-  const int bt = build_tables(gi, poses, K, T);
-  if (bt == -1) return fail(MI_E_INVALID, "non-finite pose");
-  if (bt) return fail(MI_E_UNSUPPORTED, "pose translations span too large a range");
-  const int64_t ncols = (int64_t)T.ncx * T.ncy;
-
+  bool zvar = false;
+  int hist_words = 1;
+  for (int64_t i = 0; i < n; ++i) {
+    const mi_work_item &it = w[i];
+    if (!it.ref) return fail(MI_E_INVALID, "work item %lld: NULL ref", (long long)i);
+    if (it.K < 0 || it.n_b < 0 || (it.K > 0 && !it.poses))
+      return fail(MI_E_INVALID, "work item %lld: bad pose set or scan B", (long long)i);
+    const GridInfo &gi = it.ref->g->gi;
+    zvar = zvar || (gi.features & MI_FEAT_ZVAR) != 0;
+    hist_words = std::max(hist_words, gi.nb[0] * gi.nb[0] + (gi.nf > 1 ? gi.nb[1] * gi.nb[1] : 0));
+  }
+  B.T.assign((size_t)n, PoseTables());
+  B.SS.assign((size_t)n, StripeShape());
+  B.frame_base.assign((size_t)n + 1, 0);
   const Tuning tu = tuning_now();
-  StripeShape SS;
-  const char *why = "";
-  if (!choose_stripes(gi, tu, SS, &why)) return fail(MI_E_UNSUPPORTED, "evaluator: %s", why);
-  EvalLaunch L;
+  int plan_bytes_max = 8;
+  for (int64_t i = 0; i < n; ++i) {
+    const mi_work_item &it = w[i];
+    const GridInfo &gi = it.ref->g->gi;
+    // the packed (n << 44 | S1) sums hold counts below 2^20
+    if (zvar && it.n_b >= MI_MAX_POINTS)
+      return fail(MI_E_UNSUPPORTED,
+                  "work item %lld: scan B has %lld >= 2^20 points with the z-variance feature",
+                  (long long)i, (long long)it.n_b);
+    if (it.n_b >= ((int64_t)1 << 32))
+      return fail(MI_E_UNSUPPORTED, "work item %lld: scan B has >= 2^32 points", (long long)i);
+    if (it.K >= ((int64_t)1 << 31))
+      return fail(MI_E_UNSUPPORTED, "work item %lld: more than 2^31 poses", (long long)i);
+    const int bt = build_tables(gi, it.poses, it.K, B.T[(size_t)i]);
+    if (bt == -1) return fail(MI_E_INVALID, "work item %lld: non-finite pose", (long long)i);
+    if (bt) return fail(MI_E_UNSUPPORTED, "work item %lld: pose translations span too large a range",
+                        (long long)i);
+    const char *why = "";
+    if (!choose_stripes(gi, tu, zvar, B.SS[(size_t)i], &why))
+      return fail(MI_E_UNSUPPORTED, "work item %lld: evaluator: %s", (long long)i, why);
+    const StripeShape &S = B.SS[(size_t)i];
+    plan_bytes_max = std::max(plan_bytes_max, S.plan_stripes * S.plan_entries * 8);
+    B.frame_base[(size_t)i + 1] = B.frame_base[(size_t)i] + B.T[(size_t)i].F;
+    B.n_items += it.K;
+  }
+  if (B.n_items >= ((int64_t)1 << 31)) return fail(MI_E_UNSUPPORTED, "more than 2^31 poses in all");
+  B.F = B.frame_base[(size_t)n];
+  EvalLaunch &L = B.L;
   L.waves = tu.waves;
-  L.cap_log2 = SS.cap_log2;
+  L.cap_log2 = n > 0 ? B.SS[0].cap_log2 : 6;
   L.hist_copies = tu.hist_copies;
-  L.hist_words = gi.nb[0] * gi.nb[0] + (gi.nf > 1 ? gi.nb[1] * gi.nb[1] : 0);
-  L.plan_stripes = SS.plan_stripes;
-  L.plan_entries = SS.plan_entries;
-  L.zvar = SS.zvar;
+  L.hist_words = hist_words;
+  L.plan_bytes = plan_bytes_max;
+  L.zvar = zvar;
   L.near_face = (flags & MI_EVAL_NEAR_FACE) != 0;
   if ((int64_t)eval_lds_bytes(L) > max_lds_per_block())
     return fail(MI_E_UNSUPPORTED, "tuning needs %zu LDS bytes per workgroup, device has %d",
                 eval_lds_bytes(L), max_lds_per_block());
+  return MI_OK;
+}
 
-  // Frames per chunk: from the budget when given, else as many as fit the
-  // workspace (all of them when it was sized by mi_eval_poses_workspace).
-  int32_t fc = chunk_frames(T.F, n_b, ncols, budget);
-  if (budget == 0 && T.F > 0) {
-    int32_t lo = 1, hi = T.F;
-    while (lo < hi) {
-      const int32_t mid = lo + (hi - lo + 1) / 2;
-      Carver probe(nullptr, 0);
-      plan_layout(K, T.F, mid, (T.F + mid - 1) / mid, n_b, ncols, probe, nullptr);
-      if (probe.used() + 256 <= ws_bytes) lo = mid; else hi = mid - 1;
+// Frames go into chunks greedily in table order, as many as fit the storage
+// budget (a frame larger than the budget gets a chunk of its own).
+struct ChunkPlan {
+  std::vector<int32_t> first;        // [chunks + 1]
+  size_t max_store = 0;
+};
+
+void plan_chunks(const BatchTables &B, const mi_work_item *w, size_t budget, ChunkPlan &C) {
+  C.first.assign(1, 0);
+  C.max_store = 0;
+  size_t v = 0, off = 0, cur = 0;
+  int32_t in_chunk = 0;
+  for (size_t p = 0; p < B.T.size(); ++p) {
+    const int64_t ncols = (int64_t)B.T[p].ncx * B.T[p].ncy;
+    const FrameBytes fb = frame_bytes(w[p].n_b, ncols);
+    for (int32_t f = 0; f < B.T[p].F; ++f) {
+      const size_t nv = v + fb.v, noff = off + fb.off, ncur = cur + fb.cur;
+      if (in_chunk > 0 && nv + noff + al256(ncur) > budget) {
+        C.max_store = std::max(C.max_store, v + off + al256(cur));
+        C.first.push_back(B.frame_base[p] + f);
+        v = fb.v; off = fb.off; cur = fb.cur;
+        in_chunk = 1;
+      } else {
+        v = nv; off = noff; cur = ncur;
+        ++in_chunk;
+      }
     }
-    fc = lo;
   }
-  const int32_t nch = T.F > 0 ? (T.F + fc - 1) / fc : 1;
+  C.max_store = std::max(C.max_store, v + off + al256(cur));
+  C.first.push_back(B.F);
+}
+
+struct PlanLayout {
+  PoseDev *items;
+  PairDev *pairs;
+  FrameDev *frames;
+  unsigned long long *nonfinite;
+  char *store;
+};
+
+void plan_fixed(const BatchTables &B, int64_t n_pairs, Carver &c, PlanLayout *L) {
+  PoseDev *items = c.take<PoseDev>((size_t)std::max<int64_t>(B.n_items, 1));
+  PairDev *pairs = c.take<PairDev>((size_t)std::max<int64_t>(n_pairs, 1));
+  FrameDev *frames = c.take<FrameDev>((size_t)std::max(B.F, 1));
+  unsigned long long *nf = c.take<unsigned long long>((size_t)std::max<int64_t>(2 * n_pairs, 2));
+  char *store = c.take<char>(0);
+  if (L) { L->items = items; L->pairs = pairs; L->frames = frames; L->nonfinite = nf; L->store = store; }
+}
+
+constexpr size_t kDefaultFrameBudget = (size_t)4 << 30;
+
+size_t batch_bytes(const BatchTables &B, const mi_work_item *w, int64_t n, size_t budget) {
+  Carver c(nullptr, 0);
+  plan_fixed(B, n, c, nullptr);
+  ChunkPlan C;
+  plan_chunks(B, w, budget ? budget : kDefaultFrameBudget, C);
+  return c.used() + C.max_store + 512;
+}
+
+// Workspace of a single-pair plan of K poses over F rotations whose column
+// grids have at most ncols columns (for callers that size before the poses
+// are known, such as the coarse-to-fine search).
+size_t single_plan_bytes(int64_t K, int32_t F, int64_t ncols, int64_t n_b) {
+  BatchTables B;
+  B.T.assign(1, PoseTables());
+  B.T[0].F = F;
+  B.T[0].ncx = (int32_t)std::min<int64_t>(ncols, 0x7fffffff);
+  B.T[0].ncy = 1;
+  B.frame_base = {0, F};
+  B.F = F;
+  B.n_items = K;
+  mi_work_item w;
+  memset(&w, 0, sizeof w);
+  w.n_b = n_b;
+  return batch_bytes(B, &w, 1, 0);
+}
+
+mi_status create_plan(const mi_work_item *w, int64_t n, uint32_t flags, void *ws, size_t ws_bytes,
+                      size_t budget, void *stream, bool bind_per_execution, mi_plan **out) {
+  if (!out) return fail(MI_E_INVALID, "NULL output handle");
+  *out = nullptr;
+  if (!ws || ((uintptr_t)ws & 255)) return fail(MI_E_WORKSPACE, "workspace NULL or not 256-aligned");
+  BatchTables B;
+  mi_status st = prepare_batch(w, n, flags, B);
+  if (st != MI_OK) return st;
   Carver c(ws, ws_bytes);
   PlanLayout PL;
-  plan_layout(K, T.F, fc, nch, n_b, ncols, c, &PL);
-  if (!c.fits())
-    return fail(MI_E_WORKSPACE, "eval workspace needs %zu bytes, got %zu", c.used() + 256,
-                ws_bytes);
+  plan_fixed(B, n, c, &PL);
+  if (!c.fits()) return fail(MI_E_WORKSPACE, "eval workspace too small for the pose tables");
+  // frame storage: the budget when given, else all that the workspace holds
+  const size_t room = ws_bytes - std::min(ws_bytes, c.used() + 256);
+  const size_t store_budget = budget ? std::min(budget, room) : room;
+  ChunkPlan C;
+  plan_chunks(B, w, store_budget, C);
+  if (B.F > 0 && C.max_store > room)
+    return fail(MI_E_WORKSPACE, "eval workspace needs %zu bytes, got %zu",
+                c.used() + C.max_store + 256, ws_bytes);
 
-  mi_plan *p = new (std::nothrow) mi_plan();
+  std::unique_ptr<mi_plan> p(new (std::nothrow) mi_plan());
   if (!p) return fail(MI_E_INVALID, "out of host memory");
-  p->ref = r;
-  p->n_b = n_b;
-  p->K = K;
-  p->flags = flags;
-  p->F = T.F;
-  p->F_chunk = fc;
-  p->n_chunks = nch;
-  p->ncols = ncols;
+  p->bind_per_execution = bind_per_execution;
+  p->n_items = B.n_items;
+  p->F = B.F;
+  p->launch = B.L;
   p->items_dev = PL.items;
   p->pairs_dev = PL.pairs;
   p->frames_dev = PL.frames;
-  p->fcur = PL.fcur;
   p->nonfinite = PL.nonfinite;
-  p->launch = L;
-  p->chunk_items.assign((size_t)nch + 1, K);
-  {
-    int64_t k = 0;
-    for (int32_t ch = 0; ch < nch; ++ch) {
-      p->chunk_items[(size_t)ch] = k;
-      const int32_t fend = std::min<int32_t>(T.F, (ch + 1) * fc);
-      while (k < K && T.items[(size_t)k].frame < fend) ++k;
-    }
-    p->chunk_items[(size_t)nch] = K;
-  }
-  for (auto &it : T.items) it.frame = it.frame % fc;
+  p->pairs.resize((size_t)n);
+  for (int64_t i = 0; i < n; ++i)
+    p->pairs[(size_t)i] = {w[i].ref, w[i].xyz_b, w[i].n_b, w[i].K, w[i].mi_out, w[i].argmax_out};
 
-  const RefDev &rd = r->rd;
-  const size_t nbp = (size_t)std::max<int64_t>(n_b, 1);
-  std::vector<PairDev> pairs((size_t)nch);
-  for (int32_t ch = 0; ch < nch; ++ch) {
-    PairDev &P = pairs[(size_t)ch];
+  // pose items: pairs in order, each pair's items sorted by frame
+  std::vector<PoseDev> items((size_t)B.n_items);
+  {
+    size_t k = 0;
+    for (int64_t i = 0; i < n; ++i)
+      for (const PoseDev &it : B.T[(size_t)i].items) {
+        PoseDev d = it;
+        d.pair = (int32_t)i;
+        d.frame = it.frame + B.frame_base[(size_t)i];
+        items[k++] = d;
+      }
+  }
+  // frame table with each frame's place in its chunk's storage
+  std::vector<FrameDev> frames((size_t)B.F);
+  const size_t n_chunks = C.first.size() - 1;
+  p->chunk_frame = C.first;
+  p->chunk_item.assign(n_chunks + 1, B.n_items);
+  p->chunk_cur_words.assign(n_chunks, 0);
+  p->chunk_max_n.assign(n_chunks, 0);
+  p->chunk_cur.assign(n_chunks, nullptr);
+  {
+    std::vector<int32_t> pair_of((size_t)B.F);
+    for (int64_t i = 0; i < n; ++i)
+      for (int32_t f = B.frame_base[(size_t)i]; f < B.frame_base[(size_t)i + 1]; ++f)
+        pair_of[(size_t)f] = (int32_t)i;
+    for (size_t ch = 0; ch < n_chunks; ++ch) {
+      const int32_t f0 = C.first[ch], f1 = C.first[ch + 1];
+      size_t v = 0, off = 0, cur = 0;
+      for (int32_t f = f0; f < f1; ++f) {
+        const size_t pi = (size_t)pair_of[(size_t)f];
+        const FrameBytes fb = frame_bytes(w[pi].n_b, (int64_t)B.T[pi].ncx * B.T[pi].ncy);
+        v += fb.v; off += fb.off; cur += fb.cur;
+      }
+      char *vbase = PL.store, *obase = PL.store + v;
+      uint32_t *cbase = (uint32_t *)(PL.store + v + off);
+      p->chunk_cur[ch] = cbase;
+      p->chunk_cur_words[ch] = (int64_t)(cur / 4);
+      for (int32_t f = f0; f < f1; ++f) {
+        const size_t pi = (size_t)pair_of[(size_t)f];
+        const PoseTables &T = B.T[pi];
+        const GridInfo &gi = w[pi].ref->g->gi;
+        const int64_t ncols = (int64_t)T.ncx * T.ncy;
+        const FrameBytes fb = frame_bytes(w[pi].n_b, ncols);
+        FrameDev &Fd = frames[(size_t)f];
+        memset(&Fd, 0, sizeof Fd);
+        memcpy(Fd.R, &T.R[(size_t)(f - B.frame_base[pi]) * 9], sizeof Fd.R);
+        Fd.s = gi.s;
+        Fd.xyz = w[pi].xyz_b;
+        Fd.n = w[pi].n_b;
+        Fd.gx = T.gx; Fd.gy = T.gy; Fd.ncx = T.ncx; Fd.ncy = T.ncy;
+        Fd.zlo = T.zlo; Fd.zhi = T.zhi;
+        Fd.v = (double *)vbase;
+        Fd.off = (uint32_t *)obase;
+        Fd.cur = cbase;
+        vbase += fb.v; obase += fb.off; cbase += ncols;
+        p->chunk_max_n[ch] = std::max(p->chunk_max_n[ch], w[pi].n_b);
+      }
+    }
+    int64_t k = 0;
+    p->chunk_point_poses.assign(n_chunks, 0);
+    for (size_t ch = 0; ch < n_chunks; ++ch) {
+      p->chunk_item[ch] = k;
+      while (k < B.n_items && items[(size_t)k].frame < C.first[ch + 1]) {
+        p->chunk_point_poses[ch] += w[items[(size_t)k].pair].n_b;
+        ++k;
+      }
+    }
+    p->chunk_item[n_chunks] = B.n_items;
+  }
+  std::vector<PairDev> pairs((size_t)n);
+  for (int64_t i = 0; i < n; ++i) {
+    const GridInfo &gi = w[i].ref->g->gi;
+    const RefDev &rd = w[i].ref->rd;
+    const StripeShape &S = B.SS[(size_t)i];
+    PairDev &P = pairs[(size_t)i];
     memset(&P, 0, sizeof P);
     P.nx = gi.dims[0]; P.ny = gi.dims[1]; P.nz = gi.dims[2]; P.nf = gi.nf;
     for (int f = 0; f < 2; ++f) {
@@ -805,84 +938,146 @@ extern "C" mi_status mi_plan_create(const mi_ref *r, int64_t n_b, const double *
     }
     P.voxel = gi.voxel;
     P.abox = rd.abox;
-    P.fv = PL.fv;
-    P.fstride = (int64_t)nbp;
-    P.foff = PL.foff;
-    P.gx = T.gx; P.gy = T.gy; P.ncx = T.ncx; P.ncy = T.ncy;
-    P.stripe_h = SS.stripe_h;
-    P.n_stripes = SS.n_stripes;
-    P.pieces = SS.pieces;
-    P.kx_bits = SS.kx_bits;
-    P.ky_bits = SS.ky_bits;
-    P.nonfinite = PL.nonfinite;
-    P.n_b = n_b;
-    P.K = K;
+    P.stripe_h = S.stripe_h;
+    P.n_stripes = S.n_stripes;
+    P.pieces = S.pieces;
+    P.kx_bits = S.kx_bits;
+    P.ky_bits = S.ky_bits;
+    P.plan_stripes = S.plan_stripes;
+    P.nonfinite = PL.nonfinite + 2 * i;
+    P.n_b = w[i].n_b;
+    P.mi_out = w[i].mi_out;
+    P.K = w[i].K;
+    P.hist_out = w[i].hist_out;
     P.hist_off[0] = 0;
-    P.hist_off[1] = K * (int64_t)gi.nb[0] * gi.nb[0];
+    P.hist_off[1] = w[i].K * (int64_t)gi.nb[0] * gi.nb[0];
+    P.stats_out = w[i].stats_out;
     memcpy(P.count_edges, gi.count_edges, sizeof P.count_edges);
     memcpy(P.zvar_edges, gi.zvar_edges, sizeof P.zvar_edges);
   }
-  std::vector<FrameDev> frames((size_t)T.F);
-  for (int32_t f = 0; f < T.F; ++f) {
-    FrameDev &Fd = frames[(size_t)f];
-    memset(&Fd, 0, sizeof Fd);
-    memcpy(Fd.R, &T.R[(size_t)f * 9], sizeof Fd.R);
-    Fd.s = gi.s;
-    Fd.n = n_b;
-    Fd.gx = T.gx; Fd.gy = T.gy; Fd.ncx = T.ncx; Fd.ncy = T.ncy;
-    Fd.zlo = T.zlo; Fd.zhi = T.zhi;
-    const size_t slot = (size_t)(f % fc);
-    Fd.v = PL.fv + slot * 3 * nbp;
-    Fd.off = PL.foff + slot * (size_t)(ncols + 1);
-    Fd.cur = PL.fcur + slot * (size_t)ncols;
-  }
-  const size_t b_items = sizeof(PoseDev) * (size_t)K, b_pairs = sizeof(PairDev) * pairs.size(),
+  const size_t b_items = sizeof(PoseDev) * items.size(), b_pairs = sizeof(PairDev) * pairs.size(),
                b_frames = sizeof(FrameDev) * frames.size();
   hipError_t e = hipSuccess;
-  Staging *st = staging_acquire(b_items + b_pairs + b_frames + 64, &e);
-  if (!st) { delete p; return dev_fail(e, "pinned staging"); }
-  char *h = (char *)st->p;
-  if (b_items) memcpy(h, T.items.data(), b_items);
-  memcpy(h + b_items, pairs.data(), b_pairs);
+  Staging *sg = staging_acquire(b_items + b_pairs + b_frames + 64, &e);
+  if (!sg) return dev_fail(e, "pinned staging");
+  char *h = (char *)sg->p;
+  if (b_items) memcpy(h, items.data(), b_items);
+  if (b_pairs) memcpy(h + b_items, pairs.data(), b_pairs);
   if (b_frames) memcpy(h + b_items + b_pairs, frames.data(), b_frames);
   const Upload ups[3] = {{PL.items, 0, b_items}, {PL.pairs, b_items, b_pairs},
                          {PL.frames, b_items + b_pairs, b_frames}};
-  e = staging_upload(st, ups, 3, (hipStream_t)stream);
-  if (e != hipSuccess) { delete p; return dev_fail(e, "pose table upload"); }
-  *out = p;
+  e = staging_upload(sg, ups, 3, (hipStream_t)stream);
+  if (e != hipSuccess) return dev_fail(e, "pose table upload");
+  *out = p.release();
   return MI_OK;
+}
+
+// Enqueue one execution: non-finite counts, then per chunk the frames and one
+// evaluator launch over the chunk's poses, then the argmax of each pair.
+mi_status run_plan(mi_plan *p, hipStream_t s) {
+  for (size_t i = 0; i < p->pairs.size(); ++i)
+    HIP_TRY(launch_count_nonfinite(p->pairs[i].xyz, p->pairs[i].n_b, p->nonfinite + 2 * i, s),
+            "count non-finite");
+  const size_t n_chunks = p->chunk_frame.size() - 1;
+  for (size_t ch = 0; ch < n_chunks; ++ch) {
+    const int32_t f0 = p->chunk_frame[ch], nfr = p->chunk_frame[ch + 1] - f0;
+    if (nfr > 0) {
+      hipEvent_t a = nullptr;
+      const bool timed = prof_begin(s, &a);
+      HIP_TRY(launch_fill_u32(p->chunk_cur[ch], 0u, p->chunk_cur_words[ch], s),
+              "clear column counts");
+      HIP_TRY(launch_frames(p->frames_dev + f0, nfr, p->chunk_max_n[ch], 0, s), "frames");
+      if (timed) prof_end(s, a, kStageFrames, 0, 0);
+    }
+    const int64_t i0 = p->chunk_item[ch], i1 = p->chunk_item[ch + 1];
+    if (i1 > i0) {
+      hipEvent_t a = nullptr;
+      const bool timed = prof_begin(s, &a);
+      HIP_TRY(launch_eval(p->pairs_dev, p->frames_dev, p->items_dev + i0, i1 - i0, p->launch, s),
+              "eval");
+      if (timed) prof_end(s, a, kStageEval, i1 - i0, p->chunk_point_poses[ch]);
+    }
+  }
+  for (const PairHost &ph : p->pairs)
+    if (ph.argmax_out && ph.K > 0)
+      HIP_TRY(launch_argmax(ph.mi_out, ph.K, ph.ref->g->gi.nf, ph.argmax_out, nullptr, s),
+              "argmax");
+  return MI_OK;
+}
+
+}  // namespace
+
+extern "C" size_t mi_batch_workspace(const mi_work_item *items, int64_t n_items, uint32_t flags,
+                                     size_t budget) {
+  BatchTables B;
+  if (prepare_batch(items, n_items, flags, B) != MI_OK) return 0;
+  return batch_bytes(B, items, n_items, budget);
+}
+
+extern "C" mi_status mi_batch_create(const mi_work_item *items, int64_t n_items, uint32_t flags,
+                                     void *ws, size_t ws_bytes, size_t budget, void *stream,
+                                     mi_plan **out) {
+  for (int64_t i = 0; i < n_items && items; ++i) {
+    if (items[i].K > 0 && !items[i].mi_out)
+      return fail(MI_E_INVALID, "work item %lld: mi_out is NULL", (long long)i);
+    if (items[i].n_b > 0 && !items[i].xyz_b)
+      return fail(MI_E_INVALID, "work item %lld: xyz_b is NULL", (long long)i);
+  }
+  return create_plan(items, n_items, flags, ws, ws_bytes, budget, stream, false, out);
+}
+
+extern "C" mi_status mi_batch_execute(mi_plan *p, void *stream) {
+  if (!p) return fail(MI_E_INVALID, "mi_batch_execute: NULL plan");
+  if (p->bind_per_execution)
+    return fail(MI_E_INVALID, "plan from mi_plan_create: execute it with mi_plan_execute");
+  return run_plan(p, (hipStream_t)stream);
+}
+
+extern "C" mi_status mi_eval_batch(const mi_work_item *items, int64_t n_items, uint32_t flags,
+                                   void *ws, size_t ws_bytes, void *stream) {
+  mi_plan *p = nullptr;
+  mi_status st = mi_batch_create(items, n_items, flags, ws, ws_bytes, 0, stream, &p);
+  if (st != MI_OK) return st;
+  st = run_plan(p, (hipStream_t)stream);
+  mi_plan_destroy(p);
+  return st;
+}
+
+extern "C" size_t mi_eval_poses_workspace(const mi_ref *r, int64_t n_b, const double *poses,
+                                          int64_t K, uint32_t flags, size_t budget) {
+  if (!r) return 0;
+  mi_work_item w;
+  memset(&w, 0, sizeof w);
+  w.ref = r; w.n_b = n_b; w.poses = poses; w.K = K;
+  return mi_batch_workspace(&w, 1, flags, budget);
+}
+
+extern "C" mi_status mi_plan_create(const mi_ref *r, int64_t n_b, const double *poses, int64_t K,
+                                    uint32_t flags, void *ws, size_t ws_bytes, size_t budget,
+                                    void *stream, mi_plan **out) {
+  if (!r || !out) return fail(MI_E_INVALID, "mi_plan_create: NULL argument");
+  *out = nullptr;
+  mi_work_item w;
+  memset(&w, 0, sizeof w);
+  w.ref = r; w.n_b = n_b; w.poses = poses; w.K = K;
+  return create_plan(&w, 1, flags, ws, ws_bytes, budget, stream, true, out);
 }
 
 extern "C" mi_status mi_plan_execute(mi_plan *p, const float *xyz_b, double *mi_out,
                                      int64_t *argmax_out, uint32_t *hist_out,
                                      mi_pose_stats *stats_out, void *stream) {
   if (!p) return fail(MI_E_INVALID, "mi_plan_execute: NULL plan");
-  if (p->K > 0 && !mi_out) return fail(MI_E_INVALID, "mi_out is NULL");
-  if (p->n_b > 0 && !xyz_b) return fail(MI_E_INVALID, "xyz_b is NULL");
+  if (!p->bind_per_execution) return fail(MI_E_INVALID, "batch plan: execute it with mi_batch_execute");
+  PairHost &ph = p->pairs[0];
+  if (ph.K > 0 && !mi_out) return fail(MI_E_INVALID, "mi_out is NULL");
+  if (ph.n_b > 0 && !xyz_b) return fail(MI_E_INVALID, "xyz_b is NULL");
   hipStream_t s = (hipStream_t)stream;
-  HIP_TRY(launch_bind(p->pairs_dev, p->n_chunks, p->frames_dev, p->F, xyz_b, mi_out, hist_out,
-                      stats_out, s), "bind");
-  HIP_TRY(launch_count_nonfinite(xyz_b, p->n_b, p->nonfinite, s), "count non-finite");
-  for (int32_t ch = 0; ch < p->n_chunks; ++ch) {
-    const int32_t f0 = ch * p->F_chunk;
-    const int32_t nfr = std::min(p->F_chunk, p->F - f0);
-    if (nfr > 0) {
-      hipEvent_t a = nullptr;
-      const bool timed = prof_begin(s, &a);
-      HIP_TRY(launch_fill_u32(p->fcur, 0u, (int64_t)nfr * p->ncols, s), "clear column counts");
-      HIP_TRY(launch_frames(p->frames_dev + f0, nfr, p->n_b, (int32_t)std::min<int64_t>(
-                            p->ncols, 0x7fffffff), s), "frames");
-      if (timed) prof_end(s, a, kStageFrames, 0, 0);
-    }
-    const int64_t i0 = p->chunk_items[(size_t)ch], i1 = p->chunk_items[(size_t)ch + 1];
-    hipEvent_t a = nullptr;
-    const bool timed = prof_begin(s, &a);
-    HIP_TRY(launch_eval(p->pairs_dev + ch, p->items_dev + i0, i1 - i0, p->launch, s), "eval");
-    if (timed) prof_end(s, a, kStageEval, i1 - i0, (i1 - i0) * p->n_b);
-  }
-  if (argmax_out && p->K > 0)
-    HIP_TRY(launch_argmax(mi_out, p->K, p->ref->g->gi.nf, argmax_out, nullptr, s), "argmax");
-  return MI_OK;
+  HIP_TRY(launch_bind(p->pairs_dev, p->frames_dev, p->F, xyz_b, mi_out, hist_out, stats_out, s),
+          "bind");
+  ph.xyz = xyz_b;
+  ph.mi_out = mi_out;
+  ph.argmax_out = argmax_out;
+  return run_plan(p, s);
 }
 
 extern "C" void mi_plan_destroy(mi_plan *p) { delete p; }
@@ -1054,7 +1249,7 @@ extern "C" size_t mi_align_workspace(const mi_ref *r, int64_t n_b, const mi_c2f_
   Carver c(nullptr, 0);
   c.take<double>((size_t)gi.nf * (size_t)K);
   c.take<int64_t>(2 * 8);
-  return c.used() + plan_bytes(K, (int32_t)F, ncols, n_b, 0) + 512;
+  return c.used() + single_plan_bytes(K, (int32_t)F, ncols, n_b) + 512;
 }
 
 extern "C" mi_status mi_align_coarse_to_fine(const mi_ref *r, const float *xyz_b, int64_t n_b,

@@ -74,7 +74,7 @@ hipError_t launch_frames(const FrameDev *frames_dev, int32_t n_frames, int64_t m
 
 // --------------------------------------------------------------------- eval
 
-// One scan pair (A resident, B bucketed) for one chunk of frames.
+// One scan pair of an evaluation batch: A resident, B bucketed into frames.
 struct PairDev {
   int32_t nx, ny, nz, nf;
   uint32_t kind[2];
@@ -83,15 +83,11 @@ struct PairDev {
   const uint8_t *binA[2];
   const uint32_t *sat[2];
   const int32_t *abox;
-  const double *fv;          // frame f of this chunk at fv + f * 3 * fstride
-  int64_t fstride;
-  const uint32_t *foff;      // frame f at foff + f * (ncols + 1)
-  int32_t gx, gy, ncx, ncy;
   int32_t stripe_h;          // voxel rows per stripe (bricks are pieces of stripes)
   int32_t n_stripes;
   int32_t pieces;            // x pieces per stripe in the plan
   int32_t kx_bits, ky_bits;  // hash key: iz << (kx+ky) | (iy - stripe y0) << kx | ix
-  int32_t pad0;
+  int32_t plan_stripes;      // stripes whose candidate rows are planned per round
   const unsigned long long *nonfinite; // device counter
   int64_t n_b;
   double *mi_out;
@@ -104,9 +100,9 @@ struct PairDev {
 };
 
 struct PoseDev {
-  int32_t pair;
-  int32_t frame;             // frame index within the chunk
-  int32_t out_index;         // pose index in the caller's order
+  int32_t pair;              // index into the batch's pairs
+  int32_t frame;             // index into the batch's frame table
+  int32_t out_index;         // pose index in the caller's order within its pair
   int32_t pad;
   double c[3];               // fl(fl(t - origin) * s)
 };
@@ -117,14 +113,14 @@ struct EvalLaunch {
   int32_t cap_log2;          // LDS voxel-hash slots = 1 << cap_log2
   int32_t hist_copies;       // privatized joint-histogram copies
   int32_t hist_words;        // max over pairs of sum_f nb_f^2
-  int32_t plan_stripes;      // stripes planned per round
-  int32_t plan_entries;      // max rows * (pieces + 1) per stripe over pairs
+  int32_t plan_bytes;        // max over pairs of plan_stripes * rows * (pieces + 1) * 8
   bool zvar;                 // 16-byte voxel sums (else 4-byte counts)
   bool near_face;
 };
 
-hipError_t launch_eval(const PairDev *pairs_dev, const PoseDev *items_dev, int64_t n_items,
-                       const EvalLaunch &cfg, hipStream_t s);
+hipError_t launch_eval(const PairDev *pairs_dev, const FrameDev *frames_dev,
+                       const PoseDev *items_dev, int64_t n_items, const EvalLaunch &cfg,
+                       hipStream_t s);
 size_t eval_lds_bytes(const EvalLaunch &cfg);
 int32_t eval_hash_slot_bytes(bool zvar);
 
@@ -161,9 +157,9 @@ hipError_t launch_plain_clear_dense(const PlainDev &pd, hipStream_t s);
 hipError_t launch_fill_u32(uint32_t *p, uint32_t value, int64_t n, hipStream_t s);
 hipError_t launch_argmax(const double *mi, int64_t K, int32_t nf, int64_t *out, double *out_val,
                          hipStream_t s);
-hipError_t launch_bind(PairDev *pairs, int32_t n_pairs, FrameDev *frames, int32_t n_frames,
-                       const float *xyz, double *mi_out, uint32_t *hist_out,
-                       mi_pose_stats *stats_out, hipStream_t s);
+hipError_t launch_bind(PairDev *pair, FrameDev *frames, int32_t n_frames, const float *xyz,
+                       double *mi_out, uint32_t *hist_out, mi_pose_stats *stats_out,
+                       hipStream_t s);
 hipError_t launch_count_nonfinite(const float *xyz, int64_t n, unsigned long long *out,
                                   hipStream_t s);
 

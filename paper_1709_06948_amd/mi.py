@@ -51,6 +51,12 @@ class _Profile(C.Structure):
                 ("plain_poses", C.c_int64), ("poses", C.c_int64), ("point_poses", C.c_int64)]
 
 
+class _WorkItem(C.Structure):
+    _fields_ = [("ref", C.c_void_p), ("xyz_b", C.c_void_p), ("n_b", C.c_int64),
+                ("poses", C.POINTER(C.c_double)), ("K", C.c_int64), ("mi_out", C.c_void_p),
+                ("argmax_out", C.c_void_p), ("hist_out", C.c_void_p), ("stats_out", C.c_void_p)]
+
+
 class _Tuning(C.Structure):
     _fields_ = [("waves", C.c_int32), ("hash_bytes", C.c_int32), ("hist_copies", C.c_int32),
                 ("stripe_rows", C.c_int32)]
@@ -86,6 +92,10 @@ def _load():
         "mi_plan_create": ([vp, i64, dp, i64, u32, vp, sz, sz, vp, C.POINTER(vp)], st),
         "mi_plan_execute": ([vp, vp, vp, vp, vp, vp, vp], st),
         "mi_plan_destroy": ([vp], None),
+        "mi_batch_workspace": ([C.POINTER(_WorkItem), i64, u32, sz], sz),
+        "mi_batch_create": ([C.POINTER(_WorkItem), i64, u32, vp, sz, sz, vp, C.POINTER(vp)], st),
+        "mi_batch_execute": ([vp, vp], st),
+        "mi_eval_batch": ([C.POINTER(_WorkItem), i64, u32, vp, sz, vp], st),
         "mi_align_workspace": ([vp, i64, C.POINTER(_C2F)], sz),
         "mi_align_coarse_to_fine": ([vp, vp, i64, dp, C.POINTER(_C2F), dp, dp, vp, sz, vp], st),
     }
@@ -103,6 +113,7 @@ EXPORTED = ("mi_status_str", "mi_last_error", "mi_tuning_set", "mi_tuning_get",
             "mi_features_ref", "mi_ref_destroy", "mi_ref_bins", "mi_ref_summary",
             "mi_eval_poses_workspace", "mi_eval_poses", "mi_eval_poses_plain_workspace",
             "mi_eval_poses_plain", "mi_plan_create", "mi_plan_execute", "mi_plan_destroy",
+            "mi_batch_workspace", "mi_batch_create", "mi_batch_execute", "mi_eval_batch",
             "mi_align_workspace", "mi_align_coarse_to_fine")
 
 
@@ -371,6 +382,73 @@ class Plan:
         if getattr(self, "_h", None) and _lib is not None:
             _lib.mi_plan_destroy(self._h)
             self._h = None
+
+
+class WorkItem:
+    """One scan pair and pose set of a batch, with its device outputs."""
+
+    def __init__(self, ref: Ref, xyz_b, poses, want_hist=False, want_stats=False,
+                 want_argmax=True):
+        self.ref = ref
+        self.xyz_b = _dev_points(xyz_b)
+        self.poses = _poses(poses)
+        self.K = self.poses.shape[0]
+        self.mi, self.argmax, self.hist_raw, self.stats_raw = _outputs(
+            ref.grid, self.K, want_hist, want_stats, want_argmax)
+
+    def _c(self) -> _WorkItem:
+        return _WorkItem(self.ref._h, _dptr(self.xyz_b), self.xyz_b.shape[1],
+                         self.poses.ctypes.data_as(C.POINTER(C.c_double)), self.K,
+                         _dptr(self.mi), _dptr(self.argmax), _dptr(self.hist_raw),
+                         _dptr(self.stats_raw))
+
+    def results(self) -> dict:
+        return _unpack(self.ref.grid, self.K, self.mi, self.argmax, self.hist_raw, self.stats_raw)
+
+
+def _items_array(items):
+    arr = (_WorkItem * max(len(items), 1))()
+    for i, it in enumerate(items):
+        arr[i] = it._c()
+    return arr
+
+
+class Batch:
+    """mi_batch_*: the poses of many scan pairs in one schedule; execute()
+    only launches kernels (capturable in a HIP graph)."""
+
+    def __init__(self, items, flags=0, stream=None, frame_budget=0):
+        self.items = list(items)
+        arr = _items_array(self.items)
+        nbytes = _lib.mi_batch_workspace(arr, len(self.items), flags, frame_budget)
+        if nbytes == 0:
+            raise MIError(MI_E_INVALID, "mi_batch_workspace", _lib.mi_last_error().decode())
+        self.ws = _workspace(nbytes)
+        h = C.c_void_p()
+        _check(_lib.mi_batch_create(arr, len(self.items), flags, _dptr(self.ws), self.ws.numel(),
+                                    frame_budget, _stream(stream), C.byref(h)), "mi_batch_create")
+        self._h = h
+
+    def execute(self, stream=None):
+        _check(_lib.mi_batch_execute(self._h, _stream(stream)), "mi_batch_execute")
+
+    def __del__(self):
+        if getattr(self, "_h", None) and _lib is not None:
+            _lib.mi_plan_destroy(self._h)
+            self._h = None
+
+
+def eval_batch(items, flags=0, stream=None):
+    """mi_eval_batch: create, execute and release a batch in one call."""
+    items = list(items)
+    arr = _items_array(items)
+    nbytes = _lib.mi_batch_workspace(arr, len(items), flags, 0)
+    if nbytes == 0:
+        raise MIError(MI_E_INVALID, "mi_batch_workspace", _lib.mi_last_error().decode())
+    ws = _workspace(nbytes)
+    _check(_lib.mi_eval_batch(arr, len(items), flags, _dptr(ws), ws.numel(), _stream(stream)),
+           "mi_eval_batch")
+    return ws
 
 
 def align_coarse_to_fine(ref: Ref, xyz_b, init, half_range, samples, levels, shrink,
