@@ -1,14 +1,25 @@
 """Benchmark of the MI scan-alignment hot path on one MI355X.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+                    [--workload c2f|batched|uneven] [--pairs N] [--calibrate-copy]
 
-Workload (one step): a full 6-DOF coarse-to-fine alignment of a realistic
-scan pair -- two synthetic 64-ring spinning-scanner scans (~115k points each)
-of a 160 x 160 m urban scene, 0.5 m voxels over 320 x 320 x 20, point-count and
-z-variance features at 32 bins each -- i.e. scan A's resident feature map,
-then 3 levels of 5^6 = 15,625 candidate poses (46,875 MI evaluations), each
-level one batched launch plus the argmax read back.  Inputs are resident in
-HBM before the timed region.
+Default workload (one step): a full 6-DOF coarse-to-fine alignment of a
+realistic scan pair -- two synthetic 64-ring spinning-scanner scans (~115k
+points each) of a 160 x 160 m urban scene, 0.5 m voxels over 320 x 320 x 20,
+point-count and z-variance features at 32 bins each -- i.e. scan A's resident
+feature map, then 3 levels of 5^6 = 15,625 candidate poses (46,875 MI
+evaluations), each level one batched launch plus the argmax read back.
+Inputs are resident in HBM before the timed region.
+
+Other workloads (same JSON line, their own config):
+  batched  the tiny scan pair (~20k / ~14k points, 1 m voxels, 64 x 64 x 10,
+           point count at 32 bins) with 8^6 = 262,144 candidate poses in one
+           batch, replayed as one captured HIP graph per step;
+  uneven   N surface-sampled pairs (points log-uniform in 10k-300k, voxels
+           0.25 / 0.5 / 1 m, count + z-variance at 32 bins) with 4096 random
+           poses each, all in one batch per step.
+--calibrate-copy runs a plain 1 GiB device copy, the reference kernel that
+scales the HBM byte counters of a profile.
 
 Prints one JSON line: MI pose evals/s (value), Gpoint-transforms/s, the
 roofline of the dominant kernel (the batched evaluator, timed with HIP events
@@ -45,7 +56,48 @@ def _args():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--plain-sample", type=int, default=96)
     ap.add_argument("--cpu-sample", type=int, default=2048)
+    ap.add_argument("--workload", choices=("c2f", "batched", "uneven"), default="c2f")
+    ap.add_argument("--pairs", type=int, default=64)
+    ap.add_argument("--calibrate-copy", action="store_true")
     return ap.parse_args()
+
+
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_eval_urban_c2f_traffic.md")
+EVAL_SOURCE = os.path.join(ROOT, "paper_1709_06948_amd", "csrc", "k_eval.hip")
+
+
+def _measured_traffic():
+    """HBM bytes per evaluator launch from the committed counter profile, or
+    None when the kernel source has changed since the counters were taken."""
+    import hashlib
+    try:
+        text = open(TRAFFIC_FILE).read()
+        src = hashlib.sha256(open(EVAL_SOURCE, "rb").read()).hexdigest()
+    except OSError:
+        return None
+    vals = {}
+    for line in text.splitlines():
+        if line.startswith("- ") and ":" in line:
+            k, v = line[2:].split(":", 1)
+            vals[k.strip()] = v.strip().strip("`")
+    if vals.get("k_eval.hip sha256") != src:
+        return None
+    try:
+        return float(vals["HBM bytes per launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def _calibrate_copy():
+    import torch
+    n = 1 << 28  # 1 GiB of float32
+    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_read": 4 * n, "copy_bytes_written": 4 * n, "dispatches": 3}),
+          flush=True)
 
 
 def main():
@@ -55,6 +107,11 @@ def main():
                                    "sharded over several GPUs",
                           "n_gpus": a.gpus}), flush=True)
         sys.exit(2)
+    if a.calibrate_copy:
+        _calibrate_copy()
+        return
+    if a.workload != "c2f":
+        return _bench_batch(a)
     import torch
 
     from paper_1709_06948_amd import mi, synth
@@ -100,7 +157,8 @@ def main():
     pp_per_launch = prof["point_poses"] / max(prof["eval_launches"], 1)
     achieved = OPS_PER_POINT_POSE * pp_per_launch / (eval_ms_avg * 1e-3)
     roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP64_OPS / 1e12,
-                "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_OPS, "traffic": None,
+                "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_OPS,
+                "traffic": _measured_traffic(),
                 "kernel": "k_eval", "avg_launch_ms": eval_ms_avg,
                 "point_poses_per_launch": pp_per_launch,
                 "frames_ms_per_step": prof["frames_ms"] / a.steps,
@@ -163,6 +221,81 @@ def main():
         "cpu_baseline": cpu,
         "result": {"pose": [float(v) for v in pose], "mi": best,
                    "abs_err_vs_truth": [float(v) for v in err]},
+    }
+    print(json.dumps(out), flush=True)
+
+
+def _bench_batch(a):
+    """Batched (8^6 poses, one graph) and uneven-batch workloads."""
+    import torch
+
+    from paper_1709_06948_amd import mi, synth
+
+    torch.cuda.set_device(0)
+    if a.workload == "batched":
+        pair = synth.tiny_pair()
+        grid = mi.Grid(pair.origin, pair.dims, pair.voxel, features=mi.FEAT_COUNT, nb_count=32)
+        items = [mi.WorkItem(mi.Ref(grid, pair.A), pair.B, synth.grid8_poses(8))]
+        workload = ("tiny scan pair, 8^6 = 262,144 6-DOF poses in one batch (one captured HIP "
+                    "graph per step): ~20k / ~14k surface points, 1 m voxels 64x64x10, count 32 "
+                    "bins")
+    else:
+        work = synth.uneven_batch(n_pairs=a.pairs)
+        items = []
+        for pair, poses in work:
+            grid = mi.Grid(pair.origin, pair.dims, pair.voxel,
+                           features=mi.FEAT_COUNT | mi.FEAT_ZVAR, nb_count=32, nb_zvar=32)
+            items.append(mi.WorkItem(mi.Ref(grid, pair.A), pair.B, poses))
+        workload = (f"uneven batch: {a.pairs} surface-sampled pairs, points log-uniform in "
+                    "10k-300k, voxels 0.25/0.5/1 m (grids up to 640x640x40), count + z-variance "
+                    "32 bins, 4096 random 6-DOF poses per pair, one batch per step")
+    torch.cuda.synchronize()
+    batch = mi.Batch(items)
+    K = sum(it.K for it in items)
+    point_poses = sum(it.K * it.xyz_b.shape[1] for it in items)
+    graph = None
+    if a.workload == "batched":
+        s = torch.cuda.Stream()
+        s.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(s):
+            batch.execute(stream=s)
+        torch.cuda.current_stream().wait_stream(s)
+        torch.cuda.synchronize()
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph):
+            batch.execute()
+    run = graph.replay if graph is not None else batch.execute
+    for _ in range(a.warmup):
+        run()
+    torch.cuda.synchronize()
+    # stage events cannot sit inside a graph: time the stages on an eager run
+    mi.profile_enable(True)
+    batch.execute()
+    torch.cuda.synchronize()
+    prof = mi.profile_read()
+    mi.profile_enable(False)
+    t0 = time.perf_counter()
+    for _ in range(a.steps):
+        run()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    value = K * a.steps / dt
+    eval_ms_avg = prof["eval_ms"] / max(prof["eval_launches"], 1)
+    pp_per_launch = prof["point_poses"] / max(prof["eval_launches"], 1)
+    achieved = OPS_PER_POINT_POSE * pp_per_launch / (eval_ms_avg * 1e-3)
+    out = {
+        "metric": "MI pose evals/s", "value": value, "unit": "evals/s", "n_gpus": 1,
+        "steps": a.steps, "warmup": a.warmup, "ms_per_step": dt * 1e3 / a.steps,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": workload, "evals_per_step": K, "pairs": len(items)},
+        "gpoint_transforms_per_s": point_poses * a.steps / dt / 1e9,
+        "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP64_OPS / 1e12,
+                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_OPS, "traffic": None,
+                     "kernel": "k_eval", "avg_launch_ms": eval_ms_avg,
+                     "eval_launches_per_step": prof["eval_launches"],
+                     "frames_ms_per_step": prof["frames_ms"], "eval_ms_per_step": prof["eval_ms"]},
+        "cpu_baseline": None,
     }
     print(json.dumps(out), flush=True)
 
