@@ -288,6 +288,71 @@ mi_status mi_align_coarse_to_fine(const mi_ref *r, const float *xyz_b, int64_t n
                                   const double init[6], const mi_c2f_desc *d, double pose_out[6],
                                   double *mi_out, void *ws, size_t ws_bytes, void *stream);
 
+/* ------------------------------------------------------------ serving */
+
+/* A request loop for many alignments (Alg. 1 per request, with the search of
+ * mi_align_coarse_to_fine): continuous batching over one device arena.
+ *
+ * The caller hands the server one device range (`arena`, 256-aligned; the
+ * server never allocates device memory) and a slot count.  Requests are
+ * queued by mi_server_submit, which copies the host scans, so the caller may
+ * free them at once.  Each mi_server_step admits queued requests in arrival
+ * order while a slot is free and the request's data (scan B, scan A while its
+ * reference is built, the reference features) fits the arena outside the
+ * step region.  It then evaluates one search level of every active request
+ * in one batch (mi_batch_*) and reads back the argmaxes.  A request whose
+ * last level is done gives back its memory and slot.  Requests admitted
+ * later join at their first level, so levels of different requests share
+ * launches.  A request's result equals mi_align_coarse_to_fine on the same
+ * inputs, bit for bit, whatever else is in flight.
+ *
+ * step_bytes is the part of the arena kept for each step's batch (0 = a
+ * quarter): pose tables, outputs and rotated frames (chunked to fit).
+ * mi_server_submit fails with MI_E_UNSUPPORTED for a request whose data
+ * could never fit.  mi_server_submit and mi_server_poll may be called from
+ * other threads while a step runs; steps are not reentrant.  Times are
+ * seconds on a monotonic clock since the server was created. */
+typedef struct mi_server mi_server;
+
+typedef struct mi_server_desc {
+  void *arena;          /* device memory owned by the caller */
+  size_t arena_bytes;
+  size_t step_bytes;    /* 0 = arena_bytes / 4 */
+  int32_t max_active;   /* slots: requests in flight at once, >= 1 */
+} mi_server_desc;
+
+typedef struct mi_request {
+  mi_grid_desc grid;    /* edges, if given, are copied */
+  const float *xyz_a;   /* host SoA [3][n_a] */
+  int64_t n_a;
+  const float *xyz_b;   /* host SoA [3][n_b] */
+  int64_t n_b;
+  double init[6];       /* T_o */
+  mi_c2f_desc search;
+} mi_request;
+
+#define MI_REQ_QUEUED 0
+#define MI_REQ_ACTIVE 1
+#define MI_REQ_DONE 2
+#define MI_REQ_FAILED 3
+
+typedef struct mi_request_state {
+  int32_t state;        /* MI_REQ_* */
+  int32_t levels_done;
+  mi_status status;     /* MI_OK, or why the request failed */
+  int32_t pad;
+  double pose[6];       /* best pose after the last level */
+  double mi;            /* its MI (feature slot of the search) */
+  double t_submit, t_admit, t_done;
+} mi_request_state;
+
+mi_status mi_server_create(const mi_server_desc *d, void *stream, mi_server **out);
+mi_status mi_server_submit(mi_server *s, const mi_request *r, int64_t *id);
+mi_status mi_server_step(mi_server *s, int32_t *n_active, int32_t *n_queued);
+mi_status mi_server_poll(mi_server *s, int64_t id, mi_request_state *out);
+mi_status mi_server_release(mi_server *s, int64_t id); /* forget a finished request */
+void mi_server_destroy(mi_server *s);
+
 #ifdef __cplusplus
 }
 #endif

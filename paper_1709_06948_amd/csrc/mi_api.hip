@@ -6,6 +6,9 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
+#include <deque>
+#include <map>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -1299,4 +1302,411 @@ extern "C" mi_status mi_align_coarse_to_fine(const mi_ref *r, const float *xyz_b
   for (int a = 0; a < 6; ++a) pose_out[a] = ctr[a];
   if (mi_best) *mi_best = best;
   return MI_OK;
+}
+
+// ---------------------------------------------------------------- serving
+
+namespace {
+
+// First-fit allocator over offsets of a caller-owned device range, in
+// 256-byte granules; neighbours merge on release.
+class Arena {
+ public:
+  void init(size_t size) {
+    free_.clear();
+    if (size) free_[0] = size;
+  }
+  bool alloc(size_t bytes, size_t *off) {
+    bytes = al256(std::max<size_t>(bytes, 1));
+    for (auto it = free_.begin(); it != free_.end(); ++it) {
+      if (it->second < bytes) continue;
+      *off = it->first;
+      const size_t rest = it->second - bytes, o = it->first + bytes;
+      free_.erase(it);
+      if (rest) free_[o] = rest;
+      return true;
+    }
+    return false;
+  }
+  void release(size_t off, size_t bytes) {
+    if (!bytes) return;
+    auto it = free_.emplace(off, bytes).first;
+    auto nx = std::next(it);
+    if (nx != free_.end() && it->first + it->second == nx->first) {
+      it->second += nx->second;
+      free_.erase(nx);
+    }
+    if (it != free_.begin()) {
+      auto pv = std::prev(it);
+      if (pv->first + pv->second == it->first) {
+        pv->second += it->second;
+        free_.erase(it);
+      }
+    }
+  }
+
+ private:
+  std::map<size_t, size_t> free_;
+};
+
+struct Request {
+  int64_t id = 0;
+  mi_request_state st;
+  mi_grid_desc gd;
+  std::vector<uint32_t> ce;
+  std::vector<uint64_t> ze;
+  std::vector<float> a, b;
+  int64_t n_a = 0, n_b = 0;
+  mi_c2f_desc search;
+  double ctr[6], h[6];
+  mi_grid *g = nullptr;
+  mi_ref *ref = nullptr;
+  size_t ref_bytes = 0, ref_keep = 0;
+  size_t off_b = 0, off_a = 0, off_ref = 0;
+  bool holds = false;              // arena blocks held
+  std::vector<double> P;           // poses of the current level
+  size_t slot = 0;                 // place of its argmax in the pinned results
+};
+
+double seconds_since(std::chrono::steady_clock::time_point t0) {
+  return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+}
+
+}  // namespace
+
+struct mi_server {
+  char *arena = nullptr;
+  size_t arena_bytes = 0, step_bytes = 0;
+  int32_t max_active = 1;
+  hipStream_t stream = nullptr;
+  Arena heap;                      // offsets within [step_bytes, arena_bytes)
+  std::mutex mu;                   // queue and request table
+  std::deque<Request *> queue;
+  std::vector<Request *> active;
+  std::unordered_map<int64_t, std::unique_ptr<Request>> table;
+  int64_t next_id = 1;
+  std::chrono::steady_clock::time_point t0;
+  char *pinned = nullptr;          // [max_active] x (argmax, MI)
+};
+
+namespace {
+
+size_t req_points_bytes(int64_t n) { return al256((size_t)std::max<int64_t>(n, 1) * 3 * sizeof(float)); }
+
+// Device bytes a step needs for one request alone: its pose table, outputs
+// and the largest of its rotated frames.
+size_t req_step_bytes(const Request &r) {
+  const GridInfo &gi = r.g->gi;
+  const int64_t K = c2f_count(&r.search);
+  const double spread_x = 2.0 * r.search.half_range[0] * gi.s + 4.0;
+  const double spread_y = 2.0 * r.search.half_range[1] * gi.s + 4.0;
+  const int64_t ncols = (int64_t)(gi.dims[0] + spread_x) * (int64_t)(gi.dims[1] + spread_y);
+  const FrameBytes fb = frame_bytes(r.n_b, ncols);
+  return al256((size_t)K * sizeof(PoseDev)) + al256(sizeof(PairDev)) +
+         al256((size_t)K * sizeof(FrameDev)) + al256((size_t)gi.nf * K * 8) + 4 * 256 + fb.v +
+         fb.off + al256(fb.cur) + 4096;
+}
+
+void req_release(mi_server *s, Request *r) {
+  if (r->holds) {
+    s->heap.release(r->off_b, req_points_bytes(r->n_b));
+    s->heap.release(r->off_ref, r->ref_keep);
+    r->holds = false;
+  }
+  if (r->ref) { mi_ref_destroy(r->ref); r->ref = nullptr; }
+}
+
+void req_fail(mi_server *s, Request *r, mi_status st) {
+  req_release(s, r);
+  std::lock_guard<std::mutex> lk(s->mu);
+  r->st.state = MI_REQ_FAILED;
+  r->st.status = st;
+  r->st.t_done = seconds_since(s->t0);
+}
+
+// Arena blocks for scan B, scan A and the reference workspace; all or none.
+bool req_reserve(mi_server *s, Request *r) {
+  size_t ob, oa, orf;
+  if (!s->heap.alloc(req_points_bytes(r->n_b), &ob)) return false;
+  if (!s->heap.alloc(req_points_bytes(r->n_a), &oa)) {
+    s->heap.release(ob, req_points_bytes(r->n_b));
+    return false;
+  }
+  if (!s->heap.alloc(r->ref_bytes, &orf)) {
+    s->heap.release(ob, req_points_bytes(r->n_b));
+    s->heap.release(oa, req_points_bytes(r->n_a));
+    return false;
+  }
+  r->off_b = ob;
+  r->off_a = oa;
+  r->off_ref = orf;
+  r->holds = true;
+  return true;
+}
+
+// Upload both scans and build the reference; scan A's block and the
+// reference's transient sums go back to the heap as soon as the kernels that
+// use them are enqueued (later users of that memory run after them on the
+// same stream).
+mi_status req_start(mi_server *s, Request *r) {
+  char *base = s->arena + s->step_bytes;
+  float *db = (float *)(base + r->off_b), *da = (float *)(base + r->off_a);
+  const size_t bb = (size_t)r->n_b * 3 * sizeof(float), ba = (size_t)r->n_a * 3 * sizeof(float);
+  hipError_t e = hipSuccess;
+  if (bb + ba > 0) {
+    Staging *sg = staging_acquire(bb + ba + 64, &e);
+    if (!sg) return dev_fail(e, "pinned staging");
+    if (bb) memcpy(sg->p, r->b.data(), bb);
+    if (ba) memcpy((char *)sg->p + bb, r->a.data(), ba);
+    const Upload ups[2] = {{db, 0, bb}, {da, bb, ba}};
+    e = staging_upload(sg, ups, 2, s->stream);
+    if (e != hipSuccess) return dev_fail(e, "scan upload");
+  }
+  mi_status st = mi_features_ref(r->g, da, r->n_a, base + r->off_ref, r->ref_bytes, s->stream,
+                                 &r->ref);
+  if (st != MI_OK) return st;
+  s->heap.release(r->off_a, req_points_bytes(r->n_a));
+  const size_t whole = al256(r->ref_bytes);
+  s->heap.release(r->off_ref + r->ref_keep, whole - r->ref_keep);
+  std::vector<float>().swap(r->a);
+  std::vector<float>().swap(r->b);
+  return MI_OK;
+}
+
+// One search level of a group of active requests as one batch, carved from
+// the step region; a group that does not fit is split in halves.  The
+// argmaxes land in the pinned results; nothing here waits for the device.
+mi_status run_level(mi_server *s, Request *const *rs, size_t n,
+                    std::vector<std::pair<Request *, mi_status>> &failed) {
+  if (n == 0) return MI_OK;
+  Carver c(s->arena, s->step_bytes);
+  std::vector<mi_work_item> items(n);
+  std::vector<double *> mis(n);
+  std::vector<int64_t *> ams(n);
+  std::vector<double *> mvs(n);
+  char *base = s->arena + s->step_bytes;
+  for (size_t i = 0; i < n; ++i) {
+    Request *r = rs[i];
+    c2f_grid(r->ctr, r->h, r->search.samples, r->P);
+    const int64_t K = (int64_t)(r->P.size() / 6);
+    mis[i] = c.take<double>((size_t)r->g->gi.nf * (size_t)K);
+    ams[i] = c.take<int64_t>(1);
+    mvs[i] = c.take<double>(1);
+    mi_work_item &w = items[i];
+    memset(&w, 0, sizeof w);
+    w.ref = r->ref;
+    w.xyz_b = (const float *)(base + r->off_b);
+    w.n_b = r->n_b;
+    w.poses = r->P.data();
+    w.K = K;
+    w.mi_out = mis[i];
+  }
+  c.take<char>(0);
+  mi_status st = MI_E_WORKSPACE;
+  mi_plan *p = nullptr;
+  if (c.fits())
+    st = create_plan(items.data(), (int64_t)n, 0, (void *)c.cur, s->step_bytes - c.used(), 0,
+                     s->stream, false, &p);
+  if (st != MI_OK && st != MI_E_DEVICE && n > 1) {
+    // split until every part fits, or a single request shows what is wrong with it
+    const size_t h = n / 2;
+    mi_status a = run_level(s, rs, h, failed);
+    if (a != MI_OK) return a;
+    return run_level(s, rs + h, n - h, failed);
+  }
+  if (st != MI_OK && st != MI_E_DEVICE) {
+    failed.emplace_back(rs[0], st);
+    return MI_OK;
+  }
+  if (st != MI_OK) return st;
+  st = run_plan(p, s->stream);
+  mi_plan_destroy(p);
+  if (st != MI_OK) return st;
+  for (size_t i = 0; i < n; ++i) {
+    Request *r = rs[i];
+    const int64_t K = items[i].K;
+    HIP_TRY(launch_argmax(mis[i] + (int64_t)r->search.feature_slot * K, K, 1, ams[i], mvs[i],
+                          s->stream), "argmax");
+    char *dst = s->pinned + 16 * r->slot;
+    HIP_TRY(hipMemcpyAsync(dst, ams[i], 8, hipMemcpyDeviceToHost, s->stream), "argmax D2H");
+    HIP_TRY(hipMemcpyAsync(dst + 8, mvs[i], 8, hipMemcpyDeviceToHost, s->stream), "MI D2H");
+  }
+  return MI_OK;
+}
+
+}  // namespace
+
+extern "C" mi_status mi_server_create(const mi_server_desc *d, void *stream, mi_server **out) {
+  if (!d || !out) return fail(MI_E_INVALID, "mi_server_create: NULL argument");
+  *out = nullptr;
+  if (!d->arena || ((uintptr_t)d->arena & 255)) return fail(MI_E_WORKSPACE, "arena NULL or not 256-aligned");
+  if (d->max_active < 1 || d->max_active > 65536) return fail(MI_E_INVALID, "max_active out of range");
+  size_t step = d->step_bytes ? d->step_bytes : d->arena_bytes / 4;
+  step &= ~(size_t)255;
+  if (step < ((size_t)1 << 20) || step >= d->arena_bytes)
+    return fail(MI_E_WORKSPACE, "step region must be at least 1 MiB and leave room for requests");
+  std::unique_ptr<mi_server> s(new (std::nothrow) mi_server());
+  if (!s) return fail(MI_E_INVALID, "out of host memory");
+  s->arena = (char *)d->arena;
+  s->arena_bytes = d->arena_bytes;
+  s->step_bytes = step;
+  s->max_active = d->max_active;
+  s->stream = (hipStream_t)stream;
+  s->heap.init((d->arena_bytes - step) & ~(size_t)255);
+  s->t0 = std::chrono::steady_clock::now();
+  HIP_TRY(hipHostMalloc((void **)&s->pinned, 16 * (size_t)d->max_active, hipHostMallocDefault),
+          "pinned results");
+  *out = s.release();
+  return MI_OK;
+}
+
+extern "C" mi_status mi_server_submit(mi_server *s, const mi_request *q, int64_t *id) {
+  if (!s || !q || !id) return fail(MI_E_INVALID, "mi_server_submit: NULL argument");
+  *id = 0;
+  if (q->n_a < 0 || q->n_b < 0 || (q->n_a > 0 && !q->xyz_a) || (q->n_b > 0 && !q->xyz_b))
+    return fail(MI_E_INVALID, "bad scans");
+  for (int a = 0; a < 6; ++a)
+    if (!std::isfinite(q->init[a])) return fail(MI_E_INVALID, "non-finite initial pose");
+  std::unique_ptr<Request> r(new (std::nothrow) Request());
+  if (!r) return fail(MI_E_INVALID, "out of host memory");
+  r->gd = q->grid;
+  if (q->grid.count_edges && q->grid.nbins_count > 1) {
+    r->ce.assign(q->grid.count_edges, q->grid.count_edges + (q->grid.nbins_count - 1));
+    r->gd.count_edges = r->ce.data();
+  }
+  if (q->grid.zvar_edges && q->grid.nbins_zvar > 2) {
+    r->ze.assign(q->grid.zvar_edges, q->grid.zvar_edges + (q->grid.nbins_zvar - 2));
+    r->gd.zvar_edges = r->ze.data();
+  }
+  mi_status st = mi_grid_create(&r->gd, &r->g);
+  if (st != MI_OK) return st;
+  std::unique_ptr<mi_grid, void (*)(mi_grid *)> gguard(r->g, mi_grid_destroy);
+  const GridInfo &gi = r->g->gi;
+  if (!c2f_ok(&q->search, gi.nf)) return fail(MI_E_INVALID, "bad search description");
+  if ((gi.features & MI_FEAT_ZVAR) && q->n_b >= MI_MAX_POINTS)
+    return fail(MI_E_UNSUPPORTED, "scan B has >= 2^20 points with the z-variance feature");
+  r->search = q->search;
+  r->n_a = q->n_a;
+  r->n_b = q->n_b;
+  r->a.assign(q->xyz_a, q->xyz_a + 3 * q->n_a);
+  r->b.assign(q->xyz_b, q->xyz_b + 3 * q->n_b);
+  for (int a = 0; a < 6; ++a) { r->ctr[a] = q->init[a]; r->h[a] = q->search.half_range[a]; }
+  size_t keep = 0;
+  r->ref_bytes = mi_features_ref_workspace(r->g, q->n_a, &keep);
+  r->ref_keep = al256(keep);
+  const size_t need = req_points_bytes(q->n_a) + req_points_bytes(q->n_b) + al256(r->ref_bytes);
+  if (need > s->arena_bytes - s->step_bytes)
+    return fail(MI_E_UNSUPPORTED, "request needs %zu bytes of arena, the server has %zu", need,
+                s->arena_bytes - s->step_bytes);
+  if (req_step_bytes(*r) > s->step_bytes)
+    return fail(MI_E_UNSUPPORTED, "one search level of the request needs a step region of %zu "
+                "bytes, the server has %zu", req_step_bytes(*r), s->step_bytes);
+  gguard.release();
+  memset(&r->st, 0, sizeof r->st);
+  r->st.state = MI_REQ_QUEUED;
+  r->st.status = MI_OK;
+  std::lock_guard<std::mutex> lk(s->mu);
+  r->id = s->next_id++;
+  r->st.t_submit = seconds_since(s->t0);
+  *id = r->id;
+  s->queue.push_back(r.get());
+  s->table.emplace(r->id, std::move(r));
+  return MI_OK;
+}
+
+extern "C" mi_status mi_server_step(mi_server *s, int32_t *n_active, int32_t *n_queued) {
+  if (!s) return fail(MI_E_INVALID, "mi_server_step: NULL server");
+  // admission: arrival order, while a slot is free and the data fits
+  std::vector<Request *> admitted;
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    while (!s->queue.empty() && (int32_t)s->active.size() < s->max_active) {
+      Request *r = s->queue.front();
+      if (!req_reserve(s, r)) break;
+      s->queue.pop_front();
+      r->st.state = MI_REQ_ACTIVE;
+      r->st.t_admit = seconds_since(s->t0);
+      s->active.push_back(r);
+      admitted.push_back(r);
+    }
+  }
+  for (Request *r : admitted) {
+    const mi_status st = req_start(s, r);
+    if (st != MI_OK) req_fail(s, r, st);
+  }
+  std::vector<Request *> live;
+  for (Request *r : s->active)
+    if (r->st.state == MI_REQ_ACTIVE) live.push_back(r);
+  for (size_t i = 0; i < live.size(); ++i) live[i]->slot = i;
+  std::vector<std::pair<Request *, mi_status>> failed;
+  mi_status st = run_level(s, live.data(), live.size(), failed);
+  if (st != MI_OK) return st;
+  HIP_TRY(hipStreamSynchronize(s->stream), "step sync");
+  const double now = seconds_since(s->t0);
+  for (auto &f : failed) req_fail(s, f.first, f.second);
+  for (Request *r : live) {
+    if (r->st.state != MI_REQ_ACTIVE) continue;
+    int64_t kbest;
+    double mv;
+    memcpy(&kbest, s->pinned + 16 * r->slot, 8);
+    memcpy(&mv, s->pinned + 16 * r->slot + 8, 8);
+    const int64_t K = (int64_t)(r->P.size() / 6);
+    if (kbest < 0 || kbest >= K) { req_fail(s, r, MI_E_DEVICE); continue; }
+    for (int a = 0; a < 6; ++a) r->ctr[a] = r->P[(size_t)kbest * 6 + a];
+    for (int a = 0; a < 6; ++a) r->h[a] = r->h[a] / r->search.shrink;
+    std::lock_guard<std::mutex> lk(s->mu);
+    r->st.levels_done += 1;
+    for (int a = 0; a < 6; ++a) r->st.pose[a] = r->ctr[a];
+    r->st.mi = mv;
+    if (r->st.levels_done >= r->search.levels) {
+      r->st.state = MI_REQ_DONE;
+      r->st.t_done = now;
+    }
+  }
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    std::vector<Request *> still;
+    for (Request *r : s->active) {
+      if (r->st.state == MI_REQ_ACTIVE) still.push_back(r);
+      else req_release(s, r);
+    }
+    s->active.swap(still);
+    if (n_active) *n_active = (int32_t)s->active.size();
+    if (n_queued) *n_queued = (int32_t)s->queue.size();
+  }
+  return MI_OK;
+}
+
+extern "C" mi_status mi_server_poll(mi_server *s, int64_t id, mi_request_state *out) {
+  if (!s || !out) return fail(MI_E_INVALID, "mi_server_poll: NULL argument");
+  std::lock_guard<std::mutex> lk(s->mu);
+  auto it = s->table.find(id);
+  if (it == s->table.end()) return fail(MI_E_INVALID, "unknown request %lld", (long long)id);
+  *out = it->second->st;
+  return MI_OK;
+}
+
+extern "C" mi_status mi_server_release(mi_server *s, int64_t id) {
+  if (!s) return fail(MI_E_INVALID, "mi_server_release: NULL server");
+  std::lock_guard<std::mutex> lk(s->mu);
+  auto it = s->table.find(id);
+  if (it == s->table.end()) return fail(MI_E_INVALID, "unknown request %lld", (long long)id);
+  const int32_t state = it->second->st.state;
+  if (state != MI_REQ_DONE && state != MI_REQ_FAILED)
+    return fail(MI_E_INVALID, "request %lld is still queued or active", (long long)id);
+  if (it->second->g) mi_grid_destroy(it->second->g);
+  s->table.erase(it);
+  return MI_OK;
+}
+
+extern "C" void mi_server_destroy(mi_server *s) {
+  if (!s) return;
+  (void)hipStreamSynchronize(s->stream);
+  for (auto &kv : s->table) {
+    Request *r = kv.second.get();
+    if (r->ref) mi_ref_destroy(r->ref);
+    if (r->g) mi_grid_destroy(r->g);
+  }
+  if (s->pinned) (void)hipHostFree(s->pinned);
+  delete s;
 }

@@ -57,6 +57,23 @@ class _WorkItem(C.Structure):
                 ("argmax_out", C.c_void_p), ("hist_out", C.c_void_p), ("stats_out", C.c_void_p)]
 
 
+class _ServerDesc(C.Structure):
+    _fields_ = [("arena", C.c_void_p), ("arena_bytes", C.c_size_t), ("step_bytes", C.c_size_t),
+                ("max_active", C.c_int32)]
+
+
+class _Request(C.Structure):
+    _fields_ = [("grid", _GridDesc), ("xyz_a", C.c_void_p), ("n_a", C.c_int64),
+                ("xyz_b", C.c_void_p), ("n_b", C.c_int64), ("init", C.c_double * 6),
+                ("search", _C2F)]
+
+
+class _RequestState(C.Structure):
+    _fields_ = [("state", C.c_int32), ("levels_done", C.c_int32), ("status", C.c_int32),
+                ("pad", C.c_int32), ("pose", C.c_double * 6), ("mi", C.c_double),
+                ("t_submit", C.c_double), ("t_admit", C.c_double), ("t_done", C.c_double)]
+
+
 class _Tuning(C.Structure):
     _fields_ = [("waves", C.c_int32), ("hash_bytes", C.c_int32), ("hist_copies", C.c_int32),
                 ("stripe_rows", C.c_int32)]
@@ -96,6 +113,12 @@ def _load():
         "mi_batch_create": ([C.POINTER(_WorkItem), i64, u32, vp, sz, sz, vp, C.POINTER(vp)], st),
         "mi_batch_execute": ([vp, vp], st),
         "mi_eval_batch": ([C.POINTER(_WorkItem), i64, u32, vp, sz, vp], st),
+        "mi_server_create": ([C.POINTER(_ServerDesc), vp, C.POINTER(vp)], st),
+        "mi_server_submit": ([vp, C.POINTER(_Request), C.POINTER(i64)], st),
+        "mi_server_step": ([vp, C.POINTER(C.c_int32), C.POINTER(C.c_int32)], st),
+        "mi_server_poll": ([vp, i64, C.POINTER(_RequestState)], st),
+        "mi_server_release": ([vp, i64], st),
+        "mi_server_destroy": ([vp], None),
         "mi_align_workspace": ([vp, i64, C.POINTER(_C2F)], sz),
         "mi_align_coarse_to_fine": ([vp, vp, i64, dp, C.POINTER(_C2F), dp, dp, vp, sz, vp], st),
     }
@@ -114,7 +137,9 @@ EXPORTED = ("mi_status_str", "mi_last_error", "mi_tuning_set", "mi_tuning_get",
             "mi_eval_poses_workspace", "mi_eval_poses", "mi_eval_poses_plain_workspace",
             "mi_eval_poses_plain", "mi_plan_create", "mi_plan_execute", "mi_plan_destroy",
             "mi_batch_workspace", "mi_batch_create", "mi_batch_execute", "mi_eval_batch",
-            "mi_align_workspace", "mi_align_coarse_to_fine")
+            "mi_align_workspace", "mi_align_coarse_to_fine", "mi_server_create",
+            "mi_server_submit", "mi_server_step", "mi_server_poll", "mi_server_release",
+            "mi_server_destroy")
 
 
 def lib():
@@ -474,3 +499,77 @@ def align_coarse_to_fine(ref: Ref, xyz_b, init, half_range, samples, levels, shr
                                         best.ctypes.data_as(C.POINTER(C.c_double)), _dptr(ws),
                                         ws.numel(), _stream(stream)), "mi_align_coarse_to_fine")
     return out, float(best[0])
+
+
+# ------------------------------------------------------------- serving
+
+REQ_QUEUED, REQ_ACTIVE, REQ_DONE, REQ_FAILED = 0, 1, 2, 3
+
+
+def _c2f_desc(half_range, samples, levels, shrink, feature_slot) -> _C2F:
+    d = _C2F()
+    d.half_range[:] = [float(v) for v in half_range]
+    d.samples[:] = [int(v) for v in samples]
+    d.levels = int(levels)
+    d.shrink = float(shrink)
+    d.feature_slot = int(feature_slot)
+    return d
+
+
+class Server:
+    """mi_server: continuous batching of coarse-to-fine alignments over one
+    device arena (torch-allocated here) and one stream."""
+
+    def __init__(self, arena_bytes: int, max_active: int, step_bytes: int = 0, stream=None):
+        self.arena = _workspace(arena_bytes)
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        d = _ServerDesc(_dptr(self.arena).value, self.arena.numel(), int(step_bytes),
+                        int(max_active))
+        h = C.c_void_p()
+        _check(_lib.mi_server_create(C.byref(d), _stream(self.stream), C.byref(h)),
+               "mi_server_create")
+        self._h = h
+
+    def submit(self, origin, dims, voxel, xyz_a, xyz_b, init, half_range, samples, levels,
+               shrink, features=FEAT_COUNT, nb_count=16, nb_zvar=32, feature_slot=0) -> int:
+        A = np.ascontiguousarray(xyz_a, np.float32)
+        B = np.ascontiguousarray(xyz_b, np.float32)
+        q = _Request()
+        q.grid.origin[:] = [float(v) for v in origin]
+        q.grid.dims[:] = [int(v) for v in dims]
+        q.grid.voxel = float(voxel)
+        q.grid.features = int(features)
+        q.grid.nbins_count = int(nb_count)
+        q.grid.nbins_zvar = int(nb_zvar)
+        q.xyz_a = A.ctypes.data
+        q.n_a = A.shape[1]
+        q.xyz_b = B.ctypes.data
+        q.n_b = B.shape[1]
+        q.init[:] = [float(v) for v in init]
+        q.search = _c2f_desc(half_range, samples, levels, shrink, feature_slot)
+        rid = C.c_int64()
+        _check(_lib.mi_server_submit(self._h, C.byref(q), C.byref(rid)), "mi_server_submit")
+        return rid.value
+
+    def step(self):
+        na, nq = C.c_int32(), C.c_int32()
+        _check(_lib.mi_server_step(self._h, C.byref(na), C.byref(nq)), "mi_server_step")
+        return na.value, nq.value
+
+    def poll(self, rid: int) -> dict:
+        st = _RequestState()
+        _check(_lib.mi_server_poll(self._h, int(rid), C.byref(st)), "mi_server_poll")
+        return dict(state=st.state, levels_done=st.levels_done, status=st.status,
+                    pose=np.array(st.pose[:]), mi=st.mi, t_submit=st.t_submit,
+                    t_admit=st.t_admit, t_done=st.t_done)
+
+    def release(self, rid: int):
+        _check(_lib.mi_server_release(self._h, int(rid)), "mi_server_release")
+
+    def close(self):
+        if getattr(self, "_h", None) and _lib is not None:
+            _lib.mi_server_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        self.close()
