@@ -67,8 +67,14 @@ typedef int32_t mi_status;
 #define MI_FEAT_COUNT 1u /* number of points in the voxel */
 #define MI_FEAT_ZVAR 2u  /* variance of z-height in the voxel */
 
-/* Evaluation flags for mi_plan_create / mi_eval_poses. */
+/* Evaluation flags for mi_plan_create / mi_eval_poses / batches. */
 #define MI_EVAL_NEAR_FACE 1u /* count points within 1e-5 m of a voxel face (stats) */
+/* How scan B reaches the evaluator (results are identical either way).  By
+ * default a pose set whose rotations serve two or more poses each on average
+ * shares rotated frames (B rotated once per distinct rotation and bucketed by
+ * column); otherwise each pose's workgroup transforms and buckets B itself. */
+#define MI_EVAL_PER_POSE 2u      /* force per-pose bucketing */
+#define MI_EVAL_SHARED_FRAMES 4u /* force shared rotated frames */
 
 /* Limits. */
 #define MI_MAX_BINS 64
@@ -104,16 +110,19 @@ const char *mi_status_str(mi_status s);
 const char *mi_last_error(void);
 
 /* Launch shape of the batched evaluator (process-wide; read when a plan is
- * created).  waves: 1..16 waves per workgroup (one workgroup per pose);
- * hash_bytes: LDS bytes for the voxel sums of one brick (the slot count is the
- * largest power of two that fits); hist_copies: 1..8 privatized joint
- * histograms; stripe_rows: 1..62 voxel rows per stripe of bricks.  Every
+ * created).  waves: 1..16 waves per workgroup (a workgroup evaluates one pose
+ * at a time); hash_bytes: LDS bytes for the voxel sums of one brick (the slot
+ * count is the largest power of two that fits); hist_copies: 1..8 privatized
+ * joint histograms; stripe_rows: 1..62 voxel rows per stripe of bricks;
+ * wgs_per_cu: 0 launches one workgroup per pose, 1..16 a persistent grid of
+ * that many workgroups per compute unit, each looping over poses.  Every
  * setting gives bit-identical histograms. */
 typedef struct mi_tuning {
   int32_t waves;
   int32_t hash_bytes;
   int32_t hist_copies;
   int32_t stripe_rows;
+  int32_t wgs_per_cu;
 } mi_tuning;
 mi_status mi_tuning_set(const mi_tuning *t);
 mi_status mi_tuning_get(mi_tuning *t);
@@ -264,6 +273,35 @@ mi_status mi_batch_create(const mi_work_item *items, int64_t n_items, uint32_t f
 mi_status mi_batch_execute(mi_plan *p, void *stream);
 mi_status mi_eval_batch(const mi_work_item *items, int64_t n_items, uint32_t flags, void *ws,
                         size_t ws_bytes, void *stream);
+
+/* ------------------------------------------------------------ autotune */
+
+/* Chooses the evaluator's launch shape (mi_tuning) for a workload by timing
+ * it.  A sample of the items is built (each item's poses strided down to at
+ * most max_poses, keeping the mix of rotations; max_poses <= 0 keeps all),
+ * and executed as a batch under candidate tunings in three stages: waves per
+ * workgroup x hash capacity, then stripe height x histogram copies around
+ * the best, then one workgroup per pose against persistent grids of 1, 2 and
+ * 4 workgroups per compute unit.  Each candidate is run once to warm up and
+ * timed over two executions with HIP events on `stream` (synchronizing).
+ * Candidates that a workload cannot use are skipped.  The fastest tuning,
+ * possibly the one in force, is made current (process-wide; plans created
+ * meanwhile by other threads may see the candidates) and reported.  Every
+ * tuning gives bit-identical results, so the choice changes speed only.  The
+ * items' own outputs are not written; ws (size from mi_autotune_workspace, 0
+ * on bad items) holds the sample's outputs and batch. */
+typedef struct mi_autotune_report {
+  mi_tuning best;
+  double best_ms;   /* one execution of the sample under `best` */
+  double start_ms;  /* the same under the tuning in force before the call */
+  int32_t tried;    /* candidates timed */
+} mi_autotune_report;
+
+size_t mi_autotune_workspace(const mi_work_item *items, int64_t n_items, uint32_t flags,
+                             int64_t max_poses);
+mi_status mi_autotune(const mi_work_item *items, int64_t n_items, uint32_t flags,
+                      int64_t max_poses, void *ws, size_t ws_bytes, void *stream,
+                      mi_autotune_report *out);
 
 /* ------------------------------------------------------------- search */
 

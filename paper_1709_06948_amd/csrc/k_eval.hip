@@ -27,6 +27,8 @@
 //         the overlap box), one count in the joint histogram at (A's bin, B's bin);
 //  finish overlap box O; the cells of voxels that B leaves empty come from A's
 //         per-bin summed-volume tables; entropies and MI.
+#include <algorithm>
+
 #include "mi_device.h"
 #include "mi_internal.h"
 
@@ -43,6 +45,7 @@ struct EvalCfgDev {
   int32_t cap_log2;
   int32_t load_max;           // voxels of a brick that is known to fit (a quarter of the slots)
   int32_t off_cnta, off_edges, off_wave, off_plan, off_hash, pad;
+  int64_t xcd_start[kXcds + 1];  // items of XCD x: [xcd_start[x], xcd_start[x + 1])
 };
 
 struct Layout {
@@ -79,21 +82,66 @@ __device__ __forceinline__ void rows_for(int y0, int y1, double cy, int gy, int 
   *nrows = b >= a ? b - a + 1 : 0;
 }
 
-template <bool NEAR, bool ZVAR>
+// Voxel of point i of scan B under a pose (rotation of frame F, translation
+// offset c): the same doubles as the rotated frames plus the offset,
+// u = fl(fl(w * s) + c) with w = ((r0 x + r1 y) + r2 z).
+struct DirectVoxel {
+  int ix, iy, iz;
+  uint32_t q;
+  bool in;     // finite and inside the grid
+  bool near;   // within kNearFace of a face (when asked for)
+};
+
+template <bool ZVAR, bool NEAR>
+__device__ __forceinline__ DirectVoxel direct_voxel(const float *xyz, int64_t n, int64_t i,
+                                                    const double (&R)[9], double s, double cx,
+                                                    double cy, double cz, int nx, int ny, int nz,
+                                                    double voxel) {
+  DirectVoxel r;
+  r.in = false;
+  r.near = false;
+  r.q = 0u;
+  const float xf = ldg(xyz + i), yf = ldg(xyz + n + i), zf = ldg(xyz + 2 * n + i);
+  if (!isfinite(xf) || !isfinite(yf) || !isfinite(zf)) return r;
+  const double x = xf, y = yf, z = zf;
+  const double wx = (R[0] * x + R[1] * y) + R[2] * z;
+  const double wy = (R[3] * x + R[4] * y) + R[5] * z;
+  const double wz = (R[6] * x + R[7] * y) + R[8] * z;
+  const double vx = wx * s, vy = wy * s, vz = wz * s;
+  const double ux = vx + cx, uy = vy + cy, uz = vz + cz;
+  const double fx = floor(ux), fy = floor(uy), fz = floor(uz);
+  r.ix = (int)fx;
+  r.iy = (int)fy;
+  r.iz = (int)fz;
+  r.in = (uint32_t)r.ix < (uint32_t)nx && (uint32_t)r.iy < (uint32_t)ny &&
+         (uint32_t)r.iz < (uint32_t)nz;
+  if (ZVAR) r.q = (uint32_t)floor((uz - fz) * kQScale);
+  if (NEAR && r.in) {
+    double d = 1.0;
+    const double fr[3] = {ux - fx, uy - fy, uz - fz};
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      const double up = 1.0 - fr[a];
+      const double m = fr[a] < up ? fr[a] : up;
+      if (m < d) d = m;
+    }
+    r.near = d * voxel < kNearFace;
+  }
+  return r;
+}
+
+// DIRECT = false: candidates come from the pose's rotated frame (points
+// bucketed by column, shared by every pose with that rotation).
+// DIRECT = true: the workgroup buckets its pose's points itself, by stripe,
+// into its own slot of `scratch` (count, scan, scatter of (key, q) pairs),
+// for pose sets whose rotations are (nearly) all distinct.
+template <bool NEAR, bool ZVAR, bool DIRECT>
 __global__ void __launch_bounds__(1024) k_eval(const PairDev *__restrict__ pairs,
                                                const FrameDev *__restrict__ frames,
-                                               const PoseDev *__restrict__ items, int64_t n_items,
-                                               int64_t per_xcd, EvalCfgDev cfg) {
+                                               const PoseDev *__restrict__ items, EvalCfgDev cfg,
+                                               uint2 *__restrict__ scratch,
+                                               int64_t scratch_stride) {
   extern __shared__ __align__(16) unsigned char smem[];
-  // XCD-aware mapping: consecutive workgroup ids go round-robin over the XCDs,
-  // so each XCD walks a contiguous run of the frame-sorted items and keeps the
-  // frames it reads in its own L2.
-  const int64_t item = (int64_t)(blockIdx.x % kXcds) * per_xcd + blockIdx.x / kXcds;
-  if (item >= n_items) return;
-  const PoseDev pose = items[item];
-  const PairDev &P = pairs[pose.pair];
-  const FrameDev &Fr = frames[pose.frame];
-
   const int T = blockDim.x, tid = threadIdx.x, lane = tid & 63, W = T >> 6;
   const int wid = __builtin_amdgcn_readfirstlane(tid >> 6);
   uint32_t *hist = (uint32_t *)smem;
@@ -114,430 +162,543 @@ __global__ void __launch_bounds__(1024) k_eval(const PairDev *__restrict__ pairs
   uint32_t *hcnt = hkey + cap;                                    // count only
   uint16_t *occ = (uint16_t *)(hkey + cap * (ZVAR ? 5 : 2));      // slots in insertion order
 
-  const int nx = P.nx, ny = P.ny, nz = P.nz, nf = P.nf;
-  const int nb0 = P.nb[0], nb1 = nf > 1 ? P.nb[1] : 0;
-  const int hoff1 = nb0 * nb0;
-
-  for (int i = tid; i < cfg.hist_copies * cfg.hist_words; i += T) hist[i] = 0u;
-  for (int i = tid; i < 64; i += T) {
-    cedge[i] = P.count_edges[i];
-    zedge[i] = P.zvar_edges[i];
-  }
+  // The hash starts empty and every brick's sweep empties the slots it used,
+  // so it is cleared once per workgroup.
   for (int i = tid; i < cap; i += T) {
     hkey[i] = kEmpty;
     if (ZVAR) { hv1[i] = 0ull; hv2[i] = 0ull; } else { hcnt[i] = 0u; }
   }
-  if (tid < 4) ovf[tid] = 0u;
-  __syncthreads();
 
-  const double cx = pose.c[0], cy = pose.c[1], cz = pose.c[2];
-  const double *fvx = Fr.v;
-  const double *fvy = fvx + Fr.n;
-  const double *fvz = fvy + Fr.n;
-  const int ncx = Fr.ncx, ncy = Fr.ncy, gx = Fr.gx, gy = Fr.gy;
-  const uint32_t *off = Fr.off;
-  const int alo0 = P.abox[0], alo1 = P.abox[1], alo2 = P.abox[2];
-  const int ahi0 = P.abox[3], ahi1 = P.abox[4], ahi2 = P.abox[5];
-  uint32_t *myhist = hist + (wid % cfg.hist_copies) * cfg.hist_words;
-  const uint32_t kind0 = P.kind[0], kind1 = P.kind[1];
-  const uint8_t *binA0 = P.binA[0], *binA1 = P.binA[1];
-  const int BY = P.stripe_h, NS = P.n_stripes, Q = P.pieces, RM = BY + 2;
-  const int kxb = P.kx_bits, kyb = P.ky_bits;
-  const uint32_t kxm = (1u << kxb) - 1u, kym = (1u << kyb) - 1u;
-  const int G = P.plan_stripes;
-  const int PE = RM * (Q + 1);  // plan entries per stripe
+  // XCD-aware mapping: consecutive workgroup ids go round-robin over the XCDs,
+  // and each XCD walks its own run of items (whole frames, so the frames it
+  // reads stay in its L2).  A workgroup takes every (grid / 8)-th item of its
+  // XCD's run: one item when the grid covers the longest run, several when
+  // the grid is persistent.
+  const int64_t xcd = blockIdx.x % kXcds, wpx = gridDim.x / kXcds;
+  const int64_t x_end = cfg.xcd_start[xcd + 1];
+  for (int64_t item = cfg.xcd_start[xcd] + blockIdx.x / kXcds; item < x_end; item += wpx) {
+    const PoseDev pose = items[item];
+    const PairDev &P = pairs[pose.pair];
+    const FrameDev &Fr = frames[pose.frame];
 
-  int lo0 = nx, lo1 = ny, lo2 = nz, hi0 = -1, hi1 = -1, hi2 = -1;
-  unsigned long long nin = 0, nnear = 0;
-  int parity = 0;
+    const int nx = P.nx, ny = P.ny, nz = P.nz, nf = P.nf;
+    const int nb0 = P.nb[0], nb1 = nf > 1 ? P.nb[1] : 0;
+    const int hoff1 = nb0 * nb0;
 
-  for (int s0 = 0; s0 < NS; s0 += G) {
-    const int gn = min(G, NS - s0);
-    // ---- plan: offsets of every candidate row at every piece cut
-    for (int e = tid; e < gn * PE; e += T) {
-      const int q = e % (Q + 1);
-      const int t1 = e / (Q + 1);
-      const int r = t1 % RM, sl = t1 / RM;
-      const int Y0 = (s0 + sl) * BY, Y1 = min(Y0 + BY, ny);
-      int r0, nrows;
-      rows_for(Y0, Y1, cy, gy, ncy, &r0, &nrows);
-      uint2 v = make_uint2(0u, 0u);
-      if (r < nrows) {
-        int K = (int)floor((double)cut_x(q, nx, Q) - cx - kColEps) - gx;
-        K = min(max(K, 0), ncx - 1);
-        const uint32_t *orow = off + (int64_t)(r0 + r) * ncx;
-        v.x = ldg(orow + K);
-        v.y = ldg(orow + min(K + 2, ncx));
-      }
-      plan[sl * PE + r * (Q + 1) + q] = v;
+    for (int i = tid; i < cfg.hist_copies * cfg.hist_words; i += T) hist[i] = 0u;
+    for (int i = tid; i < 64; i += T) {
+      cedge[i] = P.count_edges[i];
+      zedge[i] = P.zvar_edges[i];
     }
+    if (tid < 4) ovf[tid] = 0u;
     __syncthreads();
 
-    // ---- bricks of each stripe (every thread takes the same decisions)
-    for (int sl = 0; sl < gn; ++sl) {
-      const int SY0 = (s0 + sl) * BY, SY1 = min(SY0 + BY, ny);
-      int sr0, snrows;
-      rows_for(SY0, SY1, cy, gy, ncy, &sr0, &snrows);
-      if (snrows <= 0) continue;
-      const uint2 *ps = plan + sl * PE;
-      int qa = 0;
-      while (qa < Q) {
-        int qe = Q;
-        for (;;) {
-          const bool whole = qe > qa;  // false: piece qa voxel row by voxel row
-          const int qend = whole ? qe : qa + 1;
-          const int X0 = cut_x(qa, nx, Q), X1 = cut_x(qend, nx, Q);
-          const int nsub = whole ? 1 : (SY1 - SY0);
-          bool all_ok = true;
-          for (int sub = 0; sub < nsub; ++sub) {
-            const int Y0 = whole ? SY0 : SY0 + sub, Y1 = whole ? SY1 : Y0 + 1;
-            int ra = 0, nr = snrows;
-            if (!whole) {
-              int rr0, rn;
-              rows_for(Y0, Y1, cy, gy, ncy, &rr0, &rn);
-              ra = rr0 - sr0;
-              nr = rn;
-            }
-            // this brick's candidate rows, one per lane: start, length, chunk prefix
-            uint32_t my_st = 0, my_len = 0;
-            if (lane < nr) {
-              my_st = ps[(ra + lane) * (Q + 1) + qa].x;
-              my_len = ps[(ra + lane) * (Q + 1) + qend].y - my_st;
-            }
-            const uint32_t my_c = (my_len + 63u) >> 6;
-            uint32_t inc = my_c;
+    const double cx = pose.c[0], cy = pose.c[1], cz = pose.c[2];
+    const double *fvx = Fr.v;
+    const double *fvy = fvx + Fr.n;
+    const double *fvz = fvy + Fr.n;
+    const int ncx = Fr.ncx, ncy = Fr.ncy, gx = Fr.gx, gy = Fr.gy;
+    const uint32_t *off = Fr.off;
+    const int alo0 = P.abox[0], alo1 = P.abox[1], alo2 = P.abox[2];
+    const int ahi0 = P.abox[3], ahi1 = P.abox[4], ahi2 = P.abox[5];
+    uint32_t *myhist = hist + (wid % cfg.hist_copies) * cfg.hist_words;
+    const uint32_t kind0 = P.kind[0], kind1 = P.kind[1];
+    const uint8_t *binA0 = P.binA[0], *binA1 = P.binA[1];
+    const int BY = P.stripe_h, NS = P.n_stripes, Q = P.pieces, RM = BY + 2;
+    const int kxb = P.kx_bits, kyb = P.ky_bits;
+    const uint32_t kxm = (1u << kxb) - 1u, kym = (1u << kyb) - 1u;
+    const int G = DIRECT ? NS : P.plan_stripes;
+    const int PE = RM * (Q + 1);  // plan entries per stripe
+
+    int lo0 = nx, lo1 = ny, lo2 = nz, hi0 = -1, hi1 = -1, hi2 = -1;
+    unsigned long long nin = 0, nnear = 0;
+    int parity = 0;
+
+    // DIRECT: the pose's in-grid points bucketed by stripe into this
+    // workgroup's scratch slot; soff[s] .. soff[s + 1] is stripe s.
+    uint32_t *soff = (uint32_t *)plan;   // [NS + 1]
+    uint32_t *scur = soff + NS + 1;      // [NS]
+    uint2 *mine = DIRECT ? scratch + (int64_t)blockIdx.x * scratch_stride : nullptr;
+    if (DIRECT) {
+      double R[9];
 #pragma unroll
-            for (int o = 1; o < 64; o <<= 1) {
-              const uint32_t t = __shfl_up(inc, o, 64);
-              if (lane >= o) inc += t;
-            }
-            const uint32_t my_cpre = inc - my_c;
-            const int nch = nr > 0 ? (int)__shfl(inc, nr - 1, 64) : 0;
-            if (nch == 0) continue;
-            const int p = parity;
-            unsigned long long bnear = 0;
-            // a brick with at most a quarter of the slots in voxels always has an
-            // empty slot: it probes without limit and cannot overflow (single
-            // voxel rows of a piece are always such bricks)
-            const bool fits = (int64_t)(X1 - X0) * (Y1 - Y0) * nz <= cfg.load_max;
-            const int max_probe = fits ? cap : kMaxProbe;
-            // chunk k -> candidate of this lane.  A row of len candidates takes
-            // c = ceil(len/64) chunks; its candidates are cut into 4 runs of 16*c and
-            // step j of the row gives lane l candidate (l/16)*16c + 16j + l%16:
-            // 4 cache lines per load as for 64 consecutive candidates, but lanes of
-            // one step lie in 4 different parts of the row, which spreads the hot
-            // voxels (dense ground near the sensor) over fewer lanes per atomic.
-            auto chunk_idx = [&](int k, bool *valid) -> uint32_t {
-              const unsigned long long mk = __ballot(lane < nr && my_cpre <= (uint32_t)k);
-              const int row = __popcll(mk) - 1;
-              const uint32_t st = __builtin_amdgcn_readlane(my_st, row);
-              const uint32_t len = __builtin_amdgcn_readlane(my_len, row);
-              const uint32_t cpre = __builtin_amdgcn_readlane(my_cpre, row);
-              const uint32_t c = (len + 63u) >> 6;
-              const uint32_t j = (uint32_t)k - cpre;
-              const uint32_t off_in_row = ((uint32_t)lane >> 4) * (c << 4) + (j << 4) +
-                                          ((uint32_t)lane & 15u);
-              *valid = off_in_row < len;
-              return st + off_in_row;
-            };
-            // Four candidates per lane, branch-free up to the rare collisions.
-            auto step4 = [&](const bool (&val)[4], const double (&vx)[4], const double (&vy)[4],
-                             const double (&vz)[4]) {
-              bool inb[4];
-              uint32_t key[4], h[4], q[4];
+      for (int a = 0; a < 9; ++a) R[a] = Fr.R[a];
+      const double fs = Fr.s;
+      const float *xyz = Fr.xyz;
+      const int64_t nb = Fr.n;
+      for (int i = tid; i < NS; i += T) scur[i] = 0u;
+      __syncthreads();
+      for (int64_t i = tid; i < nb; i += T) {
+        const DirectVoxel dv = direct_voxel<ZVAR, NEAR>(xyz, nb, i, R, fs, cx, cy, cz, nx, ny, nz,
+                                                         P.voxel);
+        if (!dv.in) continue;
+        atomicAdd(&scur[dv.iy / BY], 1u);
+        if (NEAR && dv.near && dv.ix >= alo0 && dv.ix <= ahi0 && dv.iy >= alo1 &&
+            dv.iy <= ahi1 && dv.iz >= alo2 && dv.iz <= ahi2)
+          ++nnear;
+      }
+      __syncthreads();
+      if (wid == 0) {  // exclusive scan of the stripe counts
+        uint32_t run = 0;
+        for (int b = 0; b < NS; b += 64) {
+          const uint32_t c = b + lane < NS ? scur[b + lane] : 0u;
+          uint32_t inc = c;
 #pragma unroll
-              for (int i = 0; i < 4; ++i) {
-                const double ux = vx[i] + cx, uy = vy[i] + cy, uz = vz[i] + cz;
-                const double fx = floor(ux), fy = floor(uy), fz = floor(uz);
-                // v_cvt_i32_f64 saturates, so far-away points stay out of range
-                const int ix = (int)fx, iy = (int)fy, iz = (int)fz;
-                inb[i] = val[i] && (uint32_t)(ix - X0) < (uint32_t)(X1 - X0) &&
-                         (uint32_t)(iy - Y0) < (uint32_t)(Y1 - Y0) && (uint32_t)iz < (uint32_t)nz;
-                key[i] = ((uint32_t)iz << (kxb + kyb)) | ((uint32_t)(iy - SY0) << kxb) |
-                         (uint32_t)ix;
-                h[i] = (key[i] * 2654435761u) >> (32 - cfg.cap_log2);
-                q[i] = ZVAR ? (uint32_t)floor((uz - fz) * kQScale) : 0u;
-                if (NEAR && inb[i] && ix >= alo0 && ix <= ahi0 && iy >= alo1 && iy <= ahi1 &&
-                    iz >= alo2 && iz <= ahi2) {
-                  double d = 1.0;
-                  const double fr[3] = {ux - fx, uy - fy, uz - fz};
-#pragma unroll
-                  for (int a = 0; a < 3; ++a) {
-                    const double up = 1.0 - fr[a];
-                    const double m = fr[a] < up ? fr[a] : up;
-                    if (m < d) d = m;
-                  }
-                  if (d * P.voxel < kNearFace) ++bnear;
-                }
-              }
-              uint32_t k0[4];
-#pragma unroll
-              for (int i = 0; i < 4; ++i) k0[i] = __atomic_load_n(&hkey[h[i]], __ATOMIC_RELAXED);
-              bool coll[4], fresh[4];
-#pragma unroll
-              for (int i = 0; i < 4; ++i) {
-                // masked lanes swap on their own dummy word with a value that never matches
-                const bool want = inb[i] && k0[i] == kEmpty;
-                uint32_t *a = want ? &hkey[h[i]] : &dkey[lane];
-                const uint32_t old = atomicCAS(a, want ? kEmpty : kNever, key[i]);
-                const bool got = want ? (old == kEmpty || old == key[i]) : (k0[i] == key[i]);
-                fresh[i] = want && old == kEmpty;
-                coll[i] = inb[i] && !got;
-              }
-              if (coll[0] || coll[1] || coll[2] || coll[3]) {
-#pragma unroll
-                for (int i = 0; i < 4; ++i) {
-                  if (!coll[i]) continue;
-                  uint32_t hh = h[i];
-                  bool ok = false;
-                  for (int pr = 1; pr < max_probe; ++pr) {
-                    hh = (hh + 1u) & (uint32_t)(cap - 1);
-                    uint32_t k1 = __atomic_load_n(&hkey[hh], __ATOMIC_RELAXED);
-                    if (k1 == kEmpty) {
-                      k1 = atomicCAS(&hkey[hh], kEmpty, key[i]);
-                      if (k1 == kEmpty) fresh[i] = true;
-                    }
-                    if (k1 == kEmpty || k1 == key[i]) { ok = true; break; }
-                  }
-                  if (ok) h[i] = hh;
-                  else { ovf[p] = 1u; inb[i] = false; }
-                }
-              }
-              // newly claimed slots go on the brick's occupied list (one LDS atomic per wave)
-              {
-                unsigned long long m[4];
-                uint32_t tot = 0;
-#pragma unroll
-                for (int i = 0; i < 4; ++i) {
-                  m[i] = __ballot(fresh[i]);
-                  tot += (uint32_t)__popcll(m[i]);
-                }
-                if (tot) {
-                  uint32_t base = 0;
-                  if (lane == 0) base = atomicAdd(&occn[p], tot);
-                  base = __shfl(base, 0, 64);
-#pragma unroll
-                  for (int i = 0; i < 4; ++i) {
-                    if (fresh[i]) {
-                      const uint32_t r = __builtin_amdgcn_mbcnt_hi(
-                          (uint32_t)(m[i] >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m[i], 0u));
-                      occ[base + r] = (uint16_t)h[i];
-                    }
-                    base += (uint32_t)__popcll(m[i]);
-                  }
-                }
-              }
-#pragma unroll
-              for (int i = 0; i < 4; ++i) {
-                if (ZVAR) {
-                  unsigned long long *a1 = inb[i] ? &hv1[h[i]] : &dval[lane];
-                  unsigned long long *a2 = inb[i] ? &hv2[h[i]] : &dval[64 + lane];
-                  atomicAdd(a1, (1ull << 44) | (unsigned long long)q[i]);
-                  atomicAdd(a2, (unsigned long long)q[i] * q[i]);
-                } else {
-                  atomicAdd(inb[i] ? &hcnt[h[i]] : &dkey[lane], 1u);
-                }
-              }
-            };
-            // Four chunks per wave step: the twelve loads are issued together, then
-            // the four candidates of each lane go through step4 together.  Lanes
-            // past a row's end load index 0 (always valid) and are masked off.
-            for (int k = wid; k < nch; k += 4 * W) {
-              bool v[4];
-              uint32_t ii[4];
-              ii[0] = chunk_idx(k, &v[0]);
-#pragma unroll
-              for (int i = 1; i < 4; ++i) {
-                v[i] = false;
-                ii[i] = 0u;
-                if (k + i * W < nch) ii[i] = chunk_idx(k + i * W, &v[i]);
-              }
-              double x[4], y[4], z[4];
-#pragma unroll
-              for (int i = 0; i < 4; ++i) {
-                const uint32_t j = v[i] ? ii[i] : 0u;
-                x[i] = ldg(fvx + j);
-                y[i] = ldg(fvy + j);
-                z[i] = ldg(fvz + j);
-              }
-              step4(v, x, y, z);
-            }
-            __syncthreads();
-            const bool overflow = ovf[p] != 0u;
-            const int nocc = (int)occn[p];
-            if (tid == 0) { ovf[p ^ 1] = 0u; occn[p ^ 1] = 0u; }
-            int blo0 = nx, blo1 = ny, blo2 = nz, bhi0 = -1, bhi1 = -1, bhi2 = -1;
-            unsigned long long bnin = 0;
-            for (int i = tid; i < nocc; i += T) {
-              const uint32_t h = occ[i];
-              const uint32_t key = hkey[h];
-              const int ix = (int)(key & kxm);
-              const int iy = SY0 + (int)((key >> kxb) & kym);
-              const int iz = (int)(key >> (kxb + kyb));
-              uint32_t n;
-              unsigned long long s1 = 0, s2 = 0;
-              if (ZVAR) {
-                const unsigned long long a = hv1[h];
-                n = (uint32_t)(a >> 44);
-                s1 = a & ((1ull << 44) - 1);
-                s2 = hv2[h];
-                hv1[h] = 0ull;
-                hv2[h] = 0ull;
-              } else {
-                n = hcnt[h];
-                hcnt[h] = 0u;
-              }
-              hkey[h] = kEmpty;
-              bnin += n;
-              blo0 = min(blo0, ix); blo1 = min(blo1, iy); blo2 = min(blo2, iz);
-              bhi0 = max(bhi0, ix); bhi1 = max(bhi1, iy); bhi2 = max(bhi2, iz);
-              if (!overflow && ix >= alo0 && ix <= ahi0 && iy >= alo1 && iy <= ahi1 &&
-                  iz >= alo2 && iz <= ahi2) {
-                const int64_t lin = ((int64_t)iz * ny + iy) * nx + ix;
-                {
-                  const int a = ldg(binA0 + lin);
-                  const int b = kind0 == MI_FEAT_COUNT ? bin_count_dev(n, nb0, cedge)
-                                                       : bin_zvar_dev(n, s1, s2, nb0, zedge);
-                  atomicAdd(&myhist[a * nb0 + b], 1u);
-                }
-                if (nf > 1) {
-                  const int a = ldg(binA1 + lin);
-                  const int b = kind1 == MI_FEAT_COUNT ? bin_count_dev(n, nb1, cedge)
-                                                       : bin_zvar_dev(n, s1, s2, nb1, zedge);
-                  atomicAdd(&myhist[hoff1 + a * nb1 + b], 1u);
-                }
-              }
-            }
-            __syncthreads();
-            parity ^= 1;
-            if (overflow) {
-              all_ok = false;
-              break;
-            }
-            nin += bnin;
-            nnear += bnear;
-            lo0 = min(lo0, blo0); lo1 = min(lo1, blo1); lo2 = min(lo2, blo2);
-            hi0 = max(hi0, bhi0); hi1 = max(hi1, bhi1); hi2 = max(hi2, bhi2);
+          for (int o = 1; o < 64; o <<= 1) {
+            const uint32_t t = __shfl_up(inc, o, 64);
+            if (lane >= o) inc += t;
           }
-          if (all_ok) { qa = qend; break; }
-          // overflow: halve the run of pieces; a single piece goes row by row
-          qe = qe - qa > 1 ? qa + (qe - qa) / 2 : qa;
+          if (b + lane < NS) {
+            soff[b + lane] = run + inc - c;
+            scur[b + lane] = run + inc - c;
+          }
+          run += __shfl(inc, 63, 64);
+        }
+        if (lane == 0) soff[NS] = run;
+      }
+      __syncthreads();
+      for (int64_t i = tid; i < nb; i += T) {
+        const DirectVoxel dv = direct_voxel<ZVAR, false>(xyz, nb, i, R, fs, cx, cy, cz, nx, ny,
+                                                          nz, P.voxel);
+        if (!dv.in) continue;
+        const int st = dv.iy / BY;
+        const uint32_t pos = atomicAdd(&scur[st], 1u);
+        const uint32_t key = ((uint32_t)dv.iz << (kxb + kyb)) |
+                             ((uint32_t)(dv.iy - st * BY) << kxb) | (uint32_t)dv.ix;
+        mine[pos] = make_uint2(key, dv.q);
+      }
+      __syncthreads();
+    }
+
+    for (int s0 = 0; s0 < NS; s0 += G) {
+      const int gn = min(G, NS - s0);
+      // ---- plan: offsets of every candidate row at every piece cut
+      for (int e = tid; !DIRECT && e < gn * PE; e += T) {
+        const int q = e % (Q + 1);
+        const int t1 = e / (Q + 1);
+        const int r = t1 % RM, sl = t1 / RM;
+        const int Y0 = (s0 + sl) * BY, Y1 = min(Y0 + BY, ny);
+        int r0, nrows;
+        rows_for(Y0, Y1, cy, gy, ncy, &r0, &nrows);
+        uint2 v = make_uint2(0u, 0u);
+        if (r < nrows) {
+          int K = (int)floor((double)cut_x(q, nx, Q) - cx - kColEps) - gx;
+          K = min(max(K, 0), ncx - 1);
+          const uint32_t *orow = off + (int64_t)(r0 + r) * ncx;
+          v.x = ldg(orow + K);
+          v.y = ldg(orow + min(K + 2, ncx));
+        }
+        plan[sl * PE + r * (Q + 1) + q] = v;
+      }
+      if (!DIRECT) __syncthreads();
+
+      // ---- bricks of each stripe (every thread takes the same decisions)
+      for (int sl = 0; sl < gn; ++sl) {
+        const int SY0 = (s0 + sl) * BY, SY1 = min(SY0 + BY, ny);
+        int sr0 = 0, snrows = 0;
+        uint32_t bst = 0, bend = 0;  // DIRECT: the stripe's bucket
+        if (DIRECT) {
+          bst = soff[s0 + sl];
+          bend = soff[s0 + sl + 1];
+          if (bend == bst) continue;
+        } else {
+          rows_for(SY0, SY1, cy, gy, ncy, &sr0, &snrows);
+          if (snrows <= 0) continue;
+        }
+        const uint2 *ps = plan + sl * PE;
+        int qa = 0;
+        while (qa < Q) {
+          int qe = Q;
+          for (;;) {
+            const bool whole = qe > qa;  // false: piece qa voxel row by voxel row
+            const int qend = whole ? qe : qa + 1;
+            const int X0 = cut_x(qa, nx, Q), X1 = cut_x(qend, nx, Q);
+            const int nsub = whole ? 1 : (SY1 - SY0);
+            bool all_ok = true;
+            for (int sub = 0; sub < nsub; ++sub) {
+              const int Y0 = whole ? SY0 : SY0 + sub, Y1 = whole ? SY1 : Y0 + 1;
+              int ra = 0, nr = snrows;
+              if (!whole && !DIRECT) {
+                int rr0, rn;
+                rows_for(Y0, Y1, cy, gy, ncy, &rr0, &rn);
+                ra = rr0 - sr0;
+                nr = rn;
+              }
+              // this brick's candidate rows, one per lane: start, length, chunk prefix
+              uint32_t my_st = 0, my_len = 0;
+              if (lane < nr) {
+                my_st = ps[(ra + lane) * (Q + 1) + qa].x;
+                my_len = ps[(ra + lane) * (Q + 1) + qend].y - my_st;
+              }
+              const uint32_t my_c = (my_len + 63u) >> 6;
+              uint32_t inc = my_c;
+  #pragma unroll
+              for (int o = 1; o < 64; o <<= 1) {
+                const uint32_t t = __shfl_up(inc, o, 64);
+                if (lane >= o) inc += t;
+              }
+              const uint32_t my_cpre = inc - my_c;
+              const int nch = DIRECT ? (int)((bend - bst + 63u) >> 6)
+                                     : (nr > 0 ? (int)__shfl(inc, nr - 1, 64) : 0);
+              if (nch == 0) continue;
+              const int p = parity;
+              unsigned long long bnear = 0;
+              // a brick with at most a quarter of the slots in voxels always has an
+              // empty slot: it probes without limit and cannot overflow (single
+              // voxel rows of a piece are always such bricks)
+              const bool fits = (int64_t)(X1 - X0) * (Y1 - Y0) * nz <= cfg.load_max;
+              const int max_probe = fits ? cap : kMaxProbe;
+              // chunk k -> candidate of this lane.  A row of len candidates takes
+              // c = ceil(len/64) chunks; its candidates are cut into 4 runs of 16*c and
+              // step j of the row gives lane l candidate (l/16)*16c + 16j + l%16:
+              // 4 cache lines per load as for 64 consecutive candidates, but lanes of
+              // one step lie in 4 different parts of the row, which spreads the hot
+              // voxels (dense ground near the sensor) over fewer lanes per atomic.
+              auto chunk_idx = [&](int k, bool *valid) -> uint32_t {
+                const unsigned long long mk = __ballot(lane < nr && my_cpre <= (uint32_t)k);
+                const int row = __popcll(mk) - 1;
+                const uint32_t st = __builtin_amdgcn_readlane(my_st, row);
+                const uint32_t len = __builtin_amdgcn_readlane(my_len, row);
+                const uint32_t cpre = __builtin_amdgcn_readlane(my_cpre, row);
+                const uint32_t c = (len + 63u) >> 6;
+                const uint32_t j = (uint32_t)k - cpre;
+                const uint32_t off_in_row = ((uint32_t)lane >> 4) * (c << 4) + (j << 4) +
+                                            ((uint32_t)lane & 15u);
+                *valid = off_in_row < len;
+                return st + off_in_row;
+              };
+              // Four candidates per lane, branch-free up to the rare collisions:
+              // find or claim each in-brick candidate's slot, then add its sums.
+              auto insert4 = [&](bool (&inb)[4], const uint32_t (&key)[4],
+                                 const uint32_t (&q)[4]) {
+                uint32_t h[4];
+  #pragma unroll
+                for (int i = 0; i < 4; ++i) h[i] = (key[i] * 2654435761u) >> (32 - cfg.cap_log2);
+                uint32_t k0[4];
+  #pragma unroll
+                for (int i = 0; i < 4; ++i) k0[i] = __atomic_load_n(&hkey[h[i]], __ATOMIC_RELAXED);
+                bool coll[4], fresh[4];
+  #pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                  // masked lanes swap on their own dummy word with a value that never matches
+                  const bool want = inb[i] && k0[i] == kEmpty;
+                  uint32_t *a = want ? &hkey[h[i]] : &dkey[lane];
+                  const uint32_t old = atomicCAS(a, want ? kEmpty : kNever, key[i]);
+                  const bool got = want ? (old == kEmpty || old == key[i]) : (k0[i] == key[i]);
+                  fresh[i] = want && old == kEmpty;
+                  coll[i] = inb[i] && !got;
+                }
+                if (coll[0] || coll[1] || coll[2] || coll[3]) {
+  #pragma unroll
+                  for (int i = 0; i < 4; ++i) {
+                    if (!coll[i]) continue;
+                    uint32_t hh = h[i];
+                    bool ok = false;
+                    for (int pr = 1; pr < max_probe; ++pr) {
+                      hh = (hh + 1u) & (uint32_t)(cap - 1);
+                      uint32_t k1 = __atomic_load_n(&hkey[hh], __ATOMIC_RELAXED);
+                      if (k1 == kEmpty) {
+                        k1 = atomicCAS(&hkey[hh], kEmpty, key[i]);
+                        if (k1 == kEmpty) fresh[i] = true;
+                      }
+                      if (k1 == kEmpty || k1 == key[i]) { ok = true; break; }
+                    }
+                    if (ok) h[i] = hh;
+                    else { ovf[p] = 1u; inb[i] = false; }
+                  }
+                }
+                // newly claimed slots go on the brick's occupied list (one LDS atomic per wave)
+                {
+                  unsigned long long m[4];
+                  uint32_t tot = 0;
+  #pragma unroll
+                  for (int i = 0; i < 4; ++i) {
+                    m[i] = __ballot(fresh[i]);
+                    tot += (uint32_t)__popcll(m[i]);
+                  }
+                  if (tot) {
+                    uint32_t base = 0;
+                    if (lane == 0) base = atomicAdd(&occn[p], tot);
+                    base = __shfl(base, 0, 64);
+  #pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+                      if (fresh[i]) {
+                        const uint32_t r = __builtin_amdgcn_mbcnt_hi(
+                            (uint32_t)(m[i] >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m[i], 0u));
+                        occ[base + r] = (uint16_t)h[i];
+                      }
+                      base += (uint32_t)__popcll(m[i]);
+                    }
+                  }
+                }
+  #pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                  if (ZVAR) {
+                    unsigned long long *a1 = inb[i] ? &hv1[h[i]] : &dval[lane];
+                    unsigned long long *a2 = inb[i] ? &hv2[h[i]] : &dval[64 + lane];
+                    atomicAdd(a1, (1ull << 44) | (unsigned long long)q[i]);
+                    atomicAdd(a2, (unsigned long long)q[i] * q[i]);
+                  } else {
+                    atomicAdd(inb[i] ? &hcnt[h[i]] : &dkey[lane], 1u);
+                  }
+                }
+              };
+              // Frame candidates: u = fl(v + c), voxel floor(u), in-brick test.
+              auto step4 = [&](const bool (&val)[4], const double (&vx)[4], const double (&vy)[4],
+                               const double (&vz)[4]) {
+                bool inb[4];
+                uint32_t key[4], q[4];
+  #pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                  const double ux = vx[i] + cx, uy = vy[i] + cy, uz = vz[i] + cz;
+                  const double fx = floor(ux), fy = floor(uy), fz = floor(uz);
+                  // v_cvt_i32_f64 saturates, so far-away points stay out of range
+                  const int ix = (int)fx, iy = (int)fy, iz = (int)fz;
+                  inb[i] = val[i] && (uint32_t)(ix - X0) < (uint32_t)(X1 - X0) &&
+                           (uint32_t)(iy - Y0) < (uint32_t)(Y1 - Y0) && (uint32_t)iz < (uint32_t)nz;
+                  key[i] = ((uint32_t)iz << (kxb + kyb)) | ((uint32_t)(iy - SY0) << kxb) |
+                           (uint32_t)ix;
+                  q[i] = ZVAR ? (uint32_t)floor((uz - fz) * kQScale) : 0u;
+                  if (NEAR && inb[i] && ix >= alo0 && ix <= ahi0 && iy >= alo1 && iy <= ahi1 &&
+                      iz >= alo2 && iz <= ahi2) {
+                    double d = 1.0;
+                    const double fr[3] = {ux - fx, uy - fy, uz - fz};
+  #pragma unroll
+                    for (int a = 0; a < 3; ++a) {
+                      const double up = 1.0 - fr[a];
+                      const double m = fr[a] < up ? fr[a] : up;
+                      if (m < d) d = m;
+                    }
+                    if (d * P.voxel < kNearFace) ++bnear;
+                  }
+                }
+                insert4(inb, key, q);
+              };
+              // Four chunks per wave step: the twelve loads are issued together, then
+              // the four candidates of each lane go through step4 together.  Lanes
+              // past a row's end load index 0 (always valid) and are masked off.
+              for (int k = wid; DIRECT && k < nch; k += 4 * W) {
+                // bucketed (key, q) pairs of the stripe, 64 consecutive per chunk
+                bool inb[4];
+                uint32_t key[4], q[4];
+  #pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                  const uint32_t idx = bst + (uint32_t)(k + i * W) * 64u + (uint32_t)lane;
+                  const bool val = k + i * W < nch && idx < bend;
+                  const unsigned long long e =
+                      ldg((const unsigned long long *)(mine + (val ? idx : bst)));
+                  key[i] = (uint32_t)e;
+                  q[i] = (uint32_t)(e >> 32);
+                }
+  #pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                  const uint32_t idx = bst + (uint32_t)(k + i * W) * 64u + (uint32_t)lane;
+                  const bool val = k + i * W < nch && idx < bend;
+                  const int ix = (int)(key[i] & kxm);
+                  const int iy = SY0 + (int)((key[i] >> kxb) & kym);
+                  inb[i] = val && (uint32_t)(ix - X0) < (uint32_t)(X1 - X0) &&
+                           (uint32_t)(iy - Y0) < (uint32_t)(Y1 - Y0);
+                }
+                insert4(inb, key, q);
+              }
+              for (int k = wid; !DIRECT && k < nch; k += 4 * W) {
+                bool v[4];
+                uint32_t ii[4];
+                ii[0] = chunk_idx(k, &v[0]);
+  #pragma unroll
+                for (int i = 1; i < 4; ++i) {
+                  v[i] = false;
+                  ii[i] = 0u;
+                  if (k + i * W < nch) ii[i] = chunk_idx(k + i * W, &v[i]);
+                }
+                double x[4], y[4], z[4];
+  #pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                  const uint32_t j = v[i] ? ii[i] : 0u;
+                  x[i] = ldg(fvx + j);
+                  y[i] = ldg(fvy + j);
+                  z[i] = ldg(fvz + j);
+                }
+                step4(v, x, y, z);
+              }
+              __syncthreads();
+              const bool overflow = ovf[p] != 0u;
+              const int nocc = (int)occn[p];
+              if (tid == 0) { ovf[p ^ 1] = 0u; occn[p ^ 1] = 0u; }
+              int blo0 = nx, blo1 = ny, blo2 = nz, bhi0 = -1, bhi1 = -1, bhi2 = -1;
+              unsigned long long bnin = 0;
+              for (int i = tid; i < nocc; i += T) {
+                const uint32_t h = occ[i];
+                const uint32_t key = hkey[h];
+                const int ix = (int)(key & kxm);
+                const int iy = SY0 + (int)((key >> kxb) & kym);
+                const int iz = (int)(key >> (kxb + kyb));
+                uint32_t n;
+                unsigned long long s1 = 0, s2 = 0;
+                if (ZVAR) {
+                  const unsigned long long a = hv1[h];
+                  n = (uint32_t)(a >> 44);
+                  s1 = a & ((1ull << 44) - 1);
+                  s2 = hv2[h];
+                  hv1[h] = 0ull;
+                  hv2[h] = 0ull;
+                } else {
+                  n = hcnt[h];
+                  hcnt[h] = 0u;
+                }
+                hkey[h] = kEmpty;
+                bnin += n;
+                blo0 = min(blo0, ix); blo1 = min(blo1, iy); blo2 = min(blo2, iz);
+                bhi0 = max(bhi0, ix); bhi1 = max(bhi1, iy); bhi2 = max(bhi2, iz);
+                if (!overflow && ix >= alo0 && ix <= ahi0 && iy >= alo1 && iy <= ahi1 &&
+                    iz >= alo2 && iz <= ahi2) {
+                  const int64_t lin = ((int64_t)iz * ny + iy) * nx + ix;
+                  {
+                    const int a = ldg(binA0 + lin);
+                    const int b = kind0 == MI_FEAT_COUNT ? bin_count_dev(n, nb0, cedge)
+                                                         : bin_zvar_dev(n, s1, s2, nb0, zedge);
+                    atomicAdd(&myhist[a * nb0 + b], 1u);
+                  }
+                  if (nf > 1) {
+                    const int a = ldg(binA1 + lin);
+                    const int b = kind1 == MI_FEAT_COUNT ? bin_count_dev(n, nb1, cedge)
+                                                         : bin_zvar_dev(n, s1, s2, nb1, zedge);
+                    atomicAdd(&myhist[hoff1 + a * nb1 + b], 1u);
+                  }
+                }
+              }
+              __syncthreads();
+              parity ^= 1;
+              if (overflow) {
+                all_ok = false;
+                break;
+              }
+              nin += bnin;
+              nnear += bnear;
+              lo0 = min(lo0, blo0); lo1 = min(lo1, blo1); lo2 = min(lo2, blo2);
+              hi0 = max(hi0, bhi0); hi1 = max(hi1, bhi1); hi2 = max(hi2, bhi2);
+            }
+            if (all_ok) { qa = qend; break; }
+            // overflow: halve the run of pieces; a single piece goes row by row
+            qe = qe - qa > 1 ? qa + (qe - qa) / 2 : qa;
+          }
+        }
+      }
+      __syncthreads();
+    }
+
+    // ---------------------------------------------------------- pose reduction
+    lo0 = wave_min_i32(lo0); lo1 = wave_min_i32(lo1); lo2 = wave_min_i32(lo2);
+    hi0 = wave_max_i32(hi0); hi1 = wave_max_i32(hi1); hi2 = wave_max_i32(hi2);
+    nin = wave_sum_u64(nin);
+    if (NEAR) nnear = wave_sum_u64(nnear);
+    if (lane == 0) {
+      int *b = wbox + 8 * wid;
+      b[0] = lo0; b[1] = lo1; b[2] = lo2; b[3] = hi0; b[4] = hi1; b[5] = hi2;
+      wcnt[2 * wid] = nin;
+      wcnt[2 * wid + 1] = nnear;
+    }
+    __syncthreads();
+    if (cfg.hist_copies > 1) {
+      for (int i = tid; i < cfg.hist_words; i += T) {
+        uint32_t s = 0;
+        for (int d = 1; d < cfg.hist_copies; ++d) s += hist[d * cfg.hist_words + i];
+        hist[i] += s;
+      }
+    }
+    int blo[3] = {nx, ny, nz}, bhi[3] = {-1, -1, -1};
+    unsigned long long n_in = 0, n_near = 0;
+    for (int w = 0; w < W; ++w) {
+      const int *b = wbox + 8 * w;
+      for (int a = 0; a < 3; ++a) {
+        blo[a] = min(blo[a], b[a]);
+        bhi[a] = max(bhi[a], b[3 + a]);
+      }
+      n_in += wcnt[2 * w];
+      n_near += wcnt[2 * w + 1];
+    }
+    const int dims[3] = {nx, ny, nz};
+    const int alo[3] = {alo0, alo1, alo2}, ahi[3] = {ahi0, ahi1, ahi2};
+    int olo[3], ohi[3];
+    bool nonempty = true;
+    int64_t nO = 1;
+    for (int a = 0; a < 3; ++a) {
+      olo[a] = max(max(alo[a], blo[a]), 0);
+      ohi[a] = min(min(ahi[a], bhi[a]), dims[a] - 1);
+      if (ohi[a] < olo[a]) nonempty = false;
+      else nO *= (int64_t)(ohi[a] - olo[a] + 1);
+    }
+    if (!nonempty) nO = 0;
+    __syncthreads();
+
+    if (nonempty) {
+      const int64_t plane = (int64_t)(nx + 1) * (ny + 1) * (nz + 1);
+      for (int t = tid; t < nf * 64; t += T) {
+        const int f = t >> 6, a = t & 63;
+        if (a >= 1 && a < P.nb[f])
+          cntA[t] = sat_box(P.sat[f] + (int64_t)(a - 1) * plane, nx, ny, olo[0], olo[1], olo[2],
+                            ohi[0], ohi[1], ohi[2]);
+      }
+    }
+    __syncthreads();
+    if (nonempty) {
+      for (int t = tid; t < nf * 64; t += T) {
+        const int f = t >> 6, a = t & 63, nb = P.nb[f];
+        if (a >= 1 && a < nb) {
+          uint32_t *row = hist + (f ? hoff1 : 0) + a * nb;
+          uint32_t rs = 0;
+          for (int b = 1; b < nb; ++b) rs += row[b];
+          row[0] = cntA[t] - rs;
         }
       }
     }
     __syncthreads();
-  }
+    if (nonempty && tid < nf) {
+      const int f = tid, nb = P.nb[f];
+      uint32_t *H = hist + (f ? hoff1 : 0);
+      int64_t rest = nO;
+      for (int a = 1; a < nb; ++a) rest -= cntA[(f << 6) + a];
+      for (int b = 1; b < nb; ++b) rest -= H[b];
+      H[0] = (uint32_t)rest;
+    }
+    __syncthreads();
 
-  // ---------------------------------------------------------- pose reduction
-  lo0 = wave_min_i32(lo0); lo1 = wave_min_i32(lo1); lo2 = wave_min_i32(lo2);
-  hi0 = wave_max_i32(hi0); hi1 = wave_max_i32(hi1); hi2 = wave_max_i32(hi2);
-  nin = wave_sum_u64(nin);
-  if (NEAR) nnear = wave_sum_u64(nnear);
-  if (lane == 0) {
-    int *b = wbox + 8 * wid;
-    b[0] = lo0; b[1] = lo1; b[2] = lo2; b[3] = hi0; b[4] = hi1; b[5] = hi2;
-    wcnt[2 * wid] = nin;
-    wcnt[2 * wid + 1] = nnear;
-  }
-  __syncthreads();
-  if (cfg.hist_copies > 1) {
-    for (int i = tid; i < cfg.hist_words; i += T) {
-      uint32_t s = 0;
-      for (int d = 1; d < cfg.hist_copies; ++d) s += hist[d * cfg.hist_words + i];
-      hist[i] += s;
-    }
-  }
-  int blo[3] = {nx, ny, nz}, bhi[3] = {-1, -1, -1};
-  unsigned long long n_in = 0, n_near = 0;
-  for (int w = 0; w < W; ++w) {
-    const int *b = wbox + 8 * w;
-    for (int a = 0; a < 3; ++a) {
-      blo[a] = min(blo[a], b[a]);
-      bhi[a] = max(bhi[a], b[3 + a]);
-    }
-    n_in += wcnt[2 * w];
-    n_near += wcnt[2 * w + 1];
-  }
-  const int dims[3] = {nx, ny, nz};
-  const int alo[3] = {alo0, alo1, alo2}, ahi[3] = {ahi0, ahi1, ahi2};
-  int olo[3], ohi[3];
-  bool nonempty = true;
-  int64_t nO = 1;
-  for (int a = 0; a < 3; ++a) {
-    olo[a] = max(max(alo[a], blo[a]), 0);
-    ohi[a] = min(min(ahi[a], bhi[a]), dims[a] - 1);
-    if (ohi[a] < olo[a]) nonempty = false;
-    else nO *= (int64_t)(ohi[a] - olo[a] + 1);
-  }
-  if (!nonempty) nO = 0;
-  __syncthreads();
-
-  if (nonempty) {
-    const int64_t plane = (int64_t)(nx + 1) * (ny + 1) * (nz + 1);
-    for (int t = tid; t < nf * 64; t += T) {
-      const int f = t >> 6, a = t & 63;
-      if (a >= 1 && a < P.nb[f])
-        cntA[t] = sat_box(P.sat[f] + (int64_t)(a - 1) * plane, nx, ny, olo[0], olo[1], olo[2],
-                          ohi[0], ohi[1], ohi[2]);
-    }
-  }
-  __syncthreads();
-  if (nonempty) {
-    for (int t = tid; t < nf * 64; t += T) {
-      const int f = t >> 6, a = t & 63, nb = P.nb[f];
-      if (a >= 1 && a < nb) {
-        uint32_t *row = hist + (f ? hoff1 : 0) + a * nb;
-        uint32_t rs = 0;
-        for (int b = 1; b < nb; ++b) rs += row[b];
-        row[0] = cntA[t] - rs;
+    if (wid < nf) {
+      const int f = wid, nb = P.nb[f];
+      const uint32_t *H = hist + (f ? hoff1 : 0);
+      double hxy = 0.0, hx = 0.0, hy = 0.0;
+      if (nonempty) {
+        const double N = (double)nO;
+        for (int i = lane; i < nb * nb; i += 64) hxy += plogp_term(H[i], N);
+        if (lane < nb) {
+          uint64_t r = 0, c = 0;
+          for (int b = 0; b < nb; ++b) r += H[lane * nb + b];
+          for (int a = 0; a < nb; ++a) c += H[a * nb + lane];
+          hx = plogp_term(r, N);
+          hy = plogp_term(c, N);
+        }
+      }
+      hxy = wave_sum_f64(hxy);
+      hx = wave_sum_f64(hx);
+      hy = wave_sum_f64(hy);
+      if (lane == 0) P.mi_out[(int64_t)f * P.K + pose.out_index] = nonempty ? (hx + hy) - hxy : 0.0;
+      if (P.hist_out) {
+        uint32_t *dst = P.hist_out + P.hist_off[f] + (int64_t)pose.out_index * nb * nb;
+        for (int i = lane; i < nb * nb; i += 64) dst[i] = nonempty ? H[i] : 0u;
       }
     }
-  }
-  __syncthreads();
-  if (nonempty && tid < nf) {
-    const int f = tid, nb = P.nb[f];
-    uint32_t *H = hist + (f ? hoff1 : 0);
-    int64_t rest = nO;
-    for (int a = 1; a < nb; ++a) rest -= cntA[(f << 6) + a];
-    for (int b = 1; b < nb; ++b) rest -= H[b];
-    H[0] = (uint32_t)rest;
-  }
-  __syncthreads();
-
-  if (wid < nf) {
-    const int f = wid, nb = P.nb[f];
-    const uint32_t *H = hist + (f ? hoff1 : 0);
-    double hxy = 0.0, hx = 0.0, hy = 0.0;
-    if (nonempty) {
-      const double N = (double)nO;
-      for (int i = lane; i < nb * nb; i += 64) hxy += plogp_term(H[i], N);
-      if (lane < nb) {
-        uint64_t r = 0, c = 0;
-        for (int b = 0; b < nb; ++b) r += H[lane * nb + b];
-        for (int a = 0; a < nb; ++a) c += H[a * nb + lane];
-        hx = plogp_term(r, N);
-        hy = plogp_term(c, N);
-      }
+    if (P.stats_out && tid == 0) {
+      mi_pose_stats st;
+      for (int a = 0; a < 3; ++a) { st.lo[a] = olo[a]; st.hi[a] = ohi[a]; }
+      const unsigned long long nnf = *P.nonfinite;
+      st.n_overlap = nO;
+      st.n_in_grid = (int64_t)n_in;
+      st.n_nonfinite = (int64_t)nnf;
+      st.n_out_of_grid = P.n_b - (int64_t)nnf - (int64_t)n_in;
+      st.n_near_face = NEAR ? (int64_t)n_near : 0;
+      P.stats_out[pose.out_index] = st;
     }
-    hxy = wave_sum_f64(hxy);
-    hx = wave_sum_f64(hx);
-    hy = wave_sum_f64(hy);
-    if (lane == 0) P.mi_out[(int64_t)f * P.K + pose.out_index] = nonempty ? (hx + hy) - hxy : 0.0;
-    if (P.hist_out) {
-      uint32_t *dst = P.hist_out + P.hist_off[f] + (int64_t)pose.out_index * nb * nb;
-      for (int i = lane; i < nb * nb; i += 64) dst[i] = nonempty ? H[i] : 0u;
-    }
-  }
-  if (P.stats_out && tid == 0) {
-    mi_pose_stats st;
-    for (int a = 0; a < 3; ++a) { st.lo[a] = olo[a]; st.hi[a] = ohi[a]; }
-    const unsigned long long nnf = *P.nonfinite;
-    st.n_overlap = nO;
-    st.n_in_grid = (int64_t)n_in;
-    st.n_nonfinite = (int64_t)nnf;
-    st.n_out_of_grid = P.n_b - (int64_t)nnf - (int64_t)n_in;
-    st.n_near_face = NEAR ? (int64_t)n_near : 0;
-    P.stats_out[pose.out_index] = st;
+    __syncthreads();  // LDS (histograms, counters) is reused by the next item
   }
 }
 
@@ -549,10 +710,11 @@ size_t eval_lds_bytes(const EvalLaunch &c) {
       .total;
 }
 
-template <bool NEAR, bool ZVAR>
+template <bool NEAR, bool ZVAR, bool DIRECT>
 static hipError_t launch_one(const PairDev *pairs_dev, const FrameDev *frames_dev,
-                             const PoseDev *items_dev, int64_t n_items, const EvalLaunch &c,
-                             hipStream_t s) {
+                             const PoseDev *items_dev, int64_t n_items, const int64_t *xcd_start,
+                             const EvalLaunch &c, uint2 *scratch, int64_t scratch_stride,
+                             int64_t max_wgs, hipStream_t s) {
   const Layout L = eval_layout(c.waves, c.hist_copies, c.hist_words, c.plan_bytes,
                                1 << c.cap_log2, c.zvar);
   EvalCfgDev d;
@@ -566,26 +728,85 @@ static hipError_t launch_one(const PairDev *pairs_dev, const FrameDev *frames_de
   d.off_plan = L.off_plan;
   d.off_hash = L.off_hash;
   d.pad = 0;
-  const int64_t per_xcd = (n_items + kXcds - 1) / kXcds;
-  const int64_t grid = per_xcd * kXcds;
-  if (grid > 0x7fffffff) return hipErrorInvalidValue;
-  hipError_t e = hipFuncSetAttribute((const void *)k_eval<NEAR, ZVAR>,
+  // runs per XCD: the caller's split, else equal counts
+  int64_t longest = 0;
+  for (int x = 0; x <= kXcds; ++x)
+    d.xcd_start[x] = xcd_start ? xcd_start[x] : std::min<int64_t>(n_items, x * ((n_items + kXcds - 1) / kXcds));
+  for (int x = 0; x < kXcds; ++x) {
+    if (d.xcd_start[x] > d.xcd_start[x + 1] || d.xcd_start[x + 1] > n_items) return hipErrorInvalidValue;
+    longest = std::max(longest, d.xcd_start[x + 1] - d.xcd_start[x]);
+  }
+  if (d.xcd_start[0] != 0 || d.xcd_start[kXcds] != n_items) return hipErrorInvalidValue;
+  hipError_t e = hipFuncSetAttribute((const void *)k_eval<NEAR, ZVAR, DIRECT>,
                                      hipFuncAttributeMaxDynamicSharedMemorySize, L.total);
   if (e != hipSuccess) return e;
-  k_eval<NEAR, ZVAR><<<(unsigned)grid, c.waves * 64, (size_t)L.total, s>>>(
-      pairs_dev, frames_dev, items_dev, n_items, per_xcd, d);
+  int64_t wpx = std::max<int64_t>(1, longest);  // workgroups per XCD
+  if (max_wgs > 0) wpx = std::max<int64_t>(1, std::min<int64_t>(wpx, max_wgs / kXcds));
+  const int64_t grid = wpx * kXcds;
+  if (grid > 0x7fffffff) return hipErrorInvalidValue;
+  k_eval<NEAR, ZVAR, DIRECT><<<(unsigned)grid, c.waves * 64, (size_t)L.total, s>>>(
+      pairs_dev, frames_dev, items_dev, d, scratch, scratch_stride);
   return hipGetLastError();
 }
 
+// Workgroups of a persistent grid for this launch shape: the compute units
+// times the resident workgroups per unit (at most per_cu), a multiple of the
+// XCD count.
+hipError_t eval_resident_wgs(const EvalLaunch &c, int per_cu, int64_t *out) {
+  const Layout L = eval_layout(c.waves, c.hist_copies, c.hist_words, c.plan_bytes,
+                               1 << c.cap_log2, c.zvar);
+  hipError_t e;
+  int dev = 0, cus = 0, occ = 0;
+  if ((e = hipGetDevice(&dev)) != hipSuccess) return e;
+  if ((e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess)
+    return e;
+  const void *fn = (const void *)k_eval<false, false, true>;
+  if (c.zvar) fn = (const void *)k_eval<false, true, true>;
+  if ((e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, L.total)) !=
+      hipSuccess)
+    return e;
+  if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, fn, c.waves * 64, (size_t)L.total)) !=
+      hipSuccess)
+    return e;
+  const int64_t per = std::max(1, std::min(occ, per_cu));
+  *out = std::max<int64_t>(kXcds, ((int64_t)cus * per / kXcds) * kXcds);
+  return hipSuccess;
+}
+
 hipError_t launch_eval(const PairDev *pairs_dev, const FrameDev *frames_dev,
-                       const PoseDev *items_dev, int64_t n_items, const EvalLaunch &c,
-                       hipStream_t s) {
+                       const PoseDev *items_dev, int64_t n_items, const int64_t *xcd_start,
+                       const EvalLaunch &c, hipStream_t s) {
+  if (n_items <= 0) return hipSuccess;
+  int64_t max_wgs = 0;
+  if (c.wgs_per_cu > 0) {
+    hipError_t e = eval_resident_wgs(c, c.wgs_per_cu, &max_wgs);
+    if (e != hipSuccess) return e;
+  }
+  if (c.near_face)
+    return c.zvar ? launch_one<true, true, false>(pairs_dev, frames_dev, items_dev, n_items,
+                                                  xcd_start, c, nullptr, 0, max_wgs, s)
+                  : launch_one<true, false, false>(pairs_dev, frames_dev, items_dev, n_items,
+                                                   xcd_start, c, nullptr, 0, max_wgs, s);
+  return c.zvar ? launch_one<false, true, false>(pairs_dev, frames_dev, items_dev, n_items,
+                                                 xcd_start, c, nullptr, 0, max_wgs, s)
+                : launch_one<false, false, false>(pairs_dev, frames_dev, items_dev, n_items,
+                                                  xcd_start, c, nullptr, 0, max_wgs, s);
+}
+
+hipError_t launch_eval_direct(const PairDev *pairs_dev, const FrameDev *frames_dev,
+                              const PoseDev *items_dev, int64_t n_items, const int64_t *xcd_start,
+                              const EvalLaunch &c, uint2 *scratch, int64_t scratch_stride,
+                              int64_t slots, hipStream_t s) {
   if (n_items <= 0) return hipSuccess;
   if (c.near_face)
-    return c.zvar ? launch_one<true, true>(pairs_dev, frames_dev, items_dev, n_items, c, s)
-                  : launch_one<true, false>(pairs_dev, frames_dev, items_dev, n_items, c, s);
-  return c.zvar ? launch_one<false, true>(pairs_dev, frames_dev, items_dev, n_items, c, s)
-                : launch_one<false, false>(pairs_dev, frames_dev, items_dev, n_items, c, s);
+    return c.zvar ? launch_one<true, true, true>(pairs_dev, frames_dev, items_dev, n_items,
+                                                 xcd_start, c, scratch, scratch_stride, slots, s)
+                  : launch_one<true, false, true>(pairs_dev, frames_dev, items_dev, n_items,
+                                                  xcd_start, c, scratch, scratch_stride, slots, s);
+  return c.zvar ? launch_one<false, true, true>(pairs_dev, frames_dev, items_dev, n_items,
+                                                xcd_start, c, scratch, scratch_stride, slots, s)
+                : launch_one<false, false, true>(pairs_dev, frames_dev, items_dev, n_items,
+                                                 xcd_start, c, scratch, scratch_stride, slots, s);
 }
 
 }  // namespace mi

@@ -6,6 +6,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <chrono>
 #include <deque>
 #include <map>
@@ -145,6 +146,7 @@ struct Tuning {
   int32_t hash_bytes = 48 * 1024;
   int32_t hist_copies = 2;
   int32_t stripe_rows = 8;
+  int32_t wgs_per_cu = 0;
 };
 Tuning g_tuning;
 std::mutex g_tuning_mu;
@@ -171,11 +173,13 @@ extern "C" mi_status mi_tuning_set(const mi_tuning *t) {
     return fail(MI_E_INVALID, "hash_bytes must be in [1 KiB, 160 KiB]");
   if (t->hist_copies < 1 || t->hist_copies > 8) return fail(MI_E_INVALID, "hist_copies 1..8");
   if (t->stripe_rows < 1 || t->stripe_rows > 62) return fail(MI_E_INVALID, "stripe_rows 1..62");
+  if (t->wgs_per_cu < 0 || t->wgs_per_cu > 16) return fail(MI_E_INVALID, "wgs_per_cu 0..16");
   std::lock_guard<std::mutex> lk(g_tuning_mu);
   g_tuning.waves = t->waves;
   g_tuning.hash_bytes = t->hash_bytes;
   g_tuning.hist_copies = t->hist_copies;
   g_tuning.stripe_rows = t->stripe_rows;
+  g_tuning.wgs_per_cu = t->wgs_per_cu;
   return MI_OK;
 }
 
@@ -186,6 +190,7 @@ extern "C" mi_status mi_tuning_get(mi_tuning *t) {
   t->hash_bytes = g_tuning.hash_bytes;
   t->hist_copies = g_tuning.hist_copies;
   t->stripe_rows = g_tuning.stripe_rows;
+  t->wgs_per_cu = g_tuning.wgs_per_cu;
   return MI_OK;
 }
 
@@ -651,6 +656,12 @@ struct mi_plan {
   std::vector<int64_t> chunk_max_n;  // most points of a frame in the chunk
   std::vector<int64_t> chunk_point_poses;
   std::vector<uint32_t *> chunk_cur; // contiguous column cursors of each chunk's frames
+  std::vector<std::array<int64_t, kXcds + 1>> chunk_xcd;  // runs per XCD within each chunk
+  std::array<int64_t, kXcds + 1> direct_xcd;              // and within the per-pose items
+  int64_t n_frame_items;             // items [n_frame_items, n_items) are per-pose
+  int64_t direct_point_poses;
+  uint2 *scratch;                    // per-pose buckets: slots x stride
+  int64_t scratch_stride, scratch_slots;
   PoseDev *items_dev;
   PairDev *pairs_dev;
   FrameDev *frames_dev;
@@ -661,6 +672,23 @@ struct mi_plan {
 namespace {
 
 size_t al256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+// Items [i0, i1) regrouped by XCD: frame f goes to XCD f % kXcds, so every
+// XCD gets an even share of every pair's frames (and a frame's poses stay on
+// one XCD, whose L2 then holds it); within an XCD the items keep their order.
+// out[x] .. out[x + 1] (relative to i0) is XCD x's run.
+void group_by_xcd(std::vector<PoseDev> &items, int64_t i0, int64_t i1,
+                  std::array<int64_t, kXcds + 1> &out) {
+  std::array<int64_t, kXcds + 1> cnt;
+  cnt.fill(0);
+  for (int64_t k = i0; k < i1; ++k) ++cnt[(size_t)(items[(size_t)k].frame % kXcds) + 1];
+  out[0] = 0;
+  for (int x = 0; x < kXcds; ++x) out[(size_t)x + 1] = out[(size_t)x] + cnt[(size_t)x + 1];
+  std::array<int64_t, kXcds> pos;
+  for (int x = 0; x < kXcds; ++x) pos[(size_t)x] = out[(size_t)x];
+  std::vector<PoseDev> tmp(items.begin() + i0, items.begin() + i1);
+  for (const PoseDev &it : tmp) items[(size_t)(i0 + pos[(size_t)(it.frame % kXcds)]++)] = it;
+}
 
 // Device bytes of one frame inside a chunk's storage: rotated points, column
 // offsets, and the frame's share of the chunk's contiguous cursor region.
@@ -678,16 +706,24 @@ FrameBytes frame_bytes(int64_t n_b, int64_t ncols) {
 struct BatchTables {
   std::vector<PoseTables> T;
   std::vector<StripeShape> SS;
-  std::vector<int32_t> frame_base;   // [pairs + 1]
+  std::vector<char> direct;          // per pair: per-pose bucketing instead of frames
+  std::vector<int32_t> frame_start;  // per pair: first entry in the frame table
   EvalLaunch L;
   int64_t n_items = 0;
-  int32_t F = 0;
+  int64_t n_frame_items = 0;         // items of frame-mode pairs (they come first)
+  int32_t F = 0;                     // frame table entries
+  int32_t F_built = 0;               // entries of frame-mode pairs (built; they come first)
+  int64_t scratch_stride = 0;        // largest n_b of a per-pose pair
+  int64_t scratch_slots = 0;         // workgroups of the per-pose launch
 };
 
 mi_status prepare_batch(const mi_work_item *w, int64_t n, uint32_t flags, BatchTables &B) {
   if (n < 0 || (n > 0 && !w)) return fail(MI_E_INVALID, "bad work item list");
   if (n >= ((int64_t)1 << 20)) return fail(MI_E_UNSUPPORTED, "more than 2^20 work items");
-  if (flags & ~(uint32_t)MI_EVAL_NEAR_FACE) return fail(MI_E_INVALID, "unknown flags");
+  if (flags & ~(uint32_t)(MI_EVAL_NEAR_FACE | MI_EVAL_PER_POSE | MI_EVAL_SHARED_FRAMES))
+    return fail(MI_E_INVALID, "unknown flags");
+  if ((flags & MI_EVAL_PER_POSE) && (flags & MI_EVAL_SHARED_FRAMES))
+    return fail(MI_E_INVALID, "MI_EVAL_PER_POSE and MI_EVAL_SHARED_FRAMES exclude each other");
   bool zvar = false;
   int hist_words = 1;
   for (int64_t i = 0; i < n; ++i) {
@@ -701,7 +737,8 @@ mi_status prepare_batch(const mi_work_item *w, int64_t n, uint32_t flags, BatchT
   }
   B.T.assign((size_t)n, PoseTables());
   B.SS.assign((size_t)n, StripeShape());
-  B.frame_base.assign((size_t)n + 1, 0);
+  B.direct.assign((size_t)n, 0);
+  B.frame_start.assign((size_t)n, 0);
   const Tuning tu = tuning_now();
   int plan_bytes_max = 8;
   for (int64_t i = 0; i < n; ++i) {
@@ -724,23 +761,48 @@ mi_status prepare_batch(const mi_work_item *w, int64_t n, uint32_t flags, BatchT
     if (!choose_stripes(gi, tu, zvar, B.SS[(size_t)i], &why))
       return fail(MI_E_UNSUPPORTED, "work item %lld: evaluator: %s", (long long)i, why);
     const StripeShape &S = B.SS[(size_t)i];
-    plan_bytes_max = std::max(plan_bytes_max, S.plan_stripes * S.plan_entries * 8);
-    B.frame_base[(size_t)i + 1] = B.frame_base[(size_t)i] + B.T[(size_t)i].F;
+    const PoseTables &T = B.T[(size_t)i];
+    // a rotation shared by fewer than two poses on average is not worth a frame
+    const bool direct = (flags & MI_EVAL_PER_POSE) ||
+                        (!(flags & MI_EVAL_SHARED_FRAMES) && it.K > 0 && 2 * (int64_t)T.F > it.K);
+    B.direct[(size_t)i] = direct;
+    if (direct) {
+      plan_bytes_max = std::max(plan_bytes_max, (2 * S.n_stripes + 1) * 4);
+      B.scratch_stride = std::max(B.scratch_stride, std::max<int64_t>(it.n_b, 1));
+    } else {
+      plan_bytes_max = std::max(plan_bytes_max, S.plan_stripes * S.plan_entries * 8);
+      B.n_frame_items += it.K;
+    }
     B.n_items += it.K;
   }
   if (B.n_items >= ((int64_t)1 << 31)) return fail(MI_E_UNSUPPORTED, "more than 2^31 poses in all");
-  B.F = B.frame_base[(size_t)n];
+  // frame table: frame-mode pairs first (their frames are built), then the
+  // rotations of per-pose pairs (only their matrices are read)
+  int32_t f = 0;
+  for (int pass = 0; pass < 2; ++pass)
+    for (int64_t i = 0; i < n; ++i)
+      if ((bool)B.direct[(size_t)i] == (pass == 1)) {
+        B.frame_start[(size_t)i] = f;
+        f += B.T[(size_t)i].F;
+        if (pass == 0) B.F_built = f;
+      }
+  B.F = f;
   EvalLaunch &L = B.L;
   L.waves = tu.waves;
   L.cap_log2 = n > 0 ? B.SS[0].cap_log2 : 6;
   L.hist_copies = tu.hist_copies;
   L.hist_words = hist_words;
   L.plan_bytes = plan_bytes_max;
+  L.wgs_per_cu = tu.wgs_per_cu;
   L.zvar = zvar;
   L.near_face = (flags & MI_EVAL_NEAR_FACE) != 0;
   if ((int64_t)eval_lds_bytes(L) > max_lds_per_block())
     return fail(MI_E_UNSUPPORTED, "tuning needs %zu LDS bytes per workgroup, device has %d",
                 eval_lds_bytes(L), max_lds_per_block());
+  if (B.n_frame_items < B.n_items) {
+    hipError_t e = eval_resident_wgs(L, L.wgs_per_cu > 0 ? L.wgs_per_cu : 2, &B.scratch_slots);
+    if (e != hipSuccess) return dev_fail(e, "occupancy of the per-pose evaluator");
+  }
   return MI_OK;
 }
 
@@ -757,13 +819,14 @@ void plan_chunks(const BatchTables &B, const mi_work_item *w, size_t budget, Chu
   size_t v = 0, off = 0, cur = 0;
   int32_t in_chunk = 0;
   for (size_t p = 0; p < B.T.size(); ++p) {
+    if (B.direct[p]) continue;
     const int64_t ncols = (int64_t)B.T[p].ncx * B.T[p].ncy;
     const FrameBytes fb = frame_bytes(w[p].n_b, ncols);
     for (int32_t f = 0; f < B.T[p].F; ++f) {
       const size_t nv = v + fb.v, noff = off + fb.off, ncur = cur + fb.cur;
       if (in_chunk > 0 && nv + noff + al256(ncur) > budget) {
         C.max_store = std::max(C.max_store, v + off + al256(cur));
-        C.first.push_back(B.frame_base[p] + f);
+        C.first.push_back(B.frame_start[p] + f);
         v = fb.v; off = fb.off; cur = fb.cur;
         in_chunk = 1;
       } else {
@@ -773,7 +836,7 @@ void plan_chunks(const BatchTables &B, const mi_work_item *w, size_t budget, Chu
     }
   }
   C.max_store = std::max(C.max_store, v + off + al256(cur));
-  C.first.push_back(B.F);
+  C.first.push_back(B.F_built);
 }
 
 struct PlanLayout {
@@ -781,6 +844,7 @@ struct PlanLayout {
   PairDev *pairs;
   FrameDev *frames;
   unsigned long long *nonfinite;
+  uint2 *scratch;
   char *store;
 };
 
@@ -789,8 +853,12 @@ void plan_fixed(const BatchTables &B, int64_t n_pairs, Carver &c, PlanLayout *L)
   PairDev *pairs = c.take<PairDev>((size_t)std::max<int64_t>(n_pairs, 1));
   FrameDev *frames = c.take<FrameDev>((size_t)std::max(B.F, 1));
   unsigned long long *nf = c.take<unsigned long long>((size_t)std::max<int64_t>(2 * n_pairs, 2));
+  uint2 *scratch = c.take<uint2>((size_t)(B.scratch_slots * B.scratch_stride));
   char *store = c.take<char>(0);
-  if (L) { L->items = items; L->pairs = pairs; L->frames = frames; L->nonfinite = nf; L->store = store; }
+  if (L) {
+    L->items = items; L->pairs = pairs; L->frames = frames; L->nonfinite = nf;
+    L->scratch = scratch; L->store = store;
+  }
 }
 
 constexpr size_t kDefaultFrameBudget = (size_t)4 << 30;
@@ -812,9 +880,12 @@ size_t single_plan_bytes(int64_t K, int32_t F, int64_t ncols, int64_t n_b) {
   B.T[0].F = F;
   B.T[0].ncx = (int32_t)std::min<int64_t>(ncols, 0x7fffffff);
   B.T[0].ncy = 1;
-  B.frame_base = {0, F};
+  B.direct.assign(1, 0);
+  B.frame_start.assign(1, 0);
   B.F = F;
+  B.F_built = F;
   B.n_items = K;
+  B.n_frame_items = K;
   mi_work_item w;
   memset(&w, 0, sizeof w);
   w.n_b = n_b;
@@ -838,7 +909,7 @@ mi_status create_plan(const mi_work_item *w, int64_t n, uint32_t flags, void *ws
   const size_t store_budget = budget ? std::min(budget, room) : room;
   ChunkPlan C;
   plan_chunks(B, w, store_budget, C);
-  if (B.F > 0 && C.max_store > room)
+  if (B.F_built > 0 && C.max_store > room)
     return fail(MI_E_WORKSPACE, "eval workspace needs %zu bytes, got %zu",
                 c.used() + C.max_store + 256, ws_bytes);
 
@@ -852,20 +923,30 @@ mi_status create_plan(const mi_work_item *w, int64_t n, uint32_t flags, void *ws
   p->pairs_dev = PL.pairs;
   p->frames_dev = PL.frames;
   p->nonfinite = PL.nonfinite;
+  p->n_frame_items = B.n_frame_items;
+  p->scratch = PL.scratch;
+  p->scratch_stride = B.scratch_stride;
+  p->scratch_slots = B.scratch_slots;
+  p->direct_point_poses = 0;
   p->pairs.resize((size_t)n);
   for (int64_t i = 0; i < n; ++i)
     p->pairs[(size_t)i] = {w[i].ref, w[i].xyz_b, w[i].n_b, w[i].K, w[i].mi_out, w[i].argmax_out};
 
-  // pose items: pairs in order, each pair's items sorted by frame
+  // pose items: frame-mode pairs in order, each pair's items sorted by frame
+  // (so the items of a frame chunk are contiguous), then per-pose pairs
   std::vector<PoseDev> items((size_t)B.n_items);
   {
     size_t k = 0;
-    for (int64_t i = 0; i < n; ++i)
-      for (const PoseDev &it : B.T[(size_t)i].items) {
-        PoseDev d = it;
-        d.pair = (int32_t)i;
-        d.frame = it.frame + B.frame_base[(size_t)i];
-        items[k++] = d;
+    for (int pass = 0; pass < 2; ++pass)
+      for (int64_t i = 0; i < n; ++i) {
+        if ((bool)B.direct[(size_t)i] != (pass == 1)) continue;
+        for (const PoseDev &it : B.T[(size_t)i].items) {
+          PoseDev d = it;
+          d.pair = (int32_t)i;
+          d.frame = it.frame + B.frame_start[(size_t)i];
+          items[k++] = d;
+          if (pass == 1) p->direct_point_poses += w[i].n_b;
+        }
       }
   }
   // frame table with each frame's place in its chunk's storage
@@ -879,8 +960,18 @@ mi_status create_plan(const mi_work_item *w, int64_t n, uint32_t flags, void *ws
   {
     std::vector<int32_t> pair_of((size_t)B.F);
     for (int64_t i = 0; i < n; ++i)
-      for (int32_t f = B.frame_base[(size_t)i]; f < B.frame_base[(size_t)i + 1]; ++f)
-        pair_of[(size_t)f] = (int32_t)i;
+      for (int32_t f = 0; f < B.T[(size_t)i].F; ++f)
+        pair_of[(size_t)(B.frame_start[(size_t)i] + f)] = (int32_t)i;
+    // rotations of per-pose pairs: matrices only, nothing is built
+    for (int32_t f = B.F_built; f < B.F; ++f) {
+      const size_t pi = (size_t)pair_of[(size_t)f];
+      FrameDev &Fd = frames[(size_t)f];
+      memset(&Fd, 0, sizeof Fd);
+      memcpy(Fd.R, &B.T[pi].R[(size_t)(f - B.frame_start[pi]) * 9], sizeof Fd.R);
+      Fd.s = w[pi].ref->g->gi.s;
+      Fd.xyz = w[pi].xyz_b;
+      Fd.n = w[pi].n_b;
+    }
     for (size_t ch = 0; ch < n_chunks; ++ch) {
       const int32_t f0 = C.first[ch], f1 = C.first[ch + 1];
       size_t v = 0, off = 0, cur = 0;
@@ -901,7 +992,7 @@ mi_status create_plan(const mi_work_item *w, int64_t n, uint32_t flags, void *ws
         const FrameBytes fb = frame_bytes(w[pi].n_b, ncols);
         FrameDev &Fd = frames[(size_t)f];
         memset(&Fd, 0, sizeof Fd);
-        memcpy(Fd.R, &T.R[(size_t)(f - B.frame_base[pi]) * 9], sizeof Fd.R);
+        memcpy(Fd.R, &T.R[(size_t)(f - B.frame_start[pi]) * 9], sizeof Fd.R);
         Fd.s = gi.s;
         Fd.xyz = w[pi].xyz_b;
         Fd.n = w[pi].n_b;
@@ -918,13 +1009,17 @@ mi_status create_plan(const mi_work_item *w, int64_t n, uint32_t flags, void *ws
     p->chunk_point_poses.assign(n_chunks, 0);
     for (size_t ch = 0; ch < n_chunks; ++ch) {
       p->chunk_item[ch] = k;
-      while (k < B.n_items && items[(size_t)k].frame < C.first[ch + 1]) {
+      while (k < B.n_frame_items && items[(size_t)k].frame < C.first[ch + 1]) {
         p->chunk_point_poses[ch] += w[items[(size_t)k].pair].n_b;
         ++k;
       }
     }
-    p->chunk_item[n_chunks] = B.n_items;
+    p->chunk_item[n_chunks] = B.n_frame_items;
   }
+  p->chunk_xcd.resize(n_chunks);
+  for (size_t ch = 0; ch < n_chunks; ++ch)
+    group_by_xcd(items, p->chunk_item[ch], p->chunk_item[ch + 1], p->chunk_xcd[ch]);
+  group_by_xcd(items, B.n_frame_items, B.n_items, p->direct_xcd);
   std::vector<PairDev> pairs((size_t)n);
   for (int64_t i = 0; i < n; ++i) {
     const GridInfo &gi = w[i].ref->g->gi;
@@ -996,10 +1091,21 @@ mi_status run_plan(mi_plan *p, hipStream_t s) {
     if (i1 > i0) {
       hipEvent_t a = nullptr;
       const bool timed = prof_begin(s, &a);
-      HIP_TRY(launch_eval(p->pairs_dev, p->frames_dev, p->items_dev + i0, i1 - i0, p->launch, s),
+      HIP_TRY(launch_eval(p->pairs_dev, p->frames_dev, p->items_dev + i0, i1 - i0,
+                          p->chunk_xcd[ch].data(), p->launch, s),
               "eval");
       if (timed) prof_end(s, a, kStageEval, i1 - i0, p->chunk_point_poses[ch]);
     }
+  }
+  const int64_t nd = p->n_items - p->n_frame_items;
+  if (nd > 0) {
+    hipEvent_t a = nullptr;
+    const bool timed = prof_begin(s, &a);
+    HIP_TRY(launch_eval_direct(p->pairs_dev, p->frames_dev, p->items_dev + p->n_frame_items, nd,
+                               p->direct_xcd.data(), p->launch, p->scratch, p->scratch_stride,
+                               p->scratch_slots, s),
+            "eval (per-pose buckets)");
+    if (timed) prof_end(s, a, kStageEval, nd, p->direct_point_poses);
   }
   for (const PairHost &ph : p->pairs)
     if (ph.argmax_out && ph.K > 0)
@@ -1044,6 +1150,145 @@ extern "C" mi_status mi_eval_batch(const mi_work_item *items, int64_t n_items, u
   st = run_plan(p, (hipStream_t)stream);
   mi_plan_destroy(p);
   return st;
+}
+
+// ----------------------------------------------------------------- autotune
+
+namespace {
+
+// A strided sample of each item's poses (every ceil(K / max_poses)-th), so
+// that the sample keeps the workload's mix of rotations and translations.
+struct Sample {
+  std::vector<std::vector<double>> poses;
+  std::vector<mi_work_item> items;
+};
+
+void make_sample(const mi_work_item *w, int64_t n, int64_t max_poses, Sample &S) {
+  S.poses.assign((size_t)n, std::vector<double>());
+  S.items.assign(w, w + n);
+  for (int64_t i = 0; i < n; ++i) {
+    const int64_t K = w[i].K;
+    const int64_t stride = max_poses > 0 && K > max_poses ? (K + max_poses - 1) / max_poses : 1;
+    std::vector<double> &P = S.poses[(size_t)i];
+    for (int64_t k = 0; k < K; k += stride) P.insert(P.end(), w[i].poses + 6 * k, w[i].poses + 6 * k + 6);
+    mi_work_item &it = S.items[(size_t)i];
+    it.poses = P.data();
+    it.K = (int64_t)(P.size() / 6);
+    it.argmax_out = nullptr;
+    it.hist_out = nullptr;
+    it.stats_out = nullptr;
+  }
+}
+
+size_t sample_out_bytes(const Sample &S) {
+  size_t b = 0;
+  for (const mi_work_item &it : S.items)
+    b += al256((size_t)it.ref->g->gi.nf * (size_t)std::max<int64_t>(it.K, 1) * sizeof(double));
+  return b;
+}
+
+}  // namespace
+
+extern "C" size_t mi_autotune_workspace(const mi_work_item *items, int64_t n_items, uint32_t flags,
+                                        int64_t max_poses) {
+  if (n_items <= 0 || !items) return 0;
+  Sample S;
+  make_sample(items, n_items, max_poses, S);
+  BatchTables B;
+  if (prepare_batch(S.items.data(), n_items, flags, B) != MI_OK) return 0;
+  return sample_out_bytes(S) + batch_bytes(B, S.items.data(), n_items, 0) + 512;
+}
+
+extern "C" mi_status mi_autotune(const mi_work_item *items, int64_t n_items, uint32_t flags,
+                                 int64_t max_poses, void *ws, size_t ws_bytes, void *stream,
+                                 mi_autotune_report *out) {
+  if (!items || n_items <= 0 || !out) return fail(MI_E_INVALID, "mi_autotune: bad arguments");
+  if (!ws || ((uintptr_t)ws & 255)) return fail(MI_E_WORKSPACE, "workspace NULL or not 256-aligned");
+  hipStream_t s = (hipStream_t)stream;
+  Sample S;
+  make_sample(items, n_items, max_poses, S);
+  Carver c(ws, ws_bytes);
+  for (mi_work_item &it : S.items)
+    it.mi_out = c.take<double>((size_t)it.ref->g->gi.nf * (size_t)std::max<int64_t>(it.K, 1));
+  c.take<char>(0);
+  if (!c.fits()) return fail(MI_E_WORKSPACE, "autotune workspace too small");
+  void *bws = (void *)c.cur;
+  const size_t bws_bytes = ws_bytes - c.used();
+  mi_tuning start;
+  mi_tuning_get(&start);
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  HIP_TRY(hipEventCreate(&e0), "autotune event");
+  HIP_TRY(hipEventCreate(&e1), "autotune event");
+  int tried = 0;
+  // one warm execution, then the mean of two timed ones; <0 when the tuning
+  // does not apply to this workload (LDS, key or plan limits)
+  auto time_it = [&](const mi_tuning &t, double *ms) -> mi_status {
+    *ms = -1.0;
+    if (mi_tuning_set(&t) != MI_OK) return MI_OK;
+    mi_plan *p = nullptr;
+    mi_status st = create_plan(S.items.data(), n_items, flags, bws, bws_bytes, 0, stream, false, &p);
+    if (st == MI_E_UNSUPPORTED) return MI_OK;
+    if (st != MI_OK) return st;
+    st = run_plan(p, s);
+    if (st == MI_OK) {
+      if (hipEventRecord(e0, s) != hipSuccess) st = MI_E_DEVICE;
+      for (int r = 0; r < 2 && st == MI_OK; ++r) st = run_plan(p, s);
+      if (st == MI_OK && hipEventRecord(e1, s) != hipSuccess) st = MI_E_DEVICE;
+      float f = 0.f;
+      if (st == MI_OK && (hipEventSynchronize(e1) != hipSuccess ||
+                          hipEventElapsedTime(&f, e0, e1) != hipSuccess))
+        st = MI_E_DEVICE;
+      if (st == MI_OK) *ms = f / 2.0;
+    }
+    mi_plan_destroy(p);
+    ++tried;
+    return st;
+  };
+  mi_status st = MI_OK;
+  double start_ms = -1.0, best_ms = -1.0;
+  mi_tuning best = start;
+  auto consider = [&](const mi_tuning &t) {
+    double ms = -1.0;
+    if (st != MI_OK) return;
+    st = time_it(t, &ms);
+    if (st == MI_OK && ms >= 0.0 && (best_ms < 0.0 || ms < best_ms)) {
+      best_ms = ms;
+      best = t;
+    }
+  };
+  st = time_it(start, &start_ms);
+  if (st == MI_OK && start_ms >= 0.0) { best_ms = start_ms; best = start; }
+  // stage 1: workgroup size and hash capacity
+  const int waves[3] = {4, 8, 16};
+  const int hashk[5] = {24, 32, 48, 64, 96};
+  for (int w : waves)
+    for (int hk : hashk) consider(mi_tuning{w, hk * 1024, 2, 8, 0});
+  // stage 2: stripe height and histogram privatization around the best
+  const mi_tuning b1 = best;
+  const int rows[5] = {4, 8, 12, 16, 24};
+  const int copies[3] = {1, 2, 4};
+  for (int r : rows)
+    for (int h : copies) consider(mi_tuning{b1.waves, b1.hash_bytes, h, r, 0});
+  // stage 3: one workgroup per pose, or a persistent grid
+  const mi_tuning b2 = best;
+  const int per_cu[3] = {1, 2, 4};
+  for (int pc : per_cu) consider(mi_tuning{b2.waves, b2.hash_bytes, b2.hist_copies, b2.stripe_rows, pc});
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (st != MI_OK) {
+    mi_tuning_set(&start);
+    return st;
+  }
+  if (best_ms < 0.0) {
+    mi_tuning_set(&start);
+    return fail(MI_E_UNSUPPORTED, "no tuning applies to this workload");
+  }
+  mi_tuning_set(&best);
+  out->best = best;
+  out->best_ms = best_ms;
+  out->start_ms = start_ms;
+  out->tried = tried;
+  return MI_OK;
 }
 
 extern "C" size_t mi_eval_poses_workspace(const mi_ref *r, int64_t n_b, const double *poses,

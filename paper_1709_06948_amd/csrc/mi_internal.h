@@ -114,13 +114,25 @@ struct EvalLaunch {
   int32_t hist_copies;       // privatized joint-histogram copies
   int32_t hist_words;        // max over pairs of sum_f nb_f^2
   int32_t plan_bytes;        // max over pairs of plan_stripes * rows * (pieces + 1) * 8
+  int32_t wgs_per_cu;        // 0: one workgroup per pose; else a persistent grid
   bool zvar;                 // 16-byte voxel sums (else 4-byte counts)
   bool near_face;
 };
 
+// xcd_start (host, kXcds + 1 entries, or NULL for equal counts): the items of
+// XCD x are [xcd_start[x], xcd_start[x + 1]), contiguous runs of the item array.
 hipError_t launch_eval(const PairDev *pairs_dev, const FrameDev *frames_dev,
-                       const PoseDev *items_dev, int64_t n_items, const EvalLaunch &cfg,
-                       hipStream_t s);
+                       const PoseDev *items_dev, int64_t n_items, const int64_t *xcd_start,
+                       const EvalLaunch &cfg, hipStream_t s);
+// Per-pose bucketing form (pose sets with (nearly) all rotations distinct): a
+// grid of `slots` workgroups, workgroup b using scratch[b * stride ...] for
+// its pose's bucketed points (stride >= the largest n_b of the launch).
+hipError_t launch_eval_direct(const PairDev *pairs_dev, const FrameDev *frames_dev,
+                              const PoseDev *items_dev, int64_t n_items, const int64_t *xcd_start,
+                              const EvalLaunch &cfg, uint2 *scratch, int64_t scratch_stride,
+                              int64_t slots, hipStream_t s);
+// Workgroups of a persistent grid of this shape (at most per_cu per compute unit).
+hipError_t eval_resident_wgs(const EvalLaunch &cfg, int per_cu, int64_t *out);
 size_t eval_lds_bytes(const EvalLaunch &cfg);
 int32_t eval_hash_slot_bytes(bool zvar);
 

@@ -19,6 +19,8 @@ LIB_PATH = os.path.join(_HERE, "libmi355.so")
 MI_OK, MI_E_INVALID, MI_E_WORKSPACE, MI_E_DEVICE, MI_E_UNSUPPORTED = 0, -1, -2, -3, -4
 FEAT_COUNT, FEAT_ZVAR = 1, 2
 EVAL_NEAR_FACE = 1
+EVAL_PER_POSE = 2          # force per-pose bucketing
+EVAL_SHARED_FRAMES = 4     # force shared rotated frames
 MAX_POINTS = 1 << 20
 
 STATS_DTYPE = np.dtype([("lo", "<i4", 3), ("hi", "<i4", 3), ("n_overlap", "<i8"),
@@ -76,7 +78,12 @@ class _RequestState(C.Structure):
 
 class _Tuning(C.Structure):
     _fields_ = [("waves", C.c_int32), ("hash_bytes", C.c_int32), ("hist_copies", C.c_int32),
-                ("stripe_rows", C.c_int32)]
+                ("stripe_rows", C.c_int32), ("wgs_per_cu", C.c_int32)]
+
+
+class _AutotuneReport(C.Structure):
+    _fields_ = [("best", _Tuning), ("best_ms", C.c_double), ("start_ms", C.c_double),
+                ("tried", C.c_int32)]
 
 
 def _load():
@@ -113,6 +120,9 @@ def _load():
         "mi_batch_create": ([C.POINTER(_WorkItem), i64, u32, vp, sz, sz, vp, C.POINTER(vp)], st),
         "mi_batch_execute": ([vp, vp], st),
         "mi_eval_batch": ([C.POINTER(_WorkItem), i64, u32, vp, sz, vp], st),
+        "mi_autotune_workspace": ([C.POINTER(_WorkItem), i64, u32, i64], sz),
+        "mi_autotune": ([C.POINTER(_WorkItem), i64, u32, i64, vp, sz, vp,
+                         C.POINTER(_AutotuneReport)], st),
         "mi_server_create": ([C.POINTER(_ServerDesc), vp, C.POINTER(vp)], st),
         "mi_server_submit": ([vp, C.POINTER(_Request), C.POINTER(i64)], st),
         "mi_server_step": ([vp, C.POINTER(C.c_int32), C.POINTER(C.c_int32)], st),
@@ -137,6 +147,7 @@ EXPORTED = ("mi_status_str", "mi_last_error", "mi_tuning_set", "mi_tuning_get",
             "mi_eval_poses_workspace", "mi_eval_poses", "mi_eval_poses_plain_workspace",
             "mi_eval_poses_plain", "mi_plan_create", "mi_plan_execute", "mi_plan_destroy",
             "mi_batch_workspace", "mi_batch_create", "mi_batch_execute", "mi_eval_batch",
+            "mi_autotune_workspace", "mi_autotune",
             "mi_align_workspace", "mi_align_coarse_to_fine", "mi_server_create",
             "mi_server_submit", "mi_server_step", "mi_server_poll", "mi_server_release",
             "mi_server_destroy")
@@ -189,11 +200,12 @@ def tuning_get() -> dict:
     t = _Tuning()
     _check(_lib.mi_tuning_get(C.byref(t)), "mi_tuning_get")
     return dict(waves=t.waves, hash_bytes=t.hash_bytes, hist_copies=t.hist_copies,
-                stripe_rows=t.stripe_rows)
+                stripe_rows=t.stripe_rows, wgs_per_cu=t.wgs_per_cu)
 
 
-def tuning_set(waves: int, hash_bytes: int, hist_copies: int = 2, stripe_rows: int = 8):
-    t = _Tuning(int(waves), int(hash_bytes), int(hist_copies), int(stripe_rows))
+def tuning_set(waves: int, hash_bytes: int, hist_copies: int = 2, stripe_rows: int = 8,
+               wgs_per_cu: int = 0):
+    t = _Tuning(int(waves), int(hash_bytes), int(hist_copies), int(stripe_rows), int(wgs_per_cu))
     _check(_lib.mi_tuning_set(C.byref(t)), "mi_tuning_set")
 
 
@@ -474,6 +486,24 @@ def eval_batch(items, flags=0, stream=None):
     _check(_lib.mi_eval_batch(arr, len(items), flags, _dptr(ws), ws.numel(), _stream(stream)),
            "mi_eval_batch")
     return ws
+
+
+def autotune(items, flags=0, max_poses=4096, stream=None) -> dict:
+    """mi_autotune: time candidate tunings on a sample of the workload and make
+    the fastest current.  Returns the chosen tuning and the timings."""
+    items = list(items)
+    arr = _items_array(items)
+    nbytes = _lib.mi_autotune_workspace(arr, len(items), flags, int(max_poses))
+    if nbytes == 0:
+        raise MIError(MI_E_INVALID, "mi_autotune_workspace", _lib.mi_last_error().decode())
+    ws = _workspace(nbytes)
+    rep = _AutotuneReport()
+    _check(_lib.mi_autotune(arr, len(items), flags, int(max_poses), _dptr(ws), ws.numel(),
+                            _stream(stream), C.byref(rep)), "mi_autotune")
+    b = rep.best
+    return dict(best=dict(waves=b.waves, hash_bytes=b.hash_bytes, hist_copies=b.hist_copies,
+                          stripe_rows=b.stripe_rows, wgs_per_cu=b.wgs_per_cu),
+                best_ms=rep.best_ms, start_ms=rep.start_ms, tried=rep.tried)
 
 
 def align_coarse_to_fine(ref: Ref, xyz_b, init, half_range, samples, levels, shrink,

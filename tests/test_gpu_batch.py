@@ -193,3 +193,25 @@ def test_batch_errors_name_the_item(M):
     M.eval_batch([])
     M.eval_batch([M.WorkItem(ref, pair.B, np.zeros((0, 6)))])
     torch.cuda.synchronize()
+
+
+def test_autotune_changes_speed_only(M):
+    pair = synth.tiny_pair()
+    mg = M.Grid(pair.origin, pair.dims, pair.voxel, features=3, nb_count=32, nb_zvar=32)
+    ref = M.Ref(mg, pair.A)
+    P = synth.grid8_poses(4)
+    orig = M.tuning_get()
+    try:
+        before = M.WorkItem(ref, pair.B, P, want_hist=True)
+        M.Batch([before]).execute()
+        torch.cuda.synchronize()
+        rep = M.autotune([before], max_poses=1024)
+        _say("autotune", rep)
+        assert rep["tried"] >= 10
+        assert 0 < rep["best_ms"] <= rep["start_ms"]
+        assert M.tuning_get() == rep["best"]
+        after = M.WorkItem(ref, pair.B, P, want_hist=True)
+        M.Batch([after]).execute()
+        _same(after.results(), before.results(), mg, "autotuned vs default")
+    finally:
+        M.tuning_set(**orig)

@@ -66,8 +66,12 @@ def _check(M, og, mg, A, B, poses, res, K=None, label=""):
 
 def _both_paths(M, og, mg, A, B, poses, label):
     ref = M.Ref(mg, A)
-    r1 = M.eval_poses(ref, B, poses, flags=M.EVAL_NEAR_FACE, want_hist=True, want_stats=True)
-    _check(M, og, mg, A, B, poses, r1, label=label + "/batched")
+    # batched evaluator: automatic choice, then each way of feeding it forced
+    for extra, name in ((0, "batched"), (M.EVAL_SHARED_FRAMES, "frames"),
+                        (M.EVAL_PER_POSE, "per-pose")):
+        r1 = M.eval_poses(ref, B, poses, flags=M.EVAL_NEAR_FACE | extra, want_hist=True,
+                          want_stats=True)
+        _check(M, og, mg, A, B, poses, r1, label=label + "/" + name)
     r2 = M.eval_poses_plain(ref, B, poses, flags=M.EVAL_NEAR_FACE, want_hist=True,
                             want_stats=True)
     _check(M, og, mg, A, B, poses, r2, label=label + "/plain")
@@ -212,11 +216,14 @@ def test_chunked_frames_and_tuning_variants_identical(M):
     bmi = base["mi"].cpu().numpy()
     orig = M.tuning_get()
     try:
-        for waves, hb, hc, sr in [(4, 98304, 1, 8), (8, 49152, 2, 4), (2, 36864, 1, 16),
-                                  (16, 98304, 4, 1), (1, 65536, 1, 3), (1, 8192, 2, 62),
-                                  (3, 16384, 2, 40)]:
-            _say("tuning", waves, hb, hc, sr)
-            M.tuning_set(waves, hb, hc, sr)
+        for waves, hb, hc, sr, pw in [(4, 98304, 1, 8, 0), (8, 49152, 2, 4, 0),
+                                      (2, 36864, 1, 16, 0), (16, 98304, 4, 1, 0),
+                                      (1, 65536, 1, 3, 0), (1, 8192, 2, 62, 0),
+                                      (3, 16384, 2, 40, 0), (8, 49152, 2, 8, 1),
+                                      (4, 24576, 1, 8, 3), (16, 98304, 2, 16, 1)]:
+            # the last three run a persistent grid: workgroups loop over poses
+            _say("tuning", waves, hb, hc, sr, pw)
+            M.tuning_set(waves, hb, hc, sr, pw)
             r = M.eval_poses(ref, p.B, P, want_hist=True)
             torch.cuda.synchronize()
             for f in range(2):
