@@ -59,7 +59,7 @@ __host__ __device__ inline Layout eval_layout(int waves, int hist_copies, int hi
   Layout L;
   int o = al16(hist_copies * hist_words * 4);
   L.off_cnta = o;   o += 512;                   // cntA[2][64]
-  L.off_edges = o;  o += 256 + 512;             // 64 u32 + 64 u64
+  L.off_edges = o;  o += 256 + 512 + 512;       // 64 u32 + 64 u64 + 64 f64
   L.off_wave = o;   o += al16(waves * 48 + 16); // box [W][8] i32, counts [W][2] u64, flags
   o += 64 * 4 + 64 * 16;                        // dummy targets of masked lanes
   L.off_plan = o;   o += al16(plan_bytes);
@@ -148,6 +148,7 @@ __global__ void __launch_bounds__(1024) k_eval(const PairDev *__restrict__ pairs
   uint32_t *cntA = (uint32_t *)(smem + cfg.off_cnta);
   uint32_t *cedge = (uint32_t *)(smem + cfg.off_edges);
   uint64_t *zedge = (uint64_t *)(cedge + 64);
+  double *zedged = (double *)(zedge + 64);
   int *wbox = (int *)(smem + cfg.off_wave);
   unsigned long long *wcnt = (unsigned long long *)(wbox + 8 * W);
   uint32_t *ovf = (uint32_t *)(wcnt + 2 * W);   // [2] overflow flags by brick parity
@@ -189,6 +190,7 @@ __global__ void __launch_bounds__(1024) k_eval(const PairDev *__restrict__ pairs
     for (int i = tid; i < 64; i += T) {
       cedge[i] = P.count_edges[i];
       zedge[i] = P.zvar_edges[i];
+      zedged[i] = (double)P.zvar_edges[i];
     }
     if (tid < 4) ovf[tid] = 0u;
     __syncthreads();
@@ -203,6 +205,7 @@ __global__ void __launch_bounds__(1024) k_eval(const PairDev *__restrict__ pairs
     const int ahi0 = P.abox[3], ahi1 = P.abox[4], ahi2 = P.abox[5];
     uint32_t *myhist = hist + (wid % cfg.hist_copies) * cfg.hist_words;
     const uint32_t kind0 = P.kind[0], kind1 = P.kind[1];
+    const bool count_default = P.count_default != 0;
     const uint8_t *binA0 = P.binA[0], *binA1 = P.binA[1];
     const int BY = P.stripe_h, NS = P.n_stripes, Q = P.pieces, RM = BY + 2;
     const int kxb = P.kx_bits, kyb = P.ky_bits;
@@ -330,7 +333,7 @@ __global__ void __launch_bounds__(1024) k_eval(const PairDev *__restrict__ pairs
                 my_st = ps[(ra + lane) * (Q + 1) + qa].x;
                 my_len = ps[(ra + lane) * (Q + 1) + qend].y - my_st;
               }
-              const uint32_t my_c = (my_len + 63u) >> 6;
+              const uint32_t my_c = (my_len + 255u) >> 8;
               uint32_t inc = my_c;
   #pragma unroll
               for (int o = 1; o < 64; o <<= 1) {
@@ -348,29 +351,29 @@ __global__ void __launch_bounds__(1024) k_eval(const PairDev *__restrict__ pairs
               // voxel rows of a piece are always such bricks)
               const bool fits = (int64_t)(X1 - X0) * (Y1 - Y0) * nz <= cfg.load_max;
               const int max_probe = fits ? cap : kMaxProbe;
-              // chunk k -> candidate of this lane.  A row of len candidates takes
-              // c = ceil(len/64) chunks; its candidates are cut into 4 runs of 16*c and
-              // step j of the row gives lane l candidate (l/16)*16c + 16j + l%16:
-              // 4 cache lines per load as for 64 consecutive candidates, but lanes of
-              // one step lie in 4 different parts of the row, which spreads the hot
-              // voxels (dense ground near the sensor) over fewer lanes per atomic.
-              auto chunk_idx = [&](int k, bool *valid) -> uint32_t {
+              // chunk k -> this lane's 4 consecutive candidates.  A row of len
+              // candidates takes ceil(len/256) chunks; in chunk j of the row, lane l
+              // takes candidates 256j + 4l .. 256j + 4l + 3.  Consecutive candidates
+              // of a column often share a voxel (ground), and a lane adds a run of
+              // equal voxels with one set of atomics.  Returns the first index
+              // (the row start for lanes past the row's end, whose candidates are
+              // all invalid) and how many of the 4 are in the row.
+              auto chunk_base = [&](int k, int *n_valid) -> uint32_t {
                 const unsigned long long mk = __ballot(lane < nr && my_cpre <= (uint32_t)k);
                 const int row = __popcll(mk) - 1;
                 const uint32_t st = __builtin_amdgcn_readlane(my_st, row);
                 const uint32_t len = __builtin_amdgcn_readlane(my_len, row);
                 const uint32_t cpre = __builtin_amdgcn_readlane(my_cpre, row);
-                const uint32_t c = (len + 63u) >> 6;
-                const uint32_t j = (uint32_t)k - cpre;
-                const uint32_t off_in_row = ((uint32_t)lane >> 4) * (c << 4) + (j << 4) +
-                                            ((uint32_t)lane & 15u);
-                *valid = off_in_row < len;
-                return st + off_in_row;
+                const uint32_t off0 = (((uint32_t)k - cpre) << 8) + 4u * (uint32_t)lane;
+                const int rem = (int)len - (int)off0;
+                *n_valid = rem;
+                return rem > 0 ? st + off0 : st;
               };
               // Four candidates per lane, branch-free up to the rare collisions:
               // find or claim each in-brick candidate's slot, then add its sums.
               auto insert4 = [&](bool (&inb)[4], const uint32_t (&key)[4],
-                                 const uint32_t (&q)[4]) {
+                                 const unsigned long long (&add1)[4],
+                                 const unsigned long long (&add2)[4]) {
                 uint32_t h[4];
   #pragma unroll
                 for (int i = 0; i < 4; ++i) h[i] = (key[i] * 2654435761u) >> (32 - cfg.cap_log2);
@@ -436,10 +439,10 @@ __global__ void __launch_bounds__(1024) k_eval(const PairDev *__restrict__ pairs
                   if (ZVAR) {
                     unsigned long long *a1 = inb[i] ? &hv1[h[i]] : &dval[lane];
                     unsigned long long *a2 = inb[i] ? &hv2[h[i]] : &dval[64 + lane];
-                    atomicAdd(a1, (1ull << 44) | (unsigned long long)q[i]);
-                    atomicAdd(a2, (unsigned long long)q[i] * q[i]);
+                    atomicAdd(a1, add1[i]);
+                    atomicAdd(a2, add2[i]);
                   } else {
-                    atomicAdd(inb[i] ? &hcnt[h[i]] : &dkey[lane], 1u);
+                    atomicAdd(inb[i] ? &hcnt[h[i]] : &dkey[lane], (uint32_t)add1[i]);
                   }
                 }
               };
@@ -472,7 +475,26 @@ __global__ void __launch_bounds__(1024) k_eval(const PairDev *__restrict__ pairs
                     if (d * P.voxel < kNearFace) ++bnear;
                   }
                 }
-                insert4(inb, key, q);
+                // runs of equal voxels among the 4 consecutive candidates: the
+                // first of a run adds the whole run's n, S1, S2
+                unsigned long long add1[4], add2[4];
+  #pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                  add1[i] = ZVAR ? ((1ull << 44) | (unsigned long long)q[i]) : 1ull;
+                  add2[i] = ZVAR ? (unsigned long long)q[i] * q[i] : 0ull;
+                }
+                bool same[4];
+                same[0] = false;
+  #pragma unroll
+                for (int i = 1; i < 4; ++i) same[i] = inb[i] && inb[i - 1] && key[i] == key[i - 1];
+  #pragma unroll
+                for (int i = 2; i >= 0; --i) {
+                  add1[i] += same[i + 1] ? add1[i + 1] : 0ull;
+                  add2[i] += same[i + 1] ? add2[i + 1] : 0ull;
+                }
+  #pragma unroll
+                for (int i = 1; i < 4; ++i) inb[i] = inb[i] && !same[i];
+                insert4(inb, key, add1, add2);
               };
               // Four chunks per wave step: the twelve loads are issued together, then
               // the four candidates of each lane go through step4 together.  Lanes
@@ -499,25 +521,26 @@ __global__ void __launch_bounds__(1024) k_eval(const PairDev *__restrict__ pairs
                   inb[i] = val && (uint32_t)(ix - X0) < (uint32_t)(X1 - X0) &&
                            (uint32_t)(iy - Y0) < (uint32_t)(Y1 - Y0);
                 }
-                insert4(inb, key, q);
-              }
-              for (int k = wid; !DIRECT && k < nch; k += 4 * W) {
-                bool v[4];
-                uint32_t ii[4];
-                ii[0] = chunk_idx(k, &v[0]);
-  #pragma unroll
-                for (int i = 1; i < 4; ++i) {
-                  v[i] = false;
-                  ii[i] = 0u;
-                  if (k + i * W < nch) ii[i] = chunk_idx(k + i * W, &v[i]);
-                }
-                double x[4], y[4], z[4];
+                unsigned long long add1[4], add2[4];
   #pragma unroll
                 for (int i = 0; i < 4; ++i) {
-                  const uint32_t j = v[i] ? ii[i] : 0u;
-                  x[i] = ldg(fvx + j);
-                  y[i] = ldg(fvy + j);
-                  z[i] = ldg(fvz + j);
+                  add1[i] = ZVAR ? ((1ull << 44) | (unsigned long long)q[i]) : 1ull;
+                  add2[i] = ZVAR ? (unsigned long long)q[i] * q[i] : 0ull;
+                }
+                insert4(inb, key, add1, add2);
+              }
+              for (int k = wid; !DIRECT && k < nch; k += W) {
+                int nv;
+                const uint32_t b = chunk_base(k, &nv);
+                bool v[4];
+                double x[4], y[4], z[4];
+                // the frame arrays are padded, so base + 3 is always readable
+  #pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                  v[i] = i < nv;
+                  x[i] = ldg(fvx + b + i);
+                  y[i] = ldg(fvy + b + i);
+                  z[i] = ldg(fvz + b + i);
                 }
                 step4(v, x, y, z);
               }
@@ -553,17 +576,20 @@ __global__ void __launch_bounds__(1024) k_eval(const PairDev *__restrict__ pairs
                 if (!overflow && ix >= alo0 && ix <= ahi0 && iy >= alo1 && iy <= ahi1 &&
                     iz >= alo2 && iz <= ahi2) {
                   const int64_t lin = ((int64_t)iz * ny + iy) * nx + ix;
+                  // count bins: O(1) with the default edges 1, 2, ..., nb - 1
+                  auto bin_of = [&](uint32_t kind, int nb) -> int {
+                    if (kind == MI_FEAT_COUNT)
+                      return count_default ? (int)min(n, (uint32_t)(nb - 1))
+                                           : bin_count_dev(n, nb, cedge);
+                    return bin_zvar_nodiv(n, s1, s2, nb, zedged, zedge);
+                  };
                   {
                     const int a = ldg(binA0 + lin);
-                    const int b = kind0 == MI_FEAT_COUNT ? bin_count_dev(n, nb0, cedge)
-                                                         : bin_zvar_dev(n, s1, s2, nb0, zedge);
-                    atomicAdd(&myhist[a * nb0 + b], 1u);
+                    atomicAdd(&myhist[a * nb0 + bin_of(kind0, nb0)], 1u);
                   }
                   if (nf > 1) {
                     const int a = ldg(binA1 + lin);
-                    const int b = kind1 == MI_FEAT_COUNT ? bin_count_dev(n, nb1, cedge)
-                                                         : bin_zvar_dev(n, s1, s2, nb1, zedge);
-                    atomicAdd(&myhist[hoff1 + a * nb1 + b], 1u);
+                    atomicAdd(&myhist[hoff1 + a * nb1 + bin_of(kind1, nb1)], 1u);
                   }
                 }
               }

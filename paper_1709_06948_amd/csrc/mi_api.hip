@@ -696,7 +696,8 @@ struct FrameBytes {
   size_t v, off, cur;
 };
 FrameBytes frame_bytes(int64_t n_b, int64_t ncols) {
-  return {al256((size_t)std::max<int64_t>(n_b, 1) * 3 * sizeof(double)),
+  // 4 doubles of padding: the evaluator reads 4 consecutive points from any start
+  return {al256((size_t)std::max<int64_t>(n_b, 1) * 3 * sizeof(double) + 4 * sizeof(double)),
           al256((size_t)(ncols + 1) * 4), (size_t)ncols * 4};
 }
 
@@ -1042,6 +1043,11 @@ mi_status create_plan(const mi_work_item *w, int64_t n, uint32_t flags, void *ws
     P.kx_bits = S.kx_bits;
     P.ky_bits = S.ky_bits;
     P.plan_stripes = S.plan_stripes;
+    P.count_default = 1;
+    for (int f = 0; f < gi.nf; ++f)
+      if (gi.kind[f] == MI_FEAT_COUNT)
+        for (int j = 0; j + 1 < gi.nb[f]; ++j)
+          if (gi.count_edges[j] != (uint32_t)(j + 1)) P.count_default = 0;
     P.nonfinite = PL.nonfinite + 2 * i;
     P.n_b = w[i].n_b;
     P.mi_out = w[i].mi_out;

@@ -61,6 +61,38 @@ __device__ __forceinline__ int bin_zvar_dev(uint32_t n, uint64_t s1, uint64_t s2
   return 1 + lo;
 }
 
+// The same z-variance bin without a division: the search compares FP64
+// D = n*S2 - S1^2 (relative error below 2^-51) against E[j] * n^2 (Ed holds the
+// edges as doubles, exact below 2^53), and only when an edge product lies
+// within a relative 2^-40 of D is the count redone with the exact 128-bit
+// comparison.  Identical to bin_zvar_dev for every input.
+__device__ __forceinline__ int bin_zvar_nodiv(uint32_t n, uint64_t s1, uint64_t s2, int nb,
+                                              const double *Ed, const uint64_t *E) {
+  if (n == 0) return 0;
+  const u128 D = (u128)n * (u128)s2 - (u128)s1 * (u128)s1;
+  const double Dd = (double)(uint64_t)(D >> 64) * 18446744073709551616.0 + (double)(uint64_t)D;
+  const double nd = (double)n;
+  const double n2 = nd * nd;
+  const int m = nb - 2;
+  int lo = 0, hi = m;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (Ed[mid - 1] * n2 <= Dd) lo = mid; else hi = mid - 1;
+  }
+  const double tol = 0x1p-40;
+  bool near = false;
+  if (lo > 0) {
+    const double p = Ed[lo - 1] * n2;
+    near = Dd - p <= tol * Dd;
+  }
+  if (lo < m) {
+    const double p = Ed[lo] * n2;
+    near = near || p - Dd <= tol * p;
+  }
+  if (near) lo = bin_zvar_exact(D, (u128)n * (u128)n, m, E);
+  return 1 + lo;
+}
+
 // Entropy term -p ln p for a count c out of N (0 ln 0 = 0), Eqs. 3-5.
 __device__ __forceinline__ double plogp_term(uint64_t c, double N) {
   if (c == 0) return 0.0;

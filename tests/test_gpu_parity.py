@@ -193,6 +193,24 @@ def test_edge_cases(M):
                 "faces")
 
 
+def test_custom_edges(M):
+    """Caller-given bin edges: count edges that are not 1..nb-1 (so the binary
+    search runs) and z-variance edges with repeats and a zero edge."""
+    p = synth.tiny_pair()
+    ce = np.array([1, 2, 3, 5, 8, 13, 21, 34], np.uint32)
+    ze = np.array([0, 0, 5, 100, 100, 1_000, 100_000, 10_000_000, 1_000_000_000, 10 ** 11],
+                  np.uint64)
+    kw = dict(origin=p.origin, dims=p.dims, voxel=p.voxel, features=3, nb_count=9, nb_zvar=12,
+              count_edges=ce, zvar_edges=ze)
+    og, mg = _grids(M, **kw)
+    rng = np.random.default_rng(7)
+    K = 97
+    P = np.concatenate([rng.uniform(-2, 2, (K, 2)), rng.uniform(-0.2, 0.2, (K, 1)),
+                        rng.uniform(-0.03, 0.03, (K, 2)), rng.uniform(-0.2, 0.2, (K, 1))], 1)
+    _say("custom edges")
+    _both_paths(M, og, mg, p.A, p.B, P, "custom-edges")
+
+
 def test_zero_poses(M):
     p = synth.tiny_pair()
     mg = M.Grid(p.origin, p.dims, p.voxel, features=1, nb_count=16)
