@@ -17,9 +17,10 @@
 //         offsets of every candidate row at the stripe's piece cuts, so brick
 //         boundaries and candidate ranges are known without further round trips;
 //  bricks the rest of the stripe first, halved on overflow;
-//  points four candidates per lane per wave step, branch-free: u = fl(v+c),
-//         voxel floor(u); in-brick points find or insert their voxel (one probe
-//         read and one compare-and-swap each, all four in flight together),
+//  points four consecutive candidates of a column row per lane per wave step,
+//         branch-free: u = fl(v+c), voxel floor(u); runs of equal voxels among a
+//         lane's four are added together; each in-brick run finds or claims its
+//         voxel's slot with one compare-and-swap (all four in flight together),
 //         newly claimed slots are appended to the brick's occupied list, and
 //         n, S1, S2 are added with LDS atomics that return nothing;
 //  sweep  every slot on the brick's occupied list: B's extent and point
@@ -377,19 +378,15 @@ __global__ void __launch_bounds__(1024) k_eval(const PairDev *__restrict__ pairs
                 uint32_t h[4];
   #pragma unroll
                 for (int i = 0; i < 4; ++i) h[i] = (key[i] * 2654435761u) >> (32 - cfg.cap_log2);
-                uint32_t k0[4];
-  #pragma unroll
-                for (int i = 0; i < 4; ++i) k0[i] = __atomic_load_n(&hkey[h[i]], __ATOMIC_RELAXED);
                 bool coll[4], fresh[4];
   #pragma unroll
                 for (int i = 0; i < 4; ++i) {
-                  // masked lanes swap on their own dummy word with a value that never matches
-                  const bool want = inb[i] && k0[i] == kEmpty;
-                  uint32_t *a = want ? &hkey[h[i]] : &dkey[lane];
-                  const uint32_t old = atomicCAS(a, want ? kEmpty : kNever, key[i]);
-                  const bool got = want ? (old == kEmpty || old == key[i]) : (k0[i] == key[i]);
-                  fresh[i] = want && old == kEmpty;
-                  coll[i] = inb[i] && !got;
+                  // one compare-and-swap finds or claims the home slot; masked lanes
+                  // swap on their own dummy word with a value that never matches
+                  uint32_t *a = inb[i] ? &hkey[h[i]] : &dkey[lane];
+                  const uint32_t old = atomicCAS(a, inb[i] ? kEmpty : kNever, key[i]);
+                  fresh[i] = inb[i] && old == kEmpty;
+                  coll[i] = inb[i] && old != kEmpty && old != key[i];
                 }
                 if (coll[0] || coll[1] || coll[2] || coll[3]) {
   #pragma unroll

@@ -41,56 +41,110 @@ __device__ __forceinline__ Rotated rotate_point(const FrameDev &F, int64_t i) {
   return r;
 }
 
+// Points of a scan that are neighbours in memory (consecutive samples of a
+// scanner ring) usually fall in the same column: lanes with the column of the
+// lane before them form runs, and only the first lane of a run touches the
+// column's counter, for the whole run.
+struct ColRun {
+  bool head;      // first lane of a run of kept points
+  int head_lane;  // first lane of this lane's run
+  uint32_t len;   // run length (heads only)
+};
+
+__device__ __forceinline__ ColRun col_runs(int col) {
+  const int lane = threadIdx.x & 63;
+  const int prev = __shfl_up(col, 1, 64);
+  const bool kept = col >= 0;
+  const bool head = kept && (lane == 0 || prev != col);
+  const unsigned long long H = __ballot(head);
+  const unsigned long long K = __ballot(kept);
+  ColRun r;
+  r.head = head;
+  // the run ends at the next head or at the next dropped point
+  const unsigned long long ends = H | ~K;
+  const unsigned long long above = lane == 63 ? 0ull : ends >> (lane + 1);
+  const int next = above ? __builtin_ctzll(above) + lane + 1 : 64;
+  r.len = (uint32_t)(next - lane);
+  const unsigned long long upto = lane == 63 ? H : H & ((2ull << lane) - 1ull);
+  r.head_lane = upto ? 63 - __builtin_clzll(upto) : lane;
+  return r;
+}
+
 __global__ void __launch_bounds__(256) k_frame_count(const FrameDev *__restrict__ frames) {
   const FrameDev &F = frames[blockIdx.y];
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < F.n;
-       i += (int64_t)gridDim.x * blockDim.x) {
-    const Rotated r = rotate_point(F, i);
-    if (r.col >= 0) atomicAdd(&F.cur[r.col], 1u);
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  // whole waves iterate together (the run detection needs every lane)
+  for (int64_t i0 = (int64_t)blockIdx.x * blockDim.x; i0 < F.n; i0 += stride) {
+    const int64_t i = i0 + threadIdx.x;
+    const int col = i < F.n ? rotate_point(F, i).col : -1;
+    const ColRun r = col_runs(col);
+    if (r.head) atomicAdd(&F.cur[col], r.len);
   }
 }
 
-// Exclusive scan of the column counts of one frame (one workgroup per frame);
-// off[ncols] = kept points; the cursors start at the offsets.
+// Exclusive scan of the column counts of one frame (one workgroup per frame),
+// in coalesced tiles of 4 columns per thread; off[ncols] = kept points; the
+// cursors start at the offsets.
 __global__ void __launch_bounds__(1024) k_frame_scan(const FrameDev *__restrict__ frames) {
   const FrameDev &F = frames[blockIdx.x];
   const int64_t ncols = (int64_t)F.ncx * F.ncy;
-  const int T = blockDim.x;
-  const int64_t per = (ncols + T - 1) / T;
-  const int64_t b = (int64_t)threadIdx.x * per;
-  const int64_t e = b + per < ncols ? b + per : ncols;
-  uint32_t sum = 0;
-  for (int64_t k = b; k < e; ++k) sum += F.cur[k];
-  __shared__ uint32_t part[1024];
-  part[threadIdx.x] = sum;
+  const int T = blockDim.x, tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  __shared__ uint32_t wsum[16];
+  __shared__ uint32_t carry_s;
+  if (tid == 0) carry_s = 0u;
   __syncthreads();
-  // Hillis-Steele inclusive scan over the per-thread sums.
-  for (int o = 1; o < T; o <<= 1) {
-    const uint32_t add = threadIdx.x >= (unsigned)o ? part[threadIdx.x - o] : 0u;
+  for (int64_t t0 = 0; t0 < ncols; t0 += 4 * (int64_t)T) {
+    const int64_t b = t0 + 4 * (int64_t)tid;
+    uint32_t c[4], sum = 0;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      c[j] = b + j < ncols ? F.cur[b + j] : 0u;
+      sum += c[j];
+    }
+    uint32_t inc = sum;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const uint32_t v = __shfl_up(inc, o, 64);
+      if (lane >= o) inc += v;
+    }
+    if (lane == 63) wsum[wid] = inc;
     __syncthreads();
-    part[threadIdx.x] += add;
+    uint32_t wbase = carry_s;
+    for (int w = 0; w < wid; ++w) wbase += wsum[w];
+    uint32_t run = wbase + inc - sum;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      if (b + j < ncols) {
+        F.off[b + j] = run;
+        F.cur[b + j] = run;
+      }
+      run += c[j];
+    }
+    __syncthreads();
+    if (tid == T - 1) carry_s = run;
     __syncthreads();
   }
-  uint32_t run = part[threadIdx.x] - sum;
-  for (int64_t k = b; k < e; ++k) {
-    const uint32_t c = F.cur[k];
-    F.off[k] = run;
-    F.cur[k] = run;
-    run += c;
-  }
-  if (threadIdx.x == T - 1) F.off[ncols] = part[T - 1];
+  if (tid == 0) F.off[ncols] = carry_s;
 }
 
 __global__ void __launch_bounds__(256) k_frame_scatter(const FrameDev *__restrict__ frames) {
   const FrameDev &F = frames[blockIdx.y];
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < F.n;
-       i += (int64_t)gridDim.x * blockDim.x) {
-    const Rotated r = rotate_point(F, i);
-    if (r.col < 0) continue;
-    const uint32_t pos = atomicAdd(&F.cur[r.col], 1u);
-    F.v[pos] = r.vx;
-    F.v[F.n + pos] = r.vy;
-    F.v[2 * F.n + pos] = r.vz;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  const int lane = threadIdx.x & 63;
+  for (int64_t i0 = (int64_t)blockIdx.x * blockDim.x; i0 < F.n; i0 += stride) {
+    const int64_t i = i0 + threadIdx.x;
+    Rotated rp;
+    rp.col = -1;
+    if (i < F.n) rp = rotate_point(F, i);
+    const ColRun r = col_runs(rp.col);
+    uint32_t base = 0;
+    if (r.head) base = atomicAdd(&F.cur[rp.col], r.len);
+    base = __shfl(base, r.head_lane, 64);
+    if (rp.col < 0) continue;
+    const uint32_t pos = base + (uint32_t)(lane - r.head_lane);
+    F.v[pos] = rp.vx;
+    F.v[F.n + pos] = rp.vy;
+    F.v[2 * F.n + pos] = rp.vz;
   }
 }
 

@@ -145,7 +145,7 @@ struct Tuning {
   int32_t waves = 8;
   int32_t hash_bytes = 48 * 1024;
   int32_t hist_copies = 2;
-  int32_t stripe_rows = 8;
+  int32_t stripe_rows = 12;
   int32_t wgs_per_cu = 0;
 };
 Tuning g_tuning;
@@ -533,34 +533,56 @@ struct BitsHash {
 
 // Distinct rotations, per-pose translation offsets c = fl(fl(t - origin) * s),
 // items sorted by frame, and the column grid covering every rotated position
-// from which some pose's offset reaches A's grid.
+// from which some pose's offset reaches A's grid.  Poses with bit-identical
+// (roll, pitch, yaw) share a frame; the matrix is built once per distinct
+// triple, and poses whose different triples give bit-identical matrices are
+// merged too.
 int build_tables(const GridInfo &gi, const double *poses, int64_t K, PoseTables &T) {
   T.K = K;
   T.R.clear();
-  T.items.resize((size_t)K);
-  std::unordered_map<BitsKey, int32_t, BitsHash> seen;
-  seen.reserve((size_t)K * 2 + 1);
-  std::vector<int32_t> frame_of((size_t)K);
+  std::vector<PoseDev> items((size_t)K);
+  struct AngKey {
+    uint64_t w[3];
+    bool operator==(const AngKey &o) const { return w[0] == o.w[0] && w[1] == o.w[1] && w[2] == o.w[2]; }
+  };
+  struct AngHash {
+    size_t operator()(const AngKey &k) const {
+      uint64_t h = 1469598103934665603ull;
+      for (int i = 0; i < 3; ++i) { h ^= k.w[i]; h *= 1099511628211ull; }
+      return (size_t)h;
+    }
+  };
+  std::unordered_map<AngKey, int32_t, AngHash> by_angles;
+  std::unordered_map<BitsKey, int32_t, BitsHash> by_matrix;
+  by_angles.reserve(1024);
+  by_matrix.reserve(1024);
   double cmin[3] = {INFINITY, INFINITY, INFINITY}, cmax[3] = {-INFINITY, -INFINITY, -INFINITY};
   for (int64_t k = 0; k < K; ++k) {
     const double *eta = poses + 6 * k;
     for (int a = 0; a < 6; ++a)
       if (!std::isfinite(eta[a])) return -1;
-    double R[9];
-    pose_rotation(eta, R);
-    BitsKey key;
-    memcpy(key.w, R, sizeof key.w);
-    auto it = seen.find(key);
+    AngKey ak;
+    memcpy(ak.w, eta + 3, sizeof ak.w);
     int32_t fidx;
-    if (it == seen.end()) {
-      fidx = (int32_t)(T.R.size() / 9);
-      seen.emplace(key, fidx);
-      T.R.insert(T.R.end(), R, R + 9);
+    auto ia = by_angles.find(ak);
+    if (ia != by_angles.end()) {
+      fidx = ia->second;
     } else {
-      fidx = it->second;
+      double R[9];
+      pose_rotation(eta, R);
+      BitsKey key;
+      memcpy(key.w, R, sizeof key.w);
+      auto im = by_matrix.find(key);
+      if (im == by_matrix.end()) {
+        fidx = (int32_t)(T.R.size() / 9);
+        by_matrix.emplace(key, fidx);
+        T.R.insert(T.R.end(), R, R + 9);
+      } else {
+        fidx = im->second;
+      }
+      by_angles.emplace(ak, fidx);
     }
-    frame_of[(size_t)k] = fidx;
-    PoseDev &p = T.items[(size_t)k];
+    PoseDev &p = items[(size_t)k];
     p.pair = 0;
     p.frame = fidx;
     p.out_index = (int32_t)k;
@@ -572,8 +594,14 @@ int build_tables(const GridInfo &gi, const double *poses, int64_t K, PoseTables 
     }
   }
   T.F = (int32_t)(T.R.size() / 9);
-  std::stable_sort(T.items.begin(), T.items.end(),
-                   [](const PoseDev &a, const PoseDev &b) { return a.frame < b.frame; });
+  // counting sort by frame, stable within a frame
+  {
+    std::vector<int64_t> start((size_t)T.F + 1, 0);
+    for (const PoseDev &p : items) ++start[(size_t)p.frame + 1];
+    for (int32_t f = 0; f < T.F; ++f) start[(size_t)f + 1] += start[(size_t)f];
+    T.items.resize((size_t)K);
+    for (const PoseDev &p : items) T.items[(size_t)start[(size_t)p.frame]++] = p;
+  }
   if (K == 0) { cmin[0] = cmin[1] = cmin[2] = cmax[0] = cmax[1] = cmax[2] = 0.0; }
   // v in (-c - eps, dims - c + eps) for some pose: columns floor(v) within
   // [floor(min(-c)) - 1, floor(max(dims - c)) + 1].
