@@ -62,7 +62,6 @@ __host__ __device__ inline Layout eval_layout(int waves, int hist_copies, int hi
   L.off_cnta = o;   o += 512;                   // cntA[2][64]
   L.off_edges = o;  o += 256 + 512 + 512;       // 64 u32 + 64 u64 + 64 f64
   L.off_wave = o;   o += al16(waves * 48 + 16); // box [W][8] i32, counts [W][2] u64, flags
-  o += 64 * 4 + 64 * 16;                        // dummy targets of masked lanes
   L.off_plan = o;   o += al16(plan_bytes);
   o = (o + 255) & ~255;
   L.off_hash = o;   o += cap * (4 + (zvar ? 16 : 4)) + 2 * cap;  // keys, sums, occupied list
@@ -154,8 +153,6 @@ __global__ void __launch_bounds__(1024) k_eval(const PairDev *__restrict__ pairs
   unsigned long long *wcnt = (unsigned long long *)(wbox + 8 * W);
   uint32_t *ovf = (uint32_t *)(wcnt + 2 * W);   // [2] overflow flags by brick parity
   uint32_t *occn = ovf + 2;                     // [2] occupied-slot counts by brick parity
-  uint32_t *dkey = (uint32_t *)(smem + cfg.off_wave + al16(W * 48 + 16));
-  unsigned long long *dval = (unsigned long long *)(dkey + 64);
   uint2 *plan = (uint2 *)(smem + cfg.off_plan);
   const int cap = 1 << cfg.cap_log2;
   uint32_t *hkey = (uint32_t *)(smem + cfg.off_hash);
@@ -342,8 +339,19 @@ __global__ void __launch_bounds__(1024) k_eval(const PairDev *__restrict__ pairs
                 if (lane >= o) inc += t;
               }
               const uint32_t my_cpre = inc - my_c;
+              // A brick of the whole stripe reads its rows' candidates as one
+              // contiguous range (between two rows lie only columns outside the
+              // grid's x range), cut into chunks of 256 without per-row padding.
+              const bool contig = !DIRECT && whole && qa == 0 && qend == Q && nr > 0;
+              uint32_t cs = 0, ce = 0;
+              if (contig) {
+                cs = ps[ra * (Q + 1)].x;
+                ce = ps[(ra + nr - 1) * (Q + 1) + Q].y;
+                if (ce < cs) ce = cs;
+              }
               const int nch = DIRECT ? (int)((bend - bst + 63u) >> 6)
-                                     : (nr > 0 ? (int)__shfl(inc, nr - 1, 64) : 0);
+                              : contig ? (int)((ce - cs + 255u) >> 8)
+                                       : (nr > 0 ? (int)__shfl(inc, nr - 1, 64) : 0);
               if (nch == 0) continue;
               const int p = parity;
               unsigned long long bnear = 0;
@@ -381,10 +389,10 @@ __global__ void __launch_bounds__(1024) k_eval(const PairDev *__restrict__ pairs
                 bool coll[4], fresh[4];
   #pragma unroll
                 for (int i = 0; i < 4; ++i) {
-                  // one compare-and-swap finds or claims the home slot; masked lanes
-                  // swap on their own dummy word with a value that never matches
-                  uint32_t *a = inb[i] ? &hkey[h[i]] : &dkey[lane];
-                  const uint32_t old = atomicCAS(a, inb[i] ? kEmpty : kNever, key[i]);
+                  // one compare-and-swap finds or claims the home slot (only lanes
+                  // holding a run issue it)
+                  uint32_t old = kEmpty;
+                  if (inb[i]) old = atomicCAS(&hkey[h[i]], kEmpty, key[i]);
                   fresh[i] = inb[i] && old == kEmpty;
                   coll[i] = inb[i] && old != kEmpty && old != key[i];
                 }
@@ -433,13 +441,13 @@ __global__ void __launch_bounds__(1024) k_eval(const PairDev *__restrict__ pairs
                 }
   #pragma unroll
                 for (int i = 0; i < 4; ++i) {
-                  if (ZVAR) {
-                    unsigned long long *a1 = inb[i] ? &hv1[h[i]] : &dval[lane];
-                    unsigned long long *a2 = inb[i] ? &hv2[h[i]] : &dval[64 + lane];
-                    atomicAdd(a1, add1[i]);
-                    atomicAdd(a2, add2[i]);
-                  } else {
-                    atomicAdd(inb[i] ? &hcnt[h[i]] : &dkey[lane], (uint32_t)add1[i]);
+                  if (inb[i]) {
+                    if (ZVAR) {
+                      atomicAdd(&hv1[h[i]], add1[i]);
+                      atomicAdd(&hv2[h[i]], add2[i]);
+                    } else {
+                      atomicAdd(&hcnt[h[i]], (uint32_t)add1[i]);
+                    }
                   }
                 }
               };
@@ -528,7 +536,14 @@ __global__ void __launch_bounds__(1024) k_eval(const PairDev *__restrict__ pairs
               }
               for (int k = wid; !DIRECT && k < nch; k += W) {
                 int nv;
-                const uint32_t b = chunk_base(k, &nv);
+                uint32_t b;
+                if (contig) {
+                  const uint32_t b0 = cs + ((uint32_t)k << 8) + 4u * (uint32_t)lane;
+                  nv = (int)ce - (int)b0;
+                  b = nv > 0 ? b0 : cs;
+                } else {
+                  b = chunk_base(k, &nv);
+                }
                 bool v[4];
                 double x[4], y[4], z[4];
                 // the frame arrays are padded, so base + 3 is always readable
