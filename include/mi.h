@@ -112,8 +112,9 @@ const char *mi_last_error(void);
 /* Launch shape of the batched evaluator (process-wide; read when a plan is
  * created).  waves: 1..16 waves per workgroup (a workgroup evaluates one pose
  * at a time); hash_bytes: LDS bytes for the voxel sums of one brick (the slot
- * count is the largest power of two that fits); hist_copies: 1..8 privatized
- * joint histograms; stripe_rows: 1..62 voxel rows per stripe of bricks;
+ * count is the largest multiple of 64 that fits, at most 65536); hist_copies:
+ * 1..8 privatized joint histograms; stripe_rows: 1..62 voxel rows per stripe
+ * of bricks;
  * wgs_per_cu: 0 launches one workgroup per pose, 1..16 a persistent grid of
  * that many workgroups per compute unit, each looping over poses.  Every
  * setting gives bit-identical histograms. */

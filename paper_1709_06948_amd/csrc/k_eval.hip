@@ -43,7 +43,7 @@ static constexpr int kMaxProbe = 32;
 
 struct EvalCfgDev {
   int32_t hist_copies, hist_words;
-  int32_t cap_log2;
+  int32_t cap;                // voxel-hash slots
   int32_t load_max;           // voxels of a brick that is known to fit (a quarter of the slots)
   int32_t off_cnta, off_edges, off_wave, off_plan, off_hash, pad;
   int64_t xcd_start[kXcds + 1];  // items of XCD x: [xcd_start[x], xcd_start[x + 1])
@@ -154,7 +154,7 @@ __global__ void __launch_bounds__(1024) k_eval(const PairDev *__restrict__ pairs
   uint32_t *ovf = (uint32_t *)(wcnt + 2 * W);   // [2] overflow flags by brick parity
   uint32_t *occn = ovf + 2;                     // [2] occupied-slot counts by brick parity
   uint2 *plan = (uint2 *)(smem + cfg.off_plan);
-  const int cap = 1 << cfg.cap_log2;
+  const int cap = cfg.cap;
   uint32_t *hkey = (uint32_t *)(smem + cfg.off_hash);
   unsigned long long *hv1 = (unsigned long long *)(hkey + cap);   // ZVAR: n<<44 | S1
   unsigned long long *hv2 = hv1 + cap;                            // ZVAR: S2
@@ -214,6 +214,11 @@ __global__ void __launch_bounds__(1024) k_eval(const PairDev *__restrict__ pairs
     int lo0 = nx, lo1 = ny, lo2 = nz, hi0 = -1, hi1 = -1, hi2 = -1;
     unsigned long long nin = 0, nnear = 0;
     int parity = 0;
+    // Pieces a stripe's first brick spans: the span that last fitted, doubled
+    // after a brick that used under a third of the slots (adapts to how many
+    // voxels the points fill, so that overflow retries stay rare).
+    int span = 1 << 30;
+    int last_occ = 0;
 
     // DIRECT: the pose's in-grid points bucketed by stripe into this
     // workgroup's scratch slot; soff[s] .. soff[s + 1] is stripe s.
@@ -309,7 +314,7 @@ __global__ void __launch_bounds__(1024) k_eval(const PairDev *__restrict__ pairs
         const uint2 *ps = plan + sl * PE;
         int qa = 0;
         while (qa < Q) {
-          int qe = Q;
+          int qe = qa + min(span, Q - qa);
           for (;;) {
             const bool whole = qe > qa;  // false: piece qa voxel row by voxel row
             const int qend = whole ? qe : qa + 1;
@@ -385,7 +390,7 @@ __global__ void __launch_bounds__(1024) k_eval(const PairDev *__restrict__ pairs
                                  const unsigned long long (&add2)[4]) {
                 uint32_t h[4];
   #pragma unroll
-                for (int i = 0; i < 4; ++i) h[i] = (key[i] * 2654435761u) >> (32 - cfg.cap_log2);
+                for (int i = 0; i < 4; ++i) h[i] = __umulhi(key[i] * 2654435761u, (uint32_t)cap);
                 bool coll[4], fresh[4];
   #pragma unroll
                 for (int i = 0; i < 4; ++i) {
@@ -403,7 +408,7 @@ __global__ void __launch_bounds__(1024) k_eval(const PairDev *__restrict__ pairs
                     uint32_t hh = h[i];
                     bool ok = false;
                     for (int pr = 1; pr < max_probe; ++pr) {
-                      hh = (hh + 1u) & (uint32_t)(cap - 1);
+                      hh = hh + 1u == (uint32_t)cap ? 0u : hh + 1u;
                       uint32_t k1 = __atomic_load_n(&hkey[hh], __ATOMIC_RELAXED);
                       if (k1 == kEmpty) {
                         k1 = atomicCAS(&hkey[hh], kEmpty, key[i]);
@@ -559,6 +564,7 @@ __global__ void __launch_bounds__(1024) k_eval(const PairDev *__restrict__ pairs
               __syncthreads();
               const bool overflow = ovf[p] != 0u;
               const int nocc = (int)occn[p];
+              last_occ = nocc;
               if (tid == 0) { ovf[p ^ 1] = 0u; occn[p ^ 1] = 0u; }
               int blo0 = nx, blo1 = ny, blo2 = nz, bhi0 = -1, bhi1 = -1, bhi2 = -1;
               unsigned long long bnin = 0;
@@ -616,7 +622,14 @@ __global__ void __launch_bounds__(1024) k_eval(const PairDev *__restrict__ pairs
               lo0 = min(lo0, blo0); lo1 = min(lo1, blo1); lo2 = min(lo2, blo2);
               hi0 = max(hi0, bhi0); hi1 = max(hi1, bhi1); hi2 = max(hi2, bhi2);
             }
-            if (all_ok) { qa = qend; break; }
+            if (all_ok) {
+              if (whole) {
+                span = qend - qa;
+                if (3 * last_occ < cap) span = min(2 * span, Q);
+              }
+              qa = qend;
+              break;
+            }
             // overflow: halve the run of pieces; a single piece goes row by row
             qe = qe - qa > 1 ? qa + (qe - qa) / 2 : qa;
           }
@@ -743,7 +756,7 @@ __global__ void __launch_bounds__(1024) k_eval(const PairDev *__restrict__ pairs
 int32_t eval_hash_slot_bytes(bool zvar) { return 4 + (zvar ? 16 : 4) + 2; }
 
 size_t eval_lds_bytes(const EvalLaunch &c) {
-  return (size_t)eval_layout(c.waves, c.hist_copies, c.hist_words, c.plan_bytes, 1 << c.cap_log2,
+  return (size_t)eval_layout(c.waves, c.hist_copies, c.hist_words, c.plan_bytes, c.cap,
                              c.zvar)
       .total;
 }
@@ -754,12 +767,12 @@ static hipError_t launch_one(const PairDev *pairs_dev, const FrameDev *frames_de
                              const EvalLaunch &c, uint2 *scratch, int64_t scratch_stride,
                              int64_t max_wgs, hipStream_t s) {
   const Layout L = eval_layout(c.waves, c.hist_copies, c.hist_words, c.plan_bytes,
-                               1 << c.cap_log2, c.zvar);
+                               c.cap, c.zvar);
   EvalCfgDev d;
   d.hist_copies = c.hist_copies;
   d.hist_words = c.hist_words;
-  d.cap_log2 = c.cap_log2;
-  d.load_max = (1 << c.cap_log2) / 4;
+  d.cap = c.cap;
+  d.load_max = c.cap / 4;
   d.off_cnta = L.off_cnta;
   d.off_edges = L.off_edges;
   d.off_wave = L.off_wave;
@@ -792,7 +805,7 @@ static hipError_t launch_one(const PairDev *pairs_dev, const FrameDev *frames_de
 // XCD count.
 hipError_t eval_resident_wgs(const EvalLaunch &c, int per_cu, int64_t *out) {
   const Layout L = eval_layout(c.waves, c.hist_copies, c.hist_words, c.plan_bytes,
-                               1 << c.cap_log2, c.zvar);
+                               c.cap, c.zvar);
   hipError_t e;
   int dev = 0, cus = 0, occ = 0;
   if ((e = hipGetDevice(&dev)) != hipSuccess) return e;

@@ -143,9 +143,9 @@ hipError_t staging_upload(Staging *s, const Upload *ups, int n, hipStream_t st) 
 namespace {
 struct Tuning {
   int32_t waves = 8;
-  int32_t hash_bytes = 48 * 1024;
-  int32_t hist_copies = 2;
-  int32_t stripe_rows = 12;
+  int32_t hash_bytes = 60 * 1024;
+  int32_t hist_copies = 1;
+  int32_t stripe_rows = 16;
   int32_t wgs_per_cu = 0;
 };
 Tuning g_tuning;
@@ -630,7 +630,7 @@ int bits_for(int64_t n) {  // bits to hold 0..n-1
 // Stripes, plan pieces, hash capacity and key packing of one pair under a
 // tuning (see k_eval.hip for how the evaluator uses them).
 struct StripeShape {
-  int stripe_h, n_stripes, pieces, kx_bits, ky_bits, cap_log2, plan_stripes, plan_entries;
+  int stripe_h, n_stripes, pieces, kx_bits, ky_bits, cap, plan_stripes, plan_entries;
   bool zvar;
 };
 
@@ -638,13 +638,14 @@ bool choose_stripes(const GridInfo &gi, const Tuning &tu, bool zvar, StripeShape
                     const char **why) {
   S.zvar = zvar;
   const int slot = eval_hash_slot_bytes(S.zvar);
-  int cl = 6;
-  while (cl < 16 && ((int64_t)1 << (cl + 1)) * slot <= tu.hash_bytes) ++cl;
-  if (((int64_t)1 << cl) * slot > tu.hash_bytes) { *why = "hash_bytes too small"; return false; }
-  S.cap_log2 = cl;
+  // slots: as many as hash_bytes holds, a multiple of 64, at most 65536 (the
+  // occupied list stores slot indices in 16 bits)
+  const int64_t cap = std::min<int64_t>(65536, ((int64_t)tu.hash_bytes / slot) & ~(int64_t)63);
+  if (cap < 64) { *why = "hash_bytes too small"; return false; }
+  S.cap = (int)cap;
   // bricks of at most a quarter of the slots in voxels always fit; single voxel
   // rows of an x piece must be such bricks
-  const int64_t load_max = ((int64_t)1 << cl) / 4;
+  const int64_t load_max = cap / 4;
   const int nx = gi.dims[0], ny = gi.dims[1], nz = gi.dims[2];
   const int64_t wmax = load_max / nz;  // widest x piece whose single voxel row always fits
   if (wmax < 1) { *why = "grid height exceeds the voxel hash"; return false; }
@@ -658,7 +659,7 @@ bool choose_stripes(const GridInfo &gi, const Tuning &tu, bool zvar, StripeShape
   if (S.kx_bits + S.ky_bits + bits_for(nz) > 31) { *why = "grid dims exceed the voxel key"; return false; }
   S.plan_entries = (S.stripe_h + 2) * (S.pieces + 1);
   S.plan_stripes = (int)std::max<int64_t>(1, std::min<int64_t>(S.n_stripes,
-                                                                16384 / (S.plan_entries * 8)));
+                                                                8192 / (S.plan_entries * 8)));
   return true;
 }
 
@@ -789,12 +790,23 @@ mi_status prepare_batch(const mi_work_item *w, int64_t n, uint32_t flags, BatchT
     const char *why = "";
     if (!choose_stripes(gi, tu, zvar, B.SS[(size_t)i], &why))
       return fail(MI_E_UNSUPPORTED, "work item %lld: evaluator: %s", (long long)i, why);
-    const StripeShape &S = B.SS[(size_t)i];
     const PoseTables &T = B.T[(size_t)i];
     // a rotation shared by fewer than two poses on average is not worth a frame
     const bool direct = (flags & MI_EVAL_PER_POSE) ||
                         (!(flags & MI_EVAL_SHARED_FRAMES) && it.K > 0 && 2 * (int64_t)T.F > it.K);
     B.direct[(size_t)i] = direct;
+    if (direct) {
+      // A per-pose brick rescans its stripe's whole bucket, so overflow retries
+      // are costly: stripes are sized for about a third of the slots, taking
+      // about 0.6 occupied voxels per point spread evenly over the rows.
+      const StripeShape &S0 = B.SS[(size_t)i];
+      const double per_row = 0.6 * (double)std::max<int64_t>(it.n_b, 1) / (double)gi.dims[1];
+      Tuning t2 = tu;
+      t2.stripe_rows = (int)std::max(1.0, std::min((double)tu.stripe_rows, S0.cap / 3.0 / per_row));
+      if (!choose_stripes(gi, t2, zvar, B.SS[(size_t)i], &why))
+        return fail(MI_E_UNSUPPORTED, "work item %lld: evaluator: %s", (long long)i, why);
+    }
+    const StripeShape &S = B.SS[(size_t)i];
     if (direct) {
       plan_bytes_max = std::max(plan_bytes_max, (2 * S.n_stripes + 1) * 4);
       B.scratch_stride = std::max(B.scratch_stride, std::max<int64_t>(it.n_b, 1));
@@ -818,7 +830,7 @@ mi_status prepare_batch(const mi_work_item *w, int64_t n, uint32_t flags, BatchT
   B.F = f;
   EvalLaunch &L = B.L;
   L.waves = tu.waves;
-  L.cap_log2 = n > 0 ? B.SS[0].cap_log2 : 6;
+  L.cap = n > 0 ? B.SS[0].cap : 64;
   L.hist_copies = tu.hist_copies;
   L.hist_words = hist_words;
   L.plan_bytes = plan_bytes_max;
@@ -1294,12 +1306,12 @@ extern "C" mi_status mi_autotune(const mi_work_item *items, int64_t n_items, uin
   if (st == MI_OK && start_ms >= 0.0) { best_ms = start_ms; best = start; }
   // stage 1: workgroup size and hash capacity
   const int waves[3] = {4, 8, 16};
-  const int hashk[5] = {24, 32, 48, 64, 96};
+  const int hashk[7] = {24, 32, 48, 56, 60, 64, 96};
   for (int w : waves)
-    for (int hk : hashk) consider(mi_tuning{w, hk * 1024, 2, 8, 0});
+    for (int hk : hashk) consider(mi_tuning{w, hk * 1024, 1, 12, 0});
   // stage 2: stripe height and histogram privatization around the best
   const mi_tuning b1 = best;
-  const int rows[5] = {4, 8, 12, 16, 24};
+  const int rows[6] = {4, 8, 12, 16, 20, 24};
   const int copies[3] = {1, 2, 4};
   for (int r : rows)
     for (int h : copies) consider(mi_tuning{b1.waves, b1.hash_bytes, h, r, 0});

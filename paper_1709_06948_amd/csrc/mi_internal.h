@@ -112,7 +112,7 @@ struct PoseDev {
 // Launch shape of the evaluator (one workgroup per pose).
 struct EvalLaunch {
   int32_t waves;             // waves per workgroup (1..16)
-  int32_t cap_log2;          // LDS voxel-hash slots = 1 << cap_log2
+  int32_t cap;               // LDS voxel-hash slots (a multiple of 64)
   int32_t hist_copies;       // privatized joint-histogram copies
   int32_t hist_words;        // max over pairs of sum_f nb_f^2
   int32_t plan_bytes;        // max over pairs of plan_stripes * rows * (pieces + 1) * 8

@@ -203,7 +203,7 @@ def tuning_get() -> dict:
                 stripe_rows=t.stripe_rows, wgs_per_cu=t.wgs_per_cu)
 
 
-def tuning_set(waves: int, hash_bytes: int, hist_copies: int = 2, stripe_rows: int = 12,
+def tuning_set(waves: int, hash_bytes: int, hist_copies: int = 1, stripe_rows: int = 16,
                wgs_per_cu: int = 0):
     t = _Tuning(int(waves), int(hash_bytes), int(hist_copies), int(stripe_rows), int(wgs_per_cu))
     _check(_lib.mi_tuning_set(C.byref(t)), "mi_tuning_set")
