@@ -327,6 +327,35 @@ mi_status mi_align_coarse_to_fine(const mi_ref *r, const float *xyz_b, int64_t n
                                   const double init[6], const mi_c2f_desc *d, double pose_out[6],
                                   double *mi_out, void *ws, size_t ws_bytes, void *stream);
 
+/* Simplex search for Eq. 1 (Alg. 1 with the Nelder-Mead update of
+ * Sec. III-B): maximises the MI of feature slot `feature_slot` over the pose.
+ * Each start gets a simplex of N + 1 = 7 vertices (the start, and the start
+ * moved by step[i] along parameter i; Sec. IV uses steps 8, 8, 1 m, 0.1, 0.1,
+ * 0.8 rad), improved with the usual coefficients (reflection 1, expansion 2,
+ * contraction 1/2, shrink 1/2).  An iteration evaluates the reflection,
+ * expansion and both contractions of the worst vertex together (speculatively)
+ * and keeps the one the method asks for; a failed contraction shrinks the
+ * simplex towards its best vertex.  A simplex stops after max_iter iterations
+ * or when all its vertices are within xtol (max norm) and their MI within
+ * ftol of its best.  The n_starts simplexes advance together: each round is
+ * one batched evaluation of every pending point, then one synchronisation.
+ * pose_out / mi_out: the best final vertex over all starts (ties: earlier
+ * start); iters_out (host, [n_starts], nullable): iterations per start.
+ * ws from mi_align_nm_workspace. */
+typedef struct mi_nm_desc {
+  double step[6];
+  int32_t max_iter;
+  double ftol;
+  double xtol;
+  int32_t feature_slot;
+} mi_nm_desc;
+
+size_t mi_align_nm_workspace(const mi_ref *r, int64_t n_b, int32_t n_starts);
+mi_status mi_align_nelder_mead(const mi_ref *r, const float *xyz_b, int64_t n_b,
+                               const double *starts, int32_t n_starts, const mi_nm_desc *d,
+                               double pose_out[6], double *mi_out, int32_t *iters_out, void *ws,
+                               size_t ws_bytes, void *stream);
+
 /* ------------------------------------------------------------ serving */
 
 /* A request loop for many alignments (Alg. 1 per request, with the search of

@@ -252,3 +252,86 @@ def align_c2f(grid: Grid, A, B, init, half, samples, levels, shrink, feature_slo
     if rc:
         raise RuntimeError(f"mio_align_c2f failed ({rc})")
     return out, float(best[0])
+
+
+# --------------------------------------------------------------- simplex search
+
+NM_REFLECT, NM_EXPAND, NM_CONTRACT, NM_SHRINK = 1.0, 2.0, 0.5, 0.5
+
+
+def nelder_mead(f, x0, steps, max_iter, ftol, xtol):
+    """Nelder-Mead simplex minimisation of f (Sec. III-B: a simplex of N+1
+    points improved by reflecting, expanding, contracting or shrinking; the
+    method of the cited Nelder & Mead paper with its usual coefficients
+    1, 2, 1/2, 1/2).  Vertex 0 is x0, vertex i is x0 + steps[i-1] along axis
+    i-1.  Vertices are kept ordered by f, ties by age (stable sort).  Each
+    iteration reflects the worst vertex through the centroid of the others;
+    a reflection better than the best is tried expanded; one that is no better
+    than the second worst is contracted (outside if it beats the worst, else
+    inside), and a failed contraction shrinks every vertex halfway towards the
+    best.  Stops after max_iter iterations, or when every vertex is within
+    xtol (max norm) of the best and every value within ftol of the best.
+    f takes a list of points and returns their values (so a caller may batch).
+    Returns (best point, best value, iterations)."""
+    x0 = np.asarray(x0, np.float64)
+    n = x0.size
+    simplex = [x0.copy()]
+    for i in range(n):
+        v = x0.copy()
+        v[i] = v[i] + steps[i]
+        simplex.append(v)
+    values = list(f(simplex))
+    it = 0
+    while True:
+        order = sorted(range(n + 1), key=lambda k: values[k])  # stable
+        simplex = [simplex[k] for k in order]
+        values = [values[k] for k in order]
+        best, worst = values[0], values[n]
+        spread_x = max(float(np.max(np.abs(simplex[k] - simplex[0]))) for k in range(1, n + 1))
+        spread_f = max(abs(values[k] - best) for k in range(1, n + 1))
+        if it >= max_iter or (spread_x <= xtol and spread_f <= ftol):
+            return simplex[0], values[0], it
+        it += 1
+        centroid = simplex[0].copy()
+        for k in range(1, n):
+            centroid = centroid + simplex[k]
+        centroid = centroid / n
+        xw = simplex[n]
+        xr = centroid + NM_REFLECT * (centroid - xw)
+        xe = centroid + NM_EXPAND * (xr - centroid)
+        xoc = centroid + NM_CONTRACT * (xr - centroid)
+        xic = centroid + NM_CONTRACT * (xw - centroid)
+        fr, fe, foc, fic = f([xr, xe, xoc, xic])
+        second = values[n - 1]
+        if fr < best:
+            if fe < fr:
+                simplex[n], values[n] = xe, fe
+            else:
+                simplex[n], values[n] = xr, fr
+            continue
+        if fr < second:
+            simplex[n], values[n] = xr, fr
+            continue
+        if fr < worst:
+            if foc <= fr:
+                simplex[n], values[n] = xoc, foc
+                continue
+        elif fic < worst:
+            simplex[n], values[n] = xic, fic
+            continue
+        shrunk = [simplex[0] + NM_SHRINK * (simplex[k] - simplex[0]) for k in range(1, n + 1)]
+        fs = list(f(shrunk))
+        simplex = [simplex[0]] + shrunk
+        values = [values[0]] + fs
+
+
+def align_nelder_mead(grid: Grid, A, B, init, steps, max_iter, ftol, xtol, feature_slot=0,
+                      nthreads=0):
+    """Alg. 1 with the Nelder-Mead update of Sec. III-B: maximise Eq. 1 (MI of
+    feature slot `feature_slot`) over the pose from T_o = init.  Returns
+    (pose[6], MI, iterations)."""
+    def cost(points):
+        mi, _, _ = eval_poses(grid, A, B, np.asarray(points), nthreads=nthreads)
+        return [-float(v) for v in mi[feature_slot]]
+    x, v, it = nelder_mead(cost, init, steps, max_iter, ftol, xtol)
+    return x, -v, it

@@ -843,6 +843,9 @@ mi_status prepare_batch(const mi_work_item *w, int64_t n, uint32_t flags, BatchT
   if (B.n_frame_items < B.n_items) {
     hipError_t e = eval_resident_wgs(L, L.wgs_per_cu > 0 ? L.wgs_per_cu : 2, &B.scratch_slots);
     if (e != hipSuccess) return dev_fail(e, "occupancy of the per-pose evaluator");
+    // no more slots than the launch can use (a multiple of the XCD count)
+    const int64_t nd = B.n_items - B.n_frame_items;
+    B.scratch_slots = std::min<int64_t>(B.scratch_slots, ((nd + kXcds - 1) / kXcds) * kXcds);
   }
   return MI_OK;
 }
@@ -2000,4 +2003,199 @@ extern "C" void mi_server_destroy(mi_server *s) {
   }
   if (s->pinned) (void)hipHostFree(s->pinned);
   delete s;
+}
+
+// ----------------------------------------------------------- simplex search
+
+namespace {
+
+constexpr double kNmReflect = 1.0, kNmExpand = 2.0, kNmContract = 0.5, kNmShrink = 0.5;
+
+// One Nelder-Mead simplex over the 6 pose parameters, minimising g = -MI.
+// States: kInit needs the 7 vertices, kStep the 4 speculative candidates of
+// an iteration (reflection, expansion, outside and inside contraction), kShrink
+// the 6 shrunk vertices.
+struct Simplex {
+  enum State { kInit, kStep, kShrink, kDone };
+  State state = kInit;
+  double x[7][6];
+  double g[7];
+  double cand[6][6];   // points whose values are awaited
+  int n_cand = 0;
+  int32_t iters = 0;
+
+  void order() {  // by value, ties by position (stable insertion sort)
+    for (int i = 1; i < 7; ++i)
+      for (int j = i; j > 0 && g[j] < g[j - 1]; --j) {
+        std::swap(g[j], g[j - 1]);
+        for (int a = 0; a < 6; ++a) std::swap(x[j][a], x[j - 1][a]);
+      }
+  }
+  bool converged(const mi_nm_desc &d) const {
+    double sx = 0.0, sf = 0.0;
+    for (int k = 1; k < 7; ++k) {
+      for (int a = 0; a < 6; ++a) sx = std::max(sx, std::fabs(x[k][a] - x[0][a]));
+      sf = std::max(sf, std::fabs(g[k] - g[0]));
+    }
+    return sx <= d.xtol && sf <= d.ftol;
+  }
+  // after the vertices are ordered: stop, or set up the next iteration's candidates
+  void next(const mi_nm_desc &d) {
+    if (iters >= d.max_iter || converged(d)) { state = kDone; n_cand = 0; return; }
+    ++iters;
+    double c[6];
+    for (int a = 0; a < 6; ++a) {
+      double s = x[0][a];
+      for (int k = 1; k < 6; ++k) s = s + x[k][a];
+      c[a] = s / 6.0;
+    }
+    for (int a = 0; a < 6; ++a) {
+      const double xr = c[a] + kNmReflect * (c[a] - x[6][a]);
+      cand[0][a] = xr;
+      cand[1][a] = c[a] + kNmExpand * (xr - c[a]);
+      cand[2][a] = c[a] + kNmContract * (xr - c[a]);
+      cand[3][a] = c[a] + kNmContract * (x[6][a] - c[a]);
+    }
+    state = kStep;
+    n_cand = 4;
+  }
+  // values of the awaited points are in v[0 .. n_cand)
+  void take(const double *v, const mi_nm_desc &d) {
+    if (state == kInit) {
+      for (int k = 0; k < 7; ++k) g[k] = v[k];
+      order();
+      next(d);
+      return;
+    }
+    if (state == kShrink) {
+      for (int k = 1; k < 7; ++k) {
+        for (int a = 0; a < 6; ++a) x[k][a] = cand[k - 1][a];
+        g[k] = v[k - 1];
+      }
+      order();
+      next(d);
+      return;
+    }
+    const double fr = v[0], fe = v[1], foc = v[2], fic = v[3];
+    const double best = g[0], second = g[5], worst = g[6];
+    int accept = -1;
+    if (fr < best) accept = fe < fr ? 1 : 0;
+    else if (fr < second) accept = 0;
+    else if (fr < worst) { if (foc <= fr) accept = 2; }
+    else if (fic < worst) accept = 3;
+    if (accept >= 0) {
+      for (int a = 0; a < 6; ++a) x[6][a] = cand[accept][a];
+      g[6] = v[accept];
+      order();
+      next(d);
+      return;
+    }
+    for (int k = 1; k < 7; ++k)
+      for (int a = 0; a < 6; ++a) cand[k - 1][a] = x[0][a] + kNmShrink * (x[k][a] - x[0][a]);
+    state = kShrink;
+    n_cand = 6;
+  }
+};
+
+bool nm_ok(const mi_nm_desc *d, int nf) {
+  if (!d || d->max_iter < 0 || d->feature_slot < 0 || d->feature_slot >= nf) return false;
+  if (!(d->ftol >= 0.0) || !(d->xtol >= 0.0)) return false;
+  for (int a = 0; a < 6; ++a)
+    if (!std::isfinite(d->step[a])) return false;
+  return true;
+}
+
+}  // namespace
+
+extern "C" size_t mi_align_nm_workspace(const mi_ref *r, int64_t n_b, int32_t n_starts) {
+  if (!r || n_b < 0 || n_starts < 1) return 0;
+  const int64_t K = 7 * (int64_t)n_starts;
+  std::vector<double> P((size_t)K * 6, 0.0);
+  for (int64_t k = 0; k < K; ++k) P[(size_t)k * 6 + 5] = 1e-3 * (double)k;  // distinct rotations
+  mi_work_item w;
+  memset(&w, 0, sizeof w);
+  w.ref = r; w.n_b = n_b; w.poses = P.data(); w.K = K;
+  const size_t b = mi_batch_workspace(&w, 1, MI_EVAL_PER_POSE, 0);
+  if (b == 0) return 0;
+  return b + al256((size_t)r->g->gi.nf * (size_t)K * sizeof(double)) + 512;
+}
+
+extern "C" mi_status mi_align_nelder_mead(const mi_ref *r, const float *xyz_b, int64_t n_b,
+                                          const double *starts, int32_t n_starts,
+                                          const mi_nm_desc *d, double pose_out[6],
+                                          double *mi_best, int32_t *iters_out, void *ws,
+                                          size_t ws_bytes, void *stream) {
+  if (!r || !starts || !pose_out || n_starts < 1)
+    return fail(MI_E_INVALID, "mi_align_nelder_mead: bad arguments");
+  const GridInfo &gi = r->g->gi;
+  if (!nm_ok(d, gi.nf)) return fail(MI_E_INVALID, "bad simplex description");
+  if (n_b > 0 && !xyz_b) return fail(MI_E_INVALID, "xyz_b is NULL");
+  for (int64_t k = 0; k < 6 * (int64_t)n_starts; ++k)
+    if (!std::isfinite(starts[k])) return fail(MI_E_INVALID, "non-finite start pose");
+  if (!ws || ((uintptr_t)ws & 255)) return fail(MI_E_WORKSPACE, "workspace NULL or not 256-aligned");
+  const int64_t Kmax = 7 * (int64_t)n_starts;
+  Carver c(ws, ws_bytes);
+  double *mi_dev = c.take<double>((size_t)gi.nf * (size_t)Kmax);
+  c.take<char>(0);
+  if (!c.fits()) return fail(MI_E_WORKSPACE, "simplex workspace too small");
+  void *plan_ws = (void *)c.cur;
+  const size_t plan_room = ws_bytes - c.used();
+  hipStream_t s = (hipStream_t)stream;
+  std::vector<Simplex> sx((size_t)n_starts);
+  for (int32_t i = 0; i < n_starts; ++i) {
+    Simplex &S = sx[(size_t)i];
+    for (int a = 0; a < 6; ++a) S.x[0][a] = starts[6 * i + a];
+    for (int k = 1; k < 7; ++k) {
+      for (int a = 0; a < 6; ++a) S.x[k][a] = S.x[0][a];
+      S.x[k][k - 1] = S.x[k][k - 1] + d->step[k - 1];
+    }
+    for (int k = 0; k < 6; ++k)
+      for (int a = 0; a < 6; ++a) S.cand[k][a] = 0.0;
+  }
+  std::vector<double> P, vals;
+  std::vector<double> host_mi;
+  for (;;) {
+    // every active simplex's awaited points, in start order, as one batch
+    P.clear();
+    for (Simplex &S : sx) {
+      if (S.state == Simplex::kDone) continue;
+      if (S.state == Simplex::kInit)
+        for (int k = 0; k < 7; ++k) P.insert(P.end(), S.x[k], S.x[k] + 6);
+      else
+        for (int k = 0; k < S.n_cand; ++k) P.insert(P.end(), S.cand[k], S.cand[k] + 6);
+    }
+    const int64_t K = (int64_t)(P.size() / 6);
+    if (K == 0) break;
+    mi_work_item w;
+    memset(&w, 0, sizeof w);
+    w.ref = r; w.xyz_b = xyz_b; w.n_b = n_b; w.poses = P.data(); w.K = K; w.mi_out = mi_dev;
+    mi_plan *p = nullptr;
+    mi_status st = create_plan(&w, 1, MI_EVAL_PER_POSE, plan_ws, plan_room, 0, stream, false, &p);
+    if (st != MI_OK) return st;
+    st = run_plan(p, s);
+    mi_plan_destroy(p);
+    if (st != MI_OK) return st;
+    host_mi.resize((size_t)K);
+    HIP_TRY(hipMemcpyAsync(host_mi.data(), mi_dev + (int64_t)d->feature_slot * K,
+                           sizeof(double) * (size_t)K, hipMemcpyDeviceToHost, s), "MI D2H");
+    HIP_TRY(hipStreamSynchronize(s), "simplex round sync");
+    vals.resize((size_t)K);
+    for (int64_t k = 0; k < K; ++k) vals[(size_t)k] = -host_mi[(size_t)k];
+    size_t off = 0;
+    for (Simplex &S : sx) {
+      if (S.state == Simplex::kDone) continue;
+      const int need = S.state == Simplex::kInit ? 7 : S.n_cand;
+      S.take(vals.data() + off, *d);
+      off += (size_t)need;
+    }
+  }
+  // the best simplex result; ties go to the earlier start
+  int32_t bi = 0;
+  for (int32_t i = 1; i < n_starts; ++i)
+    if (sx[(size_t)i].g[0] < sx[(size_t)bi].g[0]) bi = i;
+  for (int a = 0; a < 6; ++a) pose_out[a] = sx[(size_t)bi].x[0][a];
+  if (mi_best) *mi_best = -sx[(size_t)bi].g[0];
+  if (iters_out)
+    for (int32_t i = 0; i < n_starts; ++i) iters_out[i] = sx[(size_t)i].iters;
+  return MI_OK;
 }

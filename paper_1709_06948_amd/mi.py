@@ -59,6 +59,11 @@ class _WorkItem(C.Structure):
                 ("argmax_out", C.c_void_p), ("hist_out", C.c_void_p), ("stats_out", C.c_void_p)]
 
 
+class _NMDesc(C.Structure):
+    _fields_ = [("step", C.c_double * 6), ("max_iter", C.c_int32), ("ftol", C.c_double),
+                ("xtol", C.c_double), ("feature_slot", C.c_int32)]
+
+
 class _ServerDesc(C.Structure):
     _fields_ = [("arena", C.c_void_p), ("arena_bytes", C.c_size_t), ("step_bytes", C.c_size_t),
                 ("max_active", C.c_int32)]
@@ -123,6 +128,9 @@ def _load():
         "mi_autotune_workspace": ([C.POINTER(_WorkItem), i64, u32, i64], sz),
         "mi_autotune": ([C.POINTER(_WorkItem), i64, u32, i64, vp, sz, vp,
                          C.POINTER(_AutotuneReport)], st),
+        "mi_align_nm_workspace": ([vp, i64, C.c_int32], sz),
+        "mi_align_nelder_mead": ([vp, vp, i64, dp, C.c_int32, C.POINTER(_NMDesc), dp, dp,
+                                  C.POINTER(C.c_int32), vp, sz, vp], st),
         "mi_server_create": ([C.POINTER(_ServerDesc), vp, C.POINTER(vp)], st),
         "mi_server_submit": ([vp, C.POINTER(_Request), C.POINTER(i64)], st),
         "mi_server_step": ([vp, C.POINTER(C.c_int32), C.POINTER(C.c_int32)], st),
@@ -148,7 +156,8 @@ EXPORTED = ("mi_status_str", "mi_last_error", "mi_tuning_set", "mi_tuning_get",
             "mi_eval_poses_plain", "mi_plan_create", "mi_plan_execute", "mi_plan_destroy",
             "mi_batch_workspace", "mi_batch_create", "mi_batch_execute", "mi_eval_batch",
             "mi_autotune_workspace", "mi_autotune",
-            "mi_align_workspace", "mi_align_coarse_to_fine", "mi_server_create",
+            "mi_align_workspace", "mi_align_coarse_to_fine", "mi_align_nm_workspace",
+            "mi_align_nelder_mead", "mi_server_create",
             "mi_server_submit", "mi_server_step", "mi_server_poll", "mi_server_release",
             "mi_server_destroy")
 
@@ -529,6 +538,35 @@ def align_coarse_to_fine(ref: Ref, xyz_b, init, half_range, samples, levels, shr
                                         best.ctypes.data_as(C.POINTER(C.c_double)), _dptr(ws),
                                         ws.numel(), _stream(stream)), "mi_align_coarse_to_fine")
     return out, float(best[0])
+
+
+def align_nelder_mead(ref: Ref, xyz_b, starts, step, max_iter, ftol, xtol, feature_slot=0,
+                      stream=None):
+    """mi_align_nelder_mead: simplex search for Eq. 1 (Sec. III-B) from one or
+    more starts, the simplexes advancing together in batched evaluations.
+    Returns (pose[6], MI, iterations per start)."""
+    xb = _dev_points(xyz_b)
+    S = np.ascontiguousarray(np.asarray(starts, np.float64).reshape(-1, 6))
+    d = _NMDesc()
+    d.step[:] = [float(v) for v in step]
+    d.max_iter = int(max_iter)
+    d.ftol = float(ftol)
+    d.xtol = float(xtol)
+    d.feature_slot = int(feature_slot)
+    nbytes = _lib.mi_align_nm_workspace(ref._h, xb.shape[1], S.shape[0])
+    if nbytes == 0:
+        raise MIError(MI_E_INVALID, "mi_align_nm_workspace", _lib.mi_last_error().decode())
+    ws = _workspace(nbytes)
+    out = np.zeros(6, np.float64)
+    best = np.zeros(1, np.float64)
+    iters = np.zeros(S.shape[0], np.int32)
+    _check(_lib.mi_align_nelder_mead(ref._h, _dptr(xb), xb.shape[1],
+                                     S.ctypes.data_as(C.POINTER(C.c_double)), S.shape[0],
+                                     C.byref(d), out.ctypes.data_as(C.POINTER(C.c_double)),
+                                     best.ctypes.data_as(C.POINTER(C.c_double)),
+                                     iters.ctypes.data_as(C.POINTER(C.c_int32)), _dptr(ws),
+                                     ws.numel(), _stream(stream)), "mi_align_nelder_mead")
+    return out, float(best[0]), iters
 
 
 # ------------------------------------------------------------- serving

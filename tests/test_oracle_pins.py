@@ -329,3 +329,34 @@ def test_ground_truth_recovery_tiny(seed):
     err_xy = np.abs(P[k][:2] - p.eta_gt[:2])
     err_yaw = abs(P[k][5] - p.eta_gt[5])
     assert np.all(err_xy <= 0.4 + 1e-9) and err_yaw <= math.radians(2.0) + 1e-9, (P[k], p.eta_gt)
+
+
+# ----------------------------------------------------------- simplex search
+
+def _rosenbrock(x):
+    return float(np.sum(100.0 * (x[1:] - x[:-1] ** 2) ** 2 + (1.0 - x[:-1]) ** 2))
+
+
+@pytest.mark.parametrize("fn,x0,max_iter,tols", [
+    ("rosenbrock", [0.3, -0.2, 0.5, 0.1, -0.4, 0.2], 400, (1e-10, 1e-8)),
+    ("quadratic", [1.0, -2.0, 0.5, 3.0, -1.0, 0.25], 2000, (1e-12, 1e-7)),
+])
+def test_nelder_mead_matches_scipy(fn, x0, max_iter, tols):
+    """The oracle's simplex method (Sec. III-B) against scipy's Nelder-Mead
+    with the same initial simplex, coefficients and stopping rule."""
+    from scipy.optimize import minimize
+    scale = np.array([1.0, 2.0, 3.0, 0.5, 1.5, 4.0])
+    f = _rosenbrock if fn == "rosenbrock" else (lambda x: float(np.sum(scale * (x - 0.3) ** 2)))
+    x0 = np.array(x0)
+    steps = np.array([0.5, 0.4, 0.3, 0.2, 0.25, 0.35])
+    sim = np.array([x0] + [x0 + np.eye(6)[i] * steps[i] for i in range(6)])
+    # scipy counts one more iteration than it completes and stops one short of
+    # maxiter: its maxiter + 1 / nit - 1 is this method's max_iter / iterations
+    r = minimize(f, x0, method="Nelder-Mead",
+                 options=dict(initial_simplex=sim, maxiter=max_iter + 1, fatol=tols[0],
+                              xatol=tols[1], adaptive=False))
+    x, v, it = O.nelder_mead(lambda pts: [f(p) for p in pts], x0, steps, max_iter, tols[0],
+                             tols[1])
+    assert it == r.nit - 1
+    assert np.max(np.abs(x - r.x)) <= 1e-9
+    assert abs(v - r.fun) <= 1e-12 * max(1.0, abs(r.fun))
