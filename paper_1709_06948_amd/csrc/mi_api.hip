@@ -940,10 +940,10 @@ mi_status create_plan(const mi_work_item *w, int64_t n, uint32_t flags, void *ws
                       size_t budget, void *stream, bool bind_per_execution, mi_plan **out) {
   if (!out) return fail(MI_E_INVALID, "NULL output handle");
   *out = nullptr;
-  if (!ws || ((uintptr_t)ws & 255)) return fail(MI_E_WORKSPACE, "workspace NULL or not 256-aligned");
   BatchTables B;
-  mi_status st = prepare_batch(w, n, flags, B);
+  mi_status st = prepare_batch(w, n, flags, B);  // argument errors before workspace errors
   if (st != MI_OK) return st;
+  if (!ws || ((uintptr_t)ws & 255)) return fail(MI_E_WORKSPACE, "workspace NULL or not 256-aligned");
   Carver c(ws, ws_bytes);
   PlanLayout PL;
   plan_fixed(B, n, c, &PL);

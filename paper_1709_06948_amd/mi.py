@@ -369,10 +369,9 @@ def eval_poses(ref: Ref, xyz_b, poses, flags=0, want_hist=False, want_stats=Fals
     K = P.shape[0]
     pp = P.ctypes.data_as(C.POINTER(C.c_double))
     nbytes = _lib.mi_eval_poses_workspace(ref._h, xb.shape[1], pp, K, flags, frame_budget)
-    if nbytes == 0:
-        raise MIError(MI_E_INVALID, "mi_eval_poses_workspace", "bad arguments")
-    ws = _workspace(nbytes)
     mi, am, hist, stats = _outputs(ref.grid, K, want_hist, want_stats, want_argmax)
+    # a rejected pose set sizes to 0; the call itself then reports why
+    ws = _workspace(nbytes)
     _check(_lib.mi_eval_poses(ref._h, _dptr(xb), xb.shape[1], pp, K, flags, _dptr(mi), _dptr(am),
                               _dptr(hist), _dptr(stats), _dptr(ws), ws.numel(), _stream(stream)),
            "mi_eval_poses")
@@ -410,8 +409,7 @@ class Plan:
         self.n_b = int(n_b)
         pp = P.ctypes.data_as(C.POINTER(C.c_double))
         nbytes = _lib.mi_eval_poses_workspace(ref._h, self.n_b, pp, self.K, flags, frame_budget)
-        if nbytes == 0:
-            raise MIError(MI_E_INVALID, "mi_eval_poses_workspace", "bad arguments")
+        # a rejected pose set sizes to 0; mi_plan_create then reports why
         self.ws = _workspace(nbytes)
         h = C.c_void_p()
         _check(_lib.mi_plan_create(ref._h, self.n_b, pp, self.K, flags, _dptr(self.ws),
