@@ -18,6 +18,13 @@ Other workloads (same JSON line, their own config):
   uneven   N surface-sampled pairs (points log-uniform in 10k-300k, voxels
            0.25 / 0.5 / 1 m, count + z-variance at 32 bins) with 4096 random
            poses each, all in one batch per step;
+  accuracy the accuracy protocol of the paper's experiments on synthetic
+           stand-ins: a reference scan and query scans from 1-10 m away (and
+           from 2-20 deg of heading), 1 m voxels, each aligned from the identity
+           by the simplex search with the paper's initial simplex, for both
+           features; reports alignments/s and error / success per level;
+  surface  the cost surfaces of the paper's Fig. 6: MI over a (tx, ty) grid
+           and over heading around the true pose, both features;
   serving  alignment requests (surface-sampled pairs, 20k-250k points, 0.5 or
            1 m voxels, 3 levels x 4^6 poses) arriving as Poisson processes at
            the given rates, served by the continuous-batching loop; reports
@@ -61,7 +68,9 @@ def _args():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--plain-sample", type=int, default=96)
     ap.add_argument("--cpu-sample", type=int, default=2048)
-    ap.add_argument("--workload", choices=("c2f", "batched", "uneven", "serving"), default="c2f")
+    ap.add_argument("--workload", choices=("c2f", "batched", "uneven", "serving", "accuracy",
+                                           "surface"), default="c2f")
+    ap.add_argument("--seeds", type=int, default=3)
     ap.add_argument("--pairs", type=int, default=64)
     ap.add_argument("--rates", default="50,200,800")
     ap.add_argument("--requests", type=int, default=150)
@@ -121,6 +130,10 @@ def main():
         return
     if a.workload == "serving":
         return _bench_serving(a)
+    if a.workload == "accuracy":
+        return _bench_accuracy(a)
+    if a.workload == "surface":
+        return _bench_surface(a)
     if a.workload != "c2f":
         return _bench_batch(a)
     import torch
@@ -306,6 +319,166 @@ def _bench_batch(a):
                      "kernel": "k_eval", "avg_launch_ms": eval_ms_avg,
                      "eval_launches_per_step": prof["eval_launches"],
                      "frames_ms_per_step": prof["frames_ms"], "eval_ms_per_step": prof["eval_ms"]},
+        "cpu_baseline": None,
+    }
+    print(json.dumps(out), flush=True)
+
+
+# Initial simplex of the paper's experiments (m, m, m, rad, rad, rad).
+NM_STEP = [8.0, 8.0, 1.0, 0.1, 0.1, 0.8]
+# Success: final error under one voxel (1 m) in translation and 2 deg in rotation.
+SUCCESS_M, SUCCESS_DEG = 1.0, 2.0
+
+
+def _bench_accuracy(a):
+    """Accuracy protocol of Sec. IV (Figs. 4, 5) on synthetic displaced scans:
+    every query aligned from the identity by mi_align_nelder_mead (one start,
+    the paper's simplex), and again with four starts advancing together."""
+    import math
+
+    import torch
+
+    from paper_1709_06948_amd import mi, synth
+
+    torch.cuda.set_device(0)
+    d2r = math.pi / 180.0
+    starts4 = np.array([[0, 0, 0, 0, 0, 0], [4, 4, 0, 0, 0, 0.3], [-4, 4, 0, 0, 0, -0.3],
+                        [0, -5, 0, 0, 0, 0]], np.float64)
+    methods = [("nm", np.zeros((1, 6))), ("nm_4starts", starts4)]
+    res = {}
+    n_align, t_align, iters = 0, 0.0, []
+    for study, cfg in (("translation", 6), ("rotation", 7)):
+        for sd in range(a.seeds):
+            D = synth.displaced_scans(seed=synth.seed_for(cfg, sd), study=study)
+            grid = mi.Grid(D.origin, D.dims, D.voxel, features=mi.FEAT_COUNT | mi.FEAT_ZVAR,
+                           nb_count=32, nb_zvar=32)
+            ref = mi.Ref(grid, D.A)
+            for i, (B, g) in enumerate(zip(D.B, D.eta_gt)):
+                Bd = torch.from_numpy(B).cuda()
+                for mname, starts in methods:
+                    for slot, fname in ((0, "mi_n"), (1, "mi_varz")):
+                        torch.cuda.synchronize()
+                        t0 = time.perf_counter()
+                        pose, _, it = mi.align_nelder_mead(ref, Bd, starts, NM_STEP, 400, 1e-7,
+                                                           1e-3, feature_slot=slot)
+                        torch.cuda.synchronize()
+                        t_align += time.perf_counter() - t0
+                        n_align += 1
+                        iters += [int(x) for x in it]
+                        et = float(np.linalg.norm(pose[:3] - g[:3]))
+                        er = float(np.linalg.norm(pose[3:] - g[3:]) / d2r)
+                        key = (study, mname, fname, float(D.levels[i]))
+                        res.setdefault(key, []).append((et, er))
+    summary = {}
+    for (study, mname, fname, lv), v in sorted(res.items()):
+        e = np.array(v)
+        ok = (e[:, 0] < SUCCESS_M) & (e[:, 1] < SUCCESS_DEG)
+        summary.setdefault(study, {}).setdefault(mname, {}).setdefault(fname, {})[f"{lv:g}"] = {
+            "median_t_err_m": round(float(np.median(e[:, 0])), 3),
+            "median_r_err_deg": round(float(np.median(e[:, 1])), 3),
+            "success": round(float(ok.mean()), 3)}
+    overall = {}
+    for (study, mname, fname, lv), v in res.items():
+        e = np.array(v)
+        ok = (e[:, 0] < SUCCESS_M) & (e[:, 1] < SUCCESS_DEG)
+        overall.setdefault(f"{study}/{mname}/{fname}", []).extend(ok.tolist())
+    out = {
+        "metric": "NM alignments/s", "value": n_align / t_align, "unit": "alignments/s",
+        "n_gpus": 1, "steps": 1, "warmup": 0, "ms_per_step": t_align * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": (f"accuracy protocol: {a.seeds} seeded urban scenes per study, "
+                                "reference scan at the origin, 10 query scans each at 1-10 m "
+                                "(translation study) or 2-20 deg heading (rotation study), 64-ring "
+                                "scans at 0.4 deg azimuth (~57k points), 1 m voxels 160x160x10, "
+                                "count + z-variance 32 bins, simplex search from the identity "
+                                f"with initial simplex {NM_STEP}, max 400 iterations"),
+                   "alignments": n_align},
+        "mean_nm_iterations": float(np.mean(iters)),
+        "success_rule": f"translation error < {SUCCESS_M} m and rotation error < {SUCCESS_DEG} deg",
+        "success_rate": {k: round(float(np.mean(v)), 3) for k, v in sorted(overall.items())},
+        "accuracy": summary,
+        "cpu_baseline": None,
+    }
+    print(json.dumps(out), flush=True)
+
+
+def _local_maxima_2d(S):
+    """Interior nodes strictly above all 8 neighbours."""
+    c = S[1:-1, 1:-1]
+    m = np.ones_like(c, dtype=bool)
+    for dx in (-1, 0, 1):
+        for dy in (-1, 0, 1):
+            if dx or dy:
+                m &= c > S[1 + dx:S.shape[0] - 1 + dx, 1 + dy:S.shape[1] - 1 + dy]
+    return int(m.sum())
+
+
+def _bench_surface(a):
+    """Cost surfaces of Fig. 6 around the true pose of a displaced query scan
+    (6 m away): MI over a +-10 m (tx, ty) grid at 0.25 m and over +-30 deg of
+    heading at 0.25 deg, every other parameter at the truth, both features."""
+    import math
+
+    import torch
+
+    from paper_1709_06948_amd import mi, synth
+
+    torch.cuda.set_device(0)
+    d2r = math.pi / 180.0
+    D = synth.displaced_scans(seed=synth.seed_for(8), study="translation", levels=[6.0])
+    g = D.eta_gt[0]
+    grid = mi.Grid(D.origin, D.dims, D.voxel, features=mi.FEAT_COUNT | mi.FEAT_ZVAR,
+                   nb_count=32, nb_zvar=32)
+    ref = mi.Ref(grid, D.A)
+    B = torch.from_numpy(D.B[0]).cuda()
+    P, xs, ys, Y, yaws = synth.surface_poses(g)
+    Pall = np.concatenate([P, Y])
+    plan = mi.Plan(ref, B.shape[1], Pall)
+    o = torch.empty((2, len(Pall)), dtype=torch.float64, device="cuda")
+    for _ in range(max(a.warmup, 1)):
+        plan.execute(B, o)
+    torch.cuda.synchronize()
+    mi.profile_enable(True)
+    t0 = time.perf_counter()
+    for _ in range(a.steps):
+        plan.execute(B, o)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    prof = mi.profile_read()
+    mi.profile_enable(False)
+    M = o.cpu().numpy()
+    n = len(xs)
+    feats = {}
+    for f, fname in ((0, "mi_n"), (1, "mi_varz")):
+        S = M[f, :n * n].reshape(n, n)
+        h = M[f, n * n:]
+        i, j = np.unravel_index(int(np.argmax(S)), S.shape)
+        feats[fname] = {
+            "xy_argmax_err_m": round(float(math.hypot(xs[i] - g[0], ys[j] - g[1])), 3),
+            "xy_local_maxima": _local_maxima_2d(S),
+            "heading_argmax_err_deg": round(float(abs(yaws[int(np.argmax(h))] - g[5]) / d2r), 3),
+            "heading_local_maxima": int(((h[1:-1] > h[:-2]) & (h[1:-1] > h[2:])).sum()),
+            "mi_max": float(S.max())}
+    K = len(Pall)
+    eval_ms_avg = prof["eval_ms"] / max(prof["eval_launches"], 1)
+    pp_per_launch = prof["point_poses"] / max(prof["eval_launches"], 1)
+    achieved = OPS_PER_POINT_POSE * pp_per_launch / (eval_ms_avg * 1e-3)
+    out = {
+        "metric": "MI pose evals/s", "value": K * a.steps / dt, "unit": "evals/s", "n_gpus": 1,
+        "steps": a.steps, "warmup": a.warmup, "ms_per_step": dt * 1e3 / a.steps,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": ("cost surfaces: query scan 6 m from the reference (~57k points "
+                                "each), 1 m voxels 160x160x10, count + z-variance 32 bins; "
+                                f"{n}x{n} (tx, ty) nodes over +-10 m and {len(yaws)} headings over "
+                                "+-30 deg around the true pose, one batch per step"),
+                   "evals_per_step": K},
+        "gpoint_transforms_per_s": K * B.shape[1] * a.steps / dt / 1e9,
+        "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP64_OPS / 1e12,
+                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_OPS, "traffic": None,
+                     "kernel": "k_eval", "avg_launch_ms": eval_ms_avg},
+        "surfaces": feats,
         "cpu_baseline": None,
     }
     print(json.dumps(out), flush=True)

@@ -702,21 +702,37 @@ namespace {
 
 size_t al256(size_t x) { return (x + 255) & ~(size_t)255; }
 
-// Items [i0, i1) regrouped by XCD: frame f goes to XCD f % kXcds, so every
-// XCD gets an even share of every pair's frames (and a frame's poses stay on
-// one XCD, whose L2 then holds it); within an XCD the items keep their order.
-// out[x] .. out[x + 1] (relative to i0) is XCD x's run.
+// Items [i0, i1) regrouped by XCD.  The frame-sorted items are cut into
+// pieces, a piece being a frame's items or, for a frame with many poses, at
+// most a 32nd of the range of them; pieces go round-robin to the XCDs.  So
+// every XCD gets an even share of every pair's frames, a frame's poses stay on
+// one XCD (whose L2 then holds it) unless it has many, and a pose set with few
+// distinct rotations (a translation grid) still spreads over all XCDs.  Within
+// an XCD the items keep their order.  out[x] .. out[x + 1] (relative to i0) is
+// XCD x's run.
 void group_by_xcd(std::vector<PoseDev> &items, int64_t i0, int64_t i1,
                   std::array<int64_t, kXcds + 1> &out) {
+  const int64_t cap = std::max<int64_t>(1, (i1 - i0 + 4 * kXcds - 1) / (4 * kXcds));
+  std::vector<int8_t> xcd((size_t)std::max<int64_t>(i1 - i0, 0));
   std::array<int64_t, kXcds + 1> cnt;
   cnt.fill(0);
-  for (int64_t k = i0; k < i1; ++k) ++cnt[(size_t)(items[(size_t)k].frame % kXcds) + 1];
+  int64_t piece = -1, in_piece = 0;
+  for (int64_t k = i0; k < i1; ++k) {
+    if (k == i0 || items[(size_t)k].frame != items[(size_t)k - 1].frame || in_piece == cap) {
+      ++piece;
+      in_piece = 0;
+    }
+    ++in_piece;
+    const int x = (int)(piece % kXcds);
+    xcd[(size_t)(k - i0)] = (int8_t)x;
+    ++cnt[(size_t)x + 1];
+  }
   out[0] = 0;
   for (int x = 0; x < kXcds; ++x) out[(size_t)x + 1] = out[(size_t)x] + cnt[(size_t)x + 1];
   std::array<int64_t, kXcds> pos;
   for (int x = 0; x < kXcds; ++x) pos[(size_t)x] = out[(size_t)x];
   std::vector<PoseDev> tmp(items.begin() + i0, items.begin() + i1);
-  for (const PoseDev &it : tmp) items[(size_t)(i0 + pos[(size_t)(it.frame % kXcds)]++)] = it;
+  for (size_t j = 0; j < tmp.size(); ++j) items[(size_t)(i0 + pos[(size_t)xcd[j]]++)] = tmp[j];
 }
 
 // Device bytes of one frame inside a chunk's storage: rotated points, column

@@ -327,6 +327,81 @@ def urban_pair(seed=None, max_offset=5.0, max_yaw_deg=15.0) -> Pair:
     return Pair(as_soa32(A), as_soa32(B), eta, (-80.0, -80.0, -1.0), (320, 320, 20), 0.5)
 
 
+@dataclass
+class DisplacedSet:
+    """One reference scan A and query scans B of the same scene taken from
+    other poses: B[i] is expressed in its own frame and eta_gt[i] maps it
+    into A's frame."""
+    A: np.ndarray                      # float32 [3, nA]
+    B: list                            # float32 [3, nB_i] each
+    eta_gt: np.ndarray                 # float64 [n, 6]
+    origin: tuple
+    dims: tuple
+    voxel: float
+    study: str                         # "translation" or "rotation"
+    levels: np.ndarray                 # the initial-error level of each query (m or deg)
+
+
+def displaced_scans(seed=None, study="translation", levels=None, az_step=0.4) -> DisplacedSet:
+    """Stand-in for the accuracy protocol of Sec. IV (Figs. 4, 5): a reference
+    scan A at the origin of a ray-cast urban scene and query scans B from poses
+    whose offset from A is the initial error the alignment starts with (it
+    starts from the identity).
+
+    study "translation": B at distance d in levels (default 1..10 m) along a
+    seeded heading, with yaw U[-2, 2] deg, roll/pitch U[-1, 1] deg, tz U[-0.1, 0.1] m.
+    study "rotation": yaw offsets of levels (default 2..20 deg in steps of 2,
+    seeded sign) with a translation below 5 m (distance U[0, 5] m).
+    Scans: 64 rings over -24.8..+2 deg, az_step deg azimuth, range <= 80 m.
+    Grid: origin (-80,-80,-1), 160x160x10 voxels of 1 m, the resolution of the
+    paper's experiments."""
+    rng = np.random.default_rng(seed_for(6) if seed is None else seed)
+    d2r = math.pi / 180.0
+    if study == "translation":
+        lv = np.arange(1.0, 11.0) if levels is None else np.asarray(levels, np.float64)
+        etas = []
+        for d in lv:
+            ang = rng.uniform(0, 2 * math.pi)
+            etas.append([d * math.cos(ang), d * math.sin(ang), rng.uniform(-0.1, 0.1),
+                         rng.uniform(-1, 1) * d2r, rng.uniform(-1, 1) * d2r,
+                         rng.uniform(-2, 2) * d2r])
+    elif study == "rotation":
+        lv = np.arange(2.0, 22.0, 2.0) if levels is None else np.asarray(levels, np.float64)
+        etas = []
+        for a in lv:
+            d, ang = rng.uniform(0, 5.0), rng.uniform(0, 2 * math.pi)
+            sign = 1.0 if rng.uniform() < 0.5 else -1.0
+            etas.append([d * math.cos(ang), d * math.sin(ang), rng.uniform(-0.1, 0.1),
+                         rng.uniform(-1, 1) * d2r, rng.uniform(-1, 1) * d2r, sign * a * d2r])
+    else:
+        raise ValueError("study must be 'translation' or 'rotation'")
+    etas = np.array(etas, np.float64)
+    scene = urban_scene(rng, keep_clear=((0.0, 0.0),) + tuple((e[0], e[1]) for e in etas))
+    A = raycast_scan(scene, np.zeros(6), rng, az_step=az_step)
+    B = [as_soa32(raycast_scan(scene, e, rng, az_step=az_step)) for e in etas]
+    return DisplacedSet(as_soa32(A), B, etas, (-80.0, -80.0, -1.0), (160, 160, 10), 1.0, study, lv)
+
+
+def surface_poses(center, half_xy=10.0, step_xy=0.25, half_yaw_deg=30.0, step_yaw_deg=0.25):
+    """Pose sets of the cost-surface plots of Fig. 6: a (tx, ty) grid of
+    +-half_xy m around center with every other parameter at center (row-major,
+    ty fastest), and a heading sweep of +-half_yaw_deg around center's yaw.
+    Returns (xy poses [nx*ny, 6], the x and y node values, yaw poses [n, 6],
+    yaw node values in rad)."""
+    c = np.asarray(center, np.float64)
+    n = int(round(2 * half_xy / step_xy)) + 1
+    xs = c[0] + np.linspace(-half_xy, half_xy, n)
+    ys = c[1] + np.linspace(-half_xy, half_xy, n)
+    P = np.repeat(c.reshape(1, 6), n * n, axis=0)
+    P[:, 0] = np.repeat(xs, n)
+    P[:, 1] = np.tile(ys, n)
+    m = int(round(2 * half_yaw_deg / step_yaw_deg)) + 1
+    yaws = c[5] + np.deg2rad(np.linspace(-half_yaw_deg, half_yaw_deg, m))
+    Y = np.repeat(c.reshape(1, 6), m, axis=0)
+    Y[:, 5] = yaws
+    return P, xs, ys, Y, yaws
+
+
 def level_poses(center, half, samples) -> np.ndarray:
     """A pose grid around center (per axis samples[a] values spanning
     +-half[a]), row-major with the last axis fastest -- used to draw sample
