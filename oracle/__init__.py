@@ -22,6 +22,7 @@ _LIB_PATH = os.path.join(_HERE, "liboracle.so")
 
 FEAT_COUNT = 1
 FEAT_ZVAR = 2
+FEAT_JOINT = 4
 NSTATS = 11
 STATS_FIELDS = ("lo_x", "lo_y", "lo_z", "hi_x", "hi_y", "hi_z", "n_overlap", "n_in_grid",
                 "n_out_of_grid", "n_nonfinite", "n_near_face")
@@ -75,7 +76,8 @@ def _L():
         lib.mio_grid_poses.argtypes = [dp, dp, i32p, dp]
         lib.mio_grid_poses.restype = C.c_int64
         lib.mio_align_c2f.argtypes = [gp, fp, C.c_int64, fp, C.c_int64, dp, dp, i32p, C.c_int32,
-                                      C.c_double, C.c_int32, dp, dp, C.c_int32]
+                                      C.c_double, C.c_int32, dp, dp, dp, C.c_int32]
+        lib.mio_weighted.argtypes = [dp, C.c_int64, C.c_int32, dp, dp]
         lib.mio_align_c2f.restype = C.c_int
         _lib = lib
     return _lib
@@ -88,7 +90,9 @@ def _ptr(a, ct):
 class Grid:
     """Voxel grid R_v over scan A's frame plus the feature description
     (Sec. III-A; Sec. IV uses R_v = 1 m).  Features: bitmask of FEAT_COUNT
-    (number of points, MI-N) and FEAT_ZVAR (variance of z, MI-VARZ)."""
+    (number of points, MI-N), FEAT_ZVAR (variance of z, MI-VARZ) and
+    FEAT_JOINT (the pair of the two bins as one value), at most two of them;
+    the joint feature bins its parts with nb_count and nb_zvar."""
 
     def __init__(self, origin, dims, voxel, features=FEAT_COUNT, nb_count=16, nb_zvar=32,
                  count_edges=None, zvar_edges=None):
@@ -105,7 +109,7 @@ class Grid:
                 raise ValueError("bad nb_count")
         if zvar_edges is None:
             zvar_edges = np.zeros(max(self.nb_zvar - 2, 1), np.uint64)
-            if (self.features & FEAT_ZVAR) and \
+            if (self.features & (FEAT_ZVAR | FEAT_JOINT)) and self.nb_zvar >= 3 and \
                     L.mio_default_zvar_edges(self.voxel, self.nb_zvar, _ptr(zvar_edges, C.c_uint64)):
                 raise ValueError("bad nb_zvar / voxel for default z-variance edges")
         self.count_edges = np.ascontiguousarray(count_edges, np.uint32)
@@ -132,6 +136,8 @@ class Grid:
             out.append((FEAT_COUNT, self.nb_count))
         if self.features & FEAT_ZVAR:
             out.append((FEAT_ZVAR, self.nb_zvar))
+        if self.features & FEAT_JOINT:
+            out.append((FEAT_JOINT, 1 + (self.nb_count - 1) * (self.nb_zvar - 1)))
         return out
 
 
@@ -223,6 +229,17 @@ def argmax(mi) -> int:
     return int(_L().mio_argmax(_ptr(m, C.c_double), m.shape[0]))
 
 
+def weighted(mi, weights) -> np.ndarray:
+    """Weighted objective w0 * MI_0 + w1 * MI_1 of every pose (products rounded,
+    then the sum), for mi [nfeat][K]."""
+    m = np.ascontiguousarray(mi, np.float64)
+    w = np.ascontiguousarray(weights, np.float64).reshape(2)
+    out = np.zeros(m.shape[1], np.float64)
+    _L().mio_weighted(_ptr(m, C.c_double), m.shape[1], m.shape[0], _ptr(w, C.c_double),
+                      _ptr(out, C.c_double))
+    return out
+
+
 def grid_poses(center, half, samples) -> np.ndarray:
     """Pose grid of one coarse-to-fine level (row-major, yaw fastest)."""
     c = np.ascontiguousarray(center, np.float64)
@@ -235,9 +252,11 @@ def grid_poses(center, half, samples) -> np.ndarray:
     return P
 
 
-def align_c2f(grid: Grid, A, B, init, half, samples, levels, shrink, feature_slot=0, nthreads=0):
+def align_c2f(grid: Grid, A, B, init, half, samples, levels, shrink, feature_slot=0, nthreads=0,
+              weights=None):
     """Coarse-to-fine grid maximisation of Eq. 1 (stand-in for the Sec. III-B
-    search).  Returns (pose[6], MI at that pose)."""
+    search) for feature slot feature_slot, or of the weighted objective when
+    weights (w0, w1) are given.  Returns (pose[6], objective at that pose)."""
     A = _soa(A)
     B = _soa(B)
     i0 = np.ascontiguousarray(init, np.float64)
@@ -245,9 +264,12 @@ def align_c2f(grid: Grid, A, B, init, half, samples, levels, shrink, feature_slo
     s = np.ascontiguousarray(samples, np.int32)
     out = np.zeros(6, np.float64)
     best = np.zeros(1, np.float64)
+    w = None if weights is None else np.ascontiguousarray(weights, np.float64).reshape(2)
+    slot = -1 if w is not None else int(feature_slot)
     rc = _L().mio_align_c2f(C.byref(grid._g), _ptr(A, C.c_float), A.shape[1], _ptr(B, C.c_float),
                             B.shape[1], _ptr(i0, C.c_double), _ptr(h0, C.c_double),
-                            _ptr(s, C.c_int32), int(levels), float(shrink), int(feature_slot),
+                            _ptr(s, C.c_int32), int(levels), float(shrink), slot,
+                            None if w is None else _ptr(w, C.c_double),
                             _ptr(out, C.c_double), _ptr(best, C.c_double), int(nthreads))
     if rc:
         raise RuntimeError(f"mio_align_c2f failed ({rc})")
@@ -326,12 +348,14 @@ def nelder_mead(f, x0, steps, max_iter, ftol, xtol):
 
 
 def align_nelder_mead(grid: Grid, A, B, init, steps, max_iter, ftol, xtol, feature_slot=0,
-                      nthreads=0):
+                      nthreads=0, weights=None):
     """Alg. 1 with the Nelder-Mead update of Sec. III-B: maximise Eq. 1 (MI of
-    feature slot `feature_slot`) over the pose from T_o = init.  Returns
-    (pose[6], MI, iterations)."""
+    feature slot `feature_slot`, or the weighted objective when weights are
+    given) over the pose from T_o = init.  Returns (pose[6], objective,
+    iterations)."""
     def cost(points):
         mi, _, _ = eval_poses(grid, A, B, np.asarray(points), nthreads=nthreads)
-        return [-float(v) for v in mi[feature_slot]]
+        obj = mi[feature_slot] if weights is None else weighted(mi, weights)
+        return [-float(v) for v in obj]
     x, v, it = nelder_mead(cost, init, steps, max_iter, ftol, xtol)
     return x, -v, it

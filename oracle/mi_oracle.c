@@ -29,7 +29,13 @@
  *    upper bounds; an empty overlap gives MI = 0;
  *  - entropies use the natural log, 0 ln 0 = 0, and the marginals are the row
  *    and column sums of the joint histogram over the overlap box;
- *  - argmax picks the smallest index within 1e-12 of the maximum.
+ *  - argmax picks the smallest index within 1e-12 of the maximum;
+ *  - the joint feature (an extension in the direction the conclusion points,
+ *    richer per-voxel features) is the pair (count bin, z-variance bin) of an
+ *    occupied voxel as one value, 1 + (count bin - 1) * (nb_zvar - 1) +
+ *    (z-variance bin - 1); the empty voxel keeps value 0;
+ *  - a weighted search maximises w0 * MI_0 + w1 * MI_1 over the feature slots,
+ *    each product rounded, then the sum.
  */
 #include <math.h>
 #include <stdint.h>
@@ -43,6 +49,7 @@ typedef unsigned __int128 u128;
 
 #define MIO_FEAT_COUNT 1u
 #define MIO_FEAT_ZVAR 2u
+#define MIO_FEAT_JOINT 4u
 
 /* Grid and feature description, as the oracle's caller passes it. */
 typedef struct {
@@ -52,7 +59,7 @@ typedef struct {
   uint32_t features;      /* bitmask of MIO_FEAT_* */
   int32_t nb_count;       /* bins of the point-count feature */
   const uint32_t *count_edges; /* nb_count-1 ascending lower edges */
-  int32_t nb_zvar;        /* bins of the z-variance feature */
+  int32_t nb_zvar;        /* bins of the z-variance feature (and the joint one's z part) */
   const uint64_t *zvar_edges;  /* nb_zvar-2 ascending edges, units (voxel/2^20)^2 */
 } mio_grid;
 
@@ -201,23 +208,44 @@ static void voxelize(const mio_grid *g, const float *xyz, int64_t n, const doubl
   }
 }
 
+static const uint32_t kFeatureOrder[3] = {MIO_FEAT_COUNT, MIO_FEAT_ZVAR, MIO_FEAT_JOINT};
+
 static int n_features(const mio_grid *g) {
-  return ((g->features & MIO_FEAT_COUNT) ? 1 : 0) + ((g->features & MIO_FEAT_ZVAR) ? 1 : 0);
+  int n = 0;
+  for (int i = 0; i < 3; ++i)
+    if (g->features & kFeatureOrder[i]) ++n;
+  return n;
 }
 
-/* feature slot f -> (kind, nb) in the fixed order count, z-variance */
+/* feature slot f -> kind, in the fixed order count, z-variance, joint */
 static uint32_t feature_kind(const mio_grid *g, int f) {
-  if (g->features & MIO_FEAT_COUNT) return f == 0 ? MIO_FEAT_COUNT : MIO_FEAT_ZVAR;
-  return MIO_FEAT_ZVAR;
+  int k = 0;
+  for (int i = 0; i < 3; ++i) {
+    if (!(g->features & kFeatureOrder[i])) continue;
+    if (k == f) return kFeatureOrder[i];
+    ++k;
+  }
+  return 0;
 }
+
+/* values of the joint feature: the empty voxel, then every pair of an
+ * occupied count bin (1 .. nb_count-1) and z-variance bin (1 .. nb_zvar-1) */
+static int joint_nb(const mio_grid *g) { return 1 + (g->nb_count - 1) * (g->nb_zvar - 1); }
 
 static int feature_nb(const mio_grid *g, int f) {
-  return feature_kind(g, f) == MIO_FEAT_COUNT ? g->nb_count : g->nb_zvar;
+  const uint32_t kind = feature_kind(g, f);
+  if (kind == MIO_FEAT_COUNT) return g->nb_count;
+  if (kind == MIO_FEAT_ZVAR) return g->nb_zvar;
+  return joint_nb(g);
 }
 
 static int voxel_bin(const mio_grid *g, uint32_t kind, uint32_t n, uint64_t s1, uint64_t s2) {
   if (kind == MIO_FEAT_COUNT) return bin_count(n, g->nb_count, g->count_edges);
-  return bin_zvar(n, s1, s2, g->nb_zvar, g->zvar_edges);
+  if (kind == MIO_FEAT_ZVAR) return bin_zvar(n, s1, s2, g->nb_zvar, g->zvar_edges);
+  if (n == 0) return 0;
+  const int bc = bin_count(n, g->nb_count, g->count_edges);
+  const int bz = bin_zvar(n, s1, s2, g->nb_zvar, g->zvar_edges);
+  return 1 + (bc - 1) * (g->nb_zvar - 1) + (bz - 1);
 }
 
 /* --------------------------------------------------------------- entropy */
@@ -283,10 +311,15 @@ static int grid_ok(const mio_grid *g) {
   const int64_t V = (int64_t)g->dims[0] * g->dims[1] * g->dims[2];
   if (V > 2147483647LL) return 0;
   if (!(g->voxel > 0.0) || !isfinite(g->voxel)) return 0;
-  if (g->features == 0 || (g->features & ~(MIO_FEAT_COUNT | MIO_FEAT_ZVAR))) return 0;
-  if ((g->features & MIO_FEAT_COUNT) && (g->nb_count < 2 || g->nb_count > 64 || !g->count_edges))
+  const uint32_t all = MIO_FEAT_COUNT | MIO_FEAT_ZVAR | MIO_FEAT_JOINT;
+  if (g->features == 0 || (g->features & ~all) || n_features(g) > 2) return 0;
+  if ((g->features & (MIO_FEAT_COUNT | MIO_FEAT_JOINT)) &&
+      (g->nb_count < 2 || g->nb_count > 64 || !g->count_edges))
     return 0;
   if ((g->features & MIO_FEAT_ZVAR) && (g->nb_zvar < 3 || g->nb_zvar > 64 || !g->zvar_edges))
+    return 0;
+  if ((g->features & MIO_FEAT_JOINT) &&
+      (g->nb_zvar < 2 || g->nb_zvar > 64 || (g->nb_zvar > 2 && !g->zvar_edges) || joint_nb(g) > 64))
     return 0;
   return 1;
 }
@@ -501,31 +534,43 @@ int64_t mio_grid_poses(const double center[6], const double half[6], const int32
   return K;
 }
 
+/* Weighted objective of every pose: w[0] * MI_0 + w[1] * MI_1 (slots present). */
+void mio_weighted(const double *mi, int64_t K, int32_t nf, const double w[2], double *out) {
+  for (int64_t k = 0; k < K; ++k) {
+    double v = w[0] * mi[k];
+    if (nf > 1) v = v + w[1] * mi[K + k];
+    out[k] = v;
+  }
+}
+
 /* Search for the argmax of Eq. 1 by a grid that is re-centred on the best pose
  * and shrunk at every level (the exhaustive-grid stand-in for the simplex
- * search of Sec. III-B).  feature_slot picks which feature's MI drives it. */
+ * search of Sec. III-B).  feature_slot picks which feature's MI drives it; -1
+ * drives it by the weighted objective of `weights`. */
 int mio_align_c2f(const mio_grid *g, const float *A, int64_t na, const float *B, int64_t nbp,
                   const double init[6], const double half0[6], const int32_t samples[6],
-                  int32_t levels, double shrink, int32_t feature_slot, double pose_out[6],
-                  double *mi_best, int32_t nthreads) {
+                  int32_t levels, double shrink, int32_t feature_slot, const double *weights,
+                  double pose_out[6], double *mi_best, int32_t nthreads) {
   if (!grid_ok(g) || levels < 1 || !(shrink > 0.0)) return -1;
   const int nf = n_features(g);
-  if (feature_slot < 0 || feature_slot >= nf) return -1;
+  if (feature_slot < -1 || feature_slot >= nf || (feature_slot == -1 && !weights)) return -1;
   double c[6], h[6];
   for (int a = 0; a < 6; ++a) { c[a] = init[a]; h[a] = half0[a]; }
   const int64_t K = mio_grid_poses(c, h, samples, NULL);
   if (K < 1) return -1;
   double *poses = (double *)malloc(sizeof(double) * 6 * (size_t)K);
-  double *mi = (double *)malloc(sizeof(double) * (size_t)nf * (size_t)K);
+  double *mi = (double *)malloc(sizeof(double) * ((size_t)nf + 1) * (size_t)K);
   if (!poses || !mi) { free(poses); free(mi); return -2; }
+  double *obj = feature_slot >= 0 ? mi + (int64_t)feature_slot * K : mi + (int64_t)nf * K;
   double best = 0.0;
   for (int32_t l = 0; l < levels; ++l) {
     mio_grid_poses(c, h, samples, poses);
     int rc = mio_eval_poses(g, A, na, B, nbp, poses, K, mi, NULL, NULL, nthreads);
     if (rc) { free(poses); free(mi); return rc; }
-    const int64_t k = mio_argmax(mi + (int64_t)feature_slot * K, K);
+    if (feature_slot < 0) mio_weighted(mi, K, nf, weights, obj);
+    const int64_t k = mio_argmax(obj, K);
     for (int a = 0; a < 6; ++a) c[a] = poses[6 * k + a];
-    best = mi[(int64_t)feature_slot * K + k];
+    best = obj[k];
     for (int a = 0; a < 6; ++a) h[a] = h[a] / shrink;
   }
   for (int a = 0; a < 6; ++a) pose_out[a] = c[a];

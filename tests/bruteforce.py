@@ -57,8 +57,20 @@ def zvar_bin(qs, edges):
 
 
 def bins_of(table, key, kind, edges):
+    """kind "count" / "zvar" with that feature's edges; "joint" with the pair
+    (count edges, z-variance edges): the occupied voxel's two bins numbered
+    row-major over the occupied bins (count bins 1.., z-variance bins 1..),
+    after the empty voxel's 0."""
     qs = table.get(key, [])
-    return count_bin(len(qs), edges) if kind == "count" else zvar_bin(qs, edges)
+    if kind == "count":
+        return count_bin(len(qs), edges)
+    if kind == "zvar":
+        return zvar_bin(qs, edges)
+    if not qs:
+        return 0
+    ce, ze = edges
+    n_z_occupied = len(ze) + 1
+    return 1 + (count_bin(len(qs), ce) - 1) * n_z_occupied + (zvar_bin(qs, ze) - 1)
 
 
 def box_of(table, dims):

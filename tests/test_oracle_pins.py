@@ -184,7 +184,7 @@ def _tiny_cloud(rng, n, lo, hi):
     return P.astype(np.float32)
 
 
-@pytest.mark.parametrize("kind", ["count", "zvar"])
+@pytest.mark.parametrize("kind", ["count", "zvar", "joint"])
 @pytest.mark.parametrize("seed", range(4))
 def test_bruteforce_4x4x4(kind, seed):
     rng = np.random.default_rng(100 + seed)
@@ -195,9 +195,12 @@ def test_bruteforce_4x4x4(kind, seed):
     if kind == "count":
         g = O.Grid(origin, dims, vox, features=O.FEAT_COUNT, nb_count=5)
         edges, nb = g.count_edges, 5
-    else:
+    elif kind == "zvar":
         g = O.Grid(origin, dims, vox, features=O.FEAT_ZVAR, nb_zvar=8)
         edges, nb = g.zvar_edges, 8
+    else:
+        g = O.Grid(origin, dims, vox, features=O.FEAT_JOINT, nb_count=4, nb_zvar=6)
+        edges, nb = (g.count_edges, g.zvar_edges[:4]), 1 + 3 * 5
     poses = np.array([[0, 0, 0, 0, 0, 0], [1.0, 0, 0, 0, 0, 0], [0.5, -0.5, 0.25, 0, 0, 0.2],
                       [0, 0, 0, 0.1, -0.1, -0.4], [7.0, 0, 0, 0, 0, 0]])
     mi, H, st = O.eval_poses(g, A, B, poses, want_hist=True, want_stats=True)
@@ -360,3 +363,87 @@ def test_nelder_mead_matches_scipy(fn, x0, max_iter, tols):
     assert it == r.nit - 1
     assert np.max(np.abs(x - r.x)) <= 1e-9
     assert abs(v - r.fun) <= 1e-12 * max(1.0, abs(r.fun))
+
+
+# ------------------------------------------------------------ joint feature
+
+@pytest.fixture(scope="module")
+def tiny_poses():
+    rng = np.random.default_rng(11)
+    return np.concatenate([np.zeros((1, 6)), rng.uniform(-1, 1, (5, 6)) *
+                           np.array([2, 2, 0.2, 0.03, 0.03, 0.15])])
+
+
+def test_joint_with_two_zvar_bins_is_the_count_feature(tiny_poses):
+    """With nb_zvar = 2 every occupied voxel has z-variance bin 1, so the
+    joint value is the count bin: histograms equal the count feature's."""
+    p = synth.tiny_pair()
+    g = O.Grid(p.origin, p.dims, p.voxel, features=O.FEAT_COUNT | O.FEAT_JOINT, nb_count=12,
+               nb_zvar=2)
+    mi, H, _ = O.eval_poses(g, p.A, p.B, tiny_poses, want_hist=True)
+    assert g.feature_list == [(O.FEAT_COUNT, 12), (O.FEAT_JOINT, 12)]
+    assert np.array_equal(H[0], H[1]) and np.array_equal(mi[0], mi[1])
+
+
+def test_joint_with_two_count_bins_is_the_zvar_feature(tiny_poses):
+    p = synth.tiny_pair()
+    g = O.Grid(p.origin, p.dims, p.voxel, features=O.FEAT_ZVAR | O.FEAT_JOINT, nb_count=2,
+               nb_zvar=20)
+    mi, H, _ = O.eval_poses(g, p.A, p.B, tiny_poses, want_hist=True)
+    assert np.array_equal(H[0], H[1]) and np.array_equal(mi[0], mi[1])
+
+
+def test_joint_marginalises_to_each_feature(tiny_poses):
+    """Summing the joint histogram over the z-variance part of both axes gives
+    the count feature's histogram, and over the count part the z-variance
+    feature's; and MI of the joint feature is at least either one's (data
+    processing inequality: each feature is a function of the joint value)."""
+    p = synth.tiny_pair()
+    nbc, nbz = 6, 9
+    gj = O.Grid(p.origin, p.dims, p.voxel, features=O.FEAT_JOINT, nb_count=nbc, nb_zvar=nbz)
+    gs = O.Grid(p.origin, p.dims, p.voxel, features=O.FEAT_COUNT | O.FEAT_ZVAR, nb_count=nbc,
+                nb_zvar=nbz)
+    mij, Hj, _ = O.eval_poses(gj, p.A, p.B, tiny_poses, want_hist=True)
+    mis, Hs, _ = O.eval_poses(gs, p.A, p.B, tiny_poses, want_hist=True)
+    nj = 1 + (nbc - 1) * (nbz - 1)
+    cpart = np.zeros(nj, np.int64)
+    zpart = np.zeros(nj, np.int64)
+    for v in range(1, nj):
+        cpart[v] = 1 + (v - 1) // (nbz - 1)
+        zpart[v] = 1 + (v - 1) % (nbz - 1)
+    for k in range(len(tiny_poses)):
+        J = Hj[0][k].astype(np.int64)
+        C = np.zeros((nbc, nbc), np.int64)
+        Z = np.zeros((nbz, nbz), np.int64)
+        np.add.at(C, (cpart[:, None], cpart[None, :]), J)
+        np.add.at(Z, (zpart[:, None], zpart[None, :]), J)
+        assert np.array_equal(C, Hs[0][k].astype(np.int64)), k
+        assert np.array_equal(Z, Hs[1][k].astype(np.int64)), k
+        assert mij[0][k] >= max(mis[0][k], mis[1][k]) - 1e-12
+
+
+def test_joint_grid_limits():
+    """A joint feature of more than 64 values, or three features, is refused."""
+    z = np.zeros((3, 1), np.float32)
+    for kw in (dict(features=O.FEAT_JOINT, nb_count=10, nb_zvar=10),
+               dict(features=O.FEAT_COUNT | O.FEAT_ZVAR | O.FEAT_JOINT, nb_count=4, nb_zvar=4)):
+        with pytest.raises(RuntimeError):
+            O.eval_poses(O.Grid((0, 0, 0), (4, 4, 4), 1.0, **kw), z, z, np.zeros((1, 6)))
+
+
+# -------------------------------------------------------- weighted objective
+
+def test_weighted_search_reduces_to_one_feature():
+    """Weights (1, 0) and (0, 1) drive the search exactly like feature slots 0
+    and 1, and (4, 0) doubles twice, exactly, the objective of (1, 0)."""
+    p = synth.tiny_pair()
+    g = O.Grid(p.origin, p.dims, p.voxel, features=O.FEAT_COUNT | O.FEAT_ZVAR, nb_count=16,
+               nb_zvar=16)
+    half, samples = [1.5, 1.5, 0.1, 0.02, 0.02, 0.1], [3, 3, 1, 1, 1, 3]
+    for slot, w in ((0, (1.0, 0.0)), (1, (0.0, 1.0))):
+        ps, bs = O.align_c2f(g, p.A, p.B, np.zeros(6), half, samples, 2, 3.0, feature_slot=slot)
+        pw, bw = O.align_c2f(g, p.A, p.B, np.zeros(6), half, samples, 2, 3.0, weights=w)
+        assert np.array_equal(ps, pw) and bs == bw
+    p4, b4 = O.align_c2f(g, p.A, p.B, np.zeros(6), half, samples, 2, 3.0, weights=(4.0, 0.0))
+    p1, b1 = O.align_c2f(g, p.A, p.B, np.zeros(6), half, samples, 2, 3.0, feature_slot=0)
+    assert np.array_equal(p4, p1) and b4 == 4.0 * b1
