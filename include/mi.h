@@ -63,9 +63,20 @@ typedef int32_t mi_status;
 #define MI_E_DEVICE (-3)      /* HIP error */
 #define MI_E_UNSUPPORTED (-4) /* valid but outside the supported sizes */
 
-/* Feature bitmask (Sec. IV: MI-N and MI-VARZ). */
+/* Feature bitmask (Sec. IV: MI-N and MI-VARZ), at most two set.  Feature
+ * slots follow the order count, z-variance, joint. */
 #define MI_FEAT_COUNT 1u /* number of points in the voxel */
 #define MI_FEAT_ZVAR 2u  /* variance of z-height in the voxel */
+/* Both per-voxel features as one value (an extension towards the richer
+ * features the conclusion points to): an occupied voxel with count bin c
+ * (1..nbins_count-1) and z-variance bin z (1..nbins_zvar-1) has value
+ * 1 + (c - 1) * (nbins_zvar - 1) + (z - 1); an empty voxel has 0.  Its bins
+ * number 1 + (nbins_count - 1) * (nbins_zvar - 1), at most 64. */
+#define MI_FEAT_JOINT 4u
+
+/* feature_slot value of the searches that maximises w[0] * MI_0 + w[1] * MI_1
+ * over the grid's feature slots (each product rounded, then the sum). */
+#define MI_SLOT_WEIGHTED (-1)
 
 /* Evaluation flags for mi_plan_create / mi_eval_poses / batches. */
 #define MI_EVAL_NEAR_FACE 1u /* count points within 1e-5 m of a voxel face (stats) */
@@ -78,7 +89,7 @@ typedef int32_t mi_status;
 
 /* Limits. */
 #define MI_MAX_BINS 64
-#define MI_MAX_POINTS ((int64_t)1 << 20) /* per scan B when MI_FEAT_ZVAR is on */
+#define MI_MAX_POINTS ((int64_t)1 << 20) /* per scan B when MI_FEAT_ZVAR or _JOINT is on */
 
 /* The voxel grid of resolution R_v that encompasses both scans (Sec. III-A)
  * plus the feature description.  Axis-aligned in scan A's frame. */
@@ -86,10 +97,10 @@ typedef struct mi_grid_desc {
   double origin[3];             /* m, lower corner of voxel (0,0,0) */
   int32_t dims[3];              /* voxels per axis, each >= 1, product < 2^31 */
   double voxel;                 /* edge length R_v in m, > 0 */
-  uint32_t features;            /* MI_FEAT_* bitmask, non-zero */
-  int32_t nbins_count;          /* 2..64 when MI_FEAT_COUNT */
+  uint32_t features;            /* MI_FEAT_* bitmask, one or two bits */
+  int32_t nbins_count;          /* 2..64 when MI_FEAT_COUNT or MI_FEAT_JOINT */
   const uint32_t *count_edges;  /* host, nbins_count-1 ascending, first >= 1; NULL = default */
-  int32_t nbins_zvar;           /* 3..64 when MI_FEAT_ZVAR */
+  int32_t nbins_zvar;           /* 3..64 when MI_FEAT_ZVAR; 2..64 for MI_FEAT_JOINT alone */
   const uint64_t *zvar_edges;   /* host, nbins_zvar-2 ascending; NULL = default */
 } mi_grid_desc;
 
@@ -311,15 +322,17 @@ mi_status mi_autotune(const mi_work_item *items, int64_t n_items, uint32_t flags
  * re-centring a shrinking pose grid on the best pose).  Level l evaluates, per
  * axis, samples[a] nodes c + h*(-1 + 2j/(samples[a]-1)) (c alone when 1),
  * row-major over (tx, ty, tz, roll, pitch, yaw), yaw fastest; the next level is
- * centred on the argmax of feature slot `feature_slot` with h divided by
- * `shrink`.  Synchronizes the stream once per level.  ws from
- * mi_align_workspace. */
+ * centred on the argmax of feature slot `feature_slot` (or, with
+ * MI_SLOT_WEIGHTED, of the weighted objective) with h divided by `shrink`.
+ * mi_out gets that objective at the final pose.  Synchronizes the stream once
+ * per level.  ws from mi_align_workspace. */
 typedef struct mi_c2f_desc {
   double half_range[6];
   int32_t samples[6];
   int32_t levels;
   double shrink;
-  int32_t feature_slot;
+  int32_t feature_slot;         /* 0 .. slots-1, or MI_SLOT_WEIGHTED */
+  double weight[2];             /* per slot, when feature_slot == MI_SLOT_WEIGHTED */
 } mi_c2f_desc;
 
 size_t mi_align_workspace(const mi_ref *r, int64_t n_b, const mi_c2f_desc *d);
@@ -328,7 +341,8 @@ mi_status mi_align_coarse_to_fine(const mi_ref *r, const float *xyz_b, int64_t n
                                   double *mi_out, void *ws, size_t ws_bytes, void *stream);
 
 /* Simplex search for Eq. 1 (Alg. 1 with the Nelder-Mead update of
- * Sec. III-B): maximises the MI of feature slot `feature_slot` over the pose.
+ * Sec. III-B): maximises the MI of feature slot `feature_slot` (or, with
+ * MI_SLOT_WEIGHTED, the weighted objective) over the pose.
  * Each start gets a simplex of N + 1 = 7 vertices (the start, and the start
  * moved by step[i] along parameter i; Sec. IV uses steps 8, 8, 1 m, 0.1, 0.1,
  * 0.8 rad), improved with the usual coefficients (reflection 1, expansion 2,
@@ -347,7 +361,8 @@ typedef struct mi_nm_desc {
   int32_t max_iter;
   double ftol;
   double xtol;
-  int32_t feature_slot;
+  int32_t feature_slot;         /* 0 .. slots-1, or MI_SLOT_WEIGHTED */
+  double weight[2];             /* per slot, when feature_slot == MI_SLOT_WEIGHTED */
 } mi_nm_desc;
 
 size_t mi_align_nm_workspace(const mi_ref *r, int64_t n_b, int32_t n_starts);

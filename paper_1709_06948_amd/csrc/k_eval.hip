@@ -203,6 +203,7 @@ __global__ void __launch_bounds__(1024) k_eval(const PairDev *__restrict__ pairs
     const int ahi0 = P.abox[3], ahi1 = P.abox[4], ahi2 = P.abox[5];
     uint32_t *myhist = hist + (wid % cfg.hist_copies) * cfg.hist_words;
     const uint32_t kind0 = P.kind[0], kind1 = P.kind[1];
+    const int nbc = P.nbc, nbz = P.nbz;
     const bool count_default = P.count_default != 0;
     const uint8_t *binA0 = P.binA[0], *binA1 = P.binA[1];
     const int BY = P.stripe_h, NS = P.n_stripes, Q = P.pieces, RM = BY + 2;
@@ -594,20 +595,26 @@ __global__ void __launch_bounds__(1024) k_eval(const PairDev *__restrict__ pairs
                 if (!overflow && ix >= alo0 && ix <= ahi0 && iy >= alo1 && iy <= ahi1 &&
                     iz >= alo2 && iz <= ahi2) {
                   const int64_t lin = ((int64_t)iz * ny + iy) * nx + ix;
-                  // count bins: O(1) with the default edges 1, 2, ..., nb - 1
-                  auto bin_of = [&](uint32_t kind, int nb) -> int {
-                    if (kind == MI_FEAT_COUNT)
-                      return count_default ? (int)min(n, (uint32_t)(nb - 1))
-                                           : bin_count_dev(n, nb, cedge);
-                    return bin_zvar_nodiv(n, s1, s2, nb, zedged, zedge);
+                  // count bins: O(1) with the default edges 1, 2, ..., nb - 1; the
+                  // joint feature numbers its (count, z-variance) bin pairs
+                  auto bin_of = [&](uint32_t kind) -> int {
+                    int bc = 0, bz = 0;
+                    if (kind != MI_FEAT_ZVAR)
+                      bc = count_default ? (int)min(n, (uint32_t)(nbc - 1))
+                                         : bin_count_dev(n, nbc, cedge);
+                    if (ZVAR && kind != MI_FEAT_COUNT)
+                      bz = bin_zvar_nodiv(n, s1, s2, nbz, zedged, zedge);
+                    if (kind == MI_FEAT_COUNT) return bc;
+                    if (kind == MI_FEAT_ZVAR) return bz;
+                    return joint_value(bc, bz, nbz);
                   };
                   {
                     const int a = ldg(binA0 + lin);
-                    atomicAdd(&myhist[a * nb0 + bin_of(kind0, nb0)], 1u);
+                    atomicAdd(&myhist[a * nb0 + bin_of(kind0)], 1u);
                   }
                   if (nf > 1) {
                     const int a = ldg(binA1 + lin);
-                    atomicAdd(&myhist[hoff1 + a * nb1 + bin_of(kind1, nb1)], 1u);
+                    atomicAdd(&myhist[hoff1 + a * nb1 + bin_of(kind1)], 1u);
                   }
                 }
               }

@@ -140,8 +140,8 @@ __global__ void __launch_bounds__(256) k_plain_hist(PlainDev pd) {
     for (int f = 0; f < pd.nf; ++f) {
       const int nb = pd.nb[f];
       const int a = pd.binA[f][v];
-      const int b = pd.kind[f] == MI_FEAT_COUNT ? bin_count_dev(n, nb, pd.count_edges)
-                                                : bin_zvar_dev(n, s1, s2, nb, pd.zvar_edges);
+      const int b = feature_bin_dev(pd.kind[f], n, s1, s2, pd.nbc, pd.count_edges, pd.nbz,
+                                    pd.zvar_edges);
       atomicAdd(&lh[(f ? nb0 * nb0 : 0) + a * nb + b], 1u);
     }
   }

@@ -72,9 +72,8 @@ __global__ void __launch_bounds__(256) k_ref_bins(RefDev rd) {
     const uint32_t n = rd.cnt[v];
     if (n) ++occ;
     for (int f = 0; f < rd.nf; ++f) {
-      const int b = rd.kind[f] == MI_FEAT_COUNT
-                        ? bin_count_dev(n, rd.nb[f], rd.count_edges)
-                        : bin_zvar_dev(n, rd.s1[v], rd.s2[v], rd.nb[f], rd.zvar_edges);
+      const int b = feature_bin_dev(rd.kind[f], n, rd.s1[v], rd.s2[v], rd.nbc, rd.count_edges,
+                                    rd.nbz, rd.zvar_edges);
       rd.bins[f][v] = (uint8_t)b;
     }
   }

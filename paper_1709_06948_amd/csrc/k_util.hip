@@ -56,6 +56,28 @@ hipError_t launch_argmax(const double *mi, int64_t K, int32_t nf, int64_t *out, 
   return hipGetLastError();
 }
 
+// Weighted search objective: out[k] = w0 * mi[k] + w1 * mi[K + k], each
+// product rounded, then the sum (no fused multiply-add).
+__global__ void __launch_bounds__(256) k_weighted(const double *__restrict__ mi, int64_t K,
+                                                  int32_t nf, double w0, double w1,
+                                                  double *__restrict__ out) {
+  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < K;
+       k += (int64_t)gridDim.x * blockDim.x) {
+    double v = w0 * mi[k];
+    if (nf > 1) v = v + w1 * mi[K + k];
+    out[k] = v;
+  }
+}
+
+hipError_t launch_weighted(const double *mi, int64_t K, int32_t nf, double w0, double w1,
+                           double *out, hipStream_t s) {
+  if (K <= 0) return hipSuccess;
+  int64_t g = (K + 255) / 256;
+  if (g > 1024) g = 1024;
+  k_weighted<<<(unsigned)g, 256, 0, s>>>(mi, K, nf, w0, w1, out);
+  return hipGetLastError();
+}
+
 __global__ void __launch_bounds__(256) k_count_nonfinite(const float *__restrict__ xyz, int64_t n,
                                                          unsigned long long *out) {
   unsigned long long c = 0;

@@ -329,11 +329,13 @@ extern "C" mi_status mi_grid_create(const mi_grid_desc *d, mi_grid **out) {
   if (!(d->voxel > 0.0) || !std::isfinite(d->voxel)) return fail(MI_E_INVALID, "voxel <= 0");
   gi.voxel = d->voxel;
   gi.s = 1.0 / d->voxel;
-  if (d->features == 0 || (d->features & ~(MI_FEAT_COUNT | MI_FEAT_ZVAR)))
-    return fail(MI_E_INVALID, "features bitmask %u", d->features);
+  const uint32_t all = MI_FEAT_COUNT | MI_FEAT_ZVAR | MI_FEAT_JOINT;
+  if (d->features == 0 || (d->features & ~all) || d->features == all)
+    return fail(MI_E_INVALID, "features bitmask %u (one or two of count, z-variance, joint)",
+                d->features);
   gi.features = d->features;
   gi.nf = 0;
-  if (d->features & MI_FEAT_COUNT) {
+  if (d->features & (MI_FEAT_COUNT | MI_FEAT_JOINT)) {
     const int nb = d->nbins_count;
     if (nb < 2 || nb > kMaxBins) return fail(MI_E_INVALID, "nbins_count %d not in 2..64", nb);
     if (d->count_edges) {
@@ -345,14 +347,15 @@ extern "C" mi_status mi_grid_create(const mi_grid_desc *d, mi_grid **out) {
     } else {
       for (int j = 0; j < nb - 1; ++j) gi.count_edges[j] = (uint32_t)(j + 1);
     }
-    gi.kind[gi.nf] = MI_FEAT_COUNT;
-    gi.nb[gi.nf] = nb;
-    gi.nf++;
+    gi.nbc = nb;
   }
-  if (d->features & MI_FEAT_ZVAR) {
+  if (d->features & (MI_FEAT_ZVAR | MI_FEAT_JOINT)) {
     const int nb = d->nbins_zvar;
-    if (nb < 3 || nb > kMaxBins) return fail(MI_E_INVALID, "nbins_zvar %d not in 3..64", nb);
-    if (d->zvar_edges) {
+    const int lo = (d->features & MI_FEAT_ZVAR) ? 3 : 2;
+    if (nb < lo || nb > kMaxBins) return fail(MI_E_INVALID, "nbins_zvar %d not in %d..64", nb, lo);
+    if (nb == 2) {
+      // the joint feature's z part with no edges: every occupied voxel is bin 1
+    } else if (d->zvar_edges) {
       for (int j = 0; j < nb - 2; ++j) gi.zvar_edges[j] = d->zvar_edges[j];
       for (int j = 1; j < nb - 2; ++j)
         if (gi.zvar_edges[j] < gi.zvar_edges[j - 1])
@@ -360,9 +363,23 @@ extern "C" mi_status mi_grid_create(const mi_grid_desc *d, mi_grid **out) {
     } else if (default_zvar_edges(d->voxel, nb, gi.zvar_edges)) {
       return fail(MI_E_INVALID, "default z-variance edges need voxel^2/4 > 1e-5 m^2");
     }
+    gi.nbz = nb;
+  }
+  if (d->features & MI_FEAT_COUNT) {
+    gi.kind[gi.nf] = MI_FEAT_COUNT;
+    gi.nb[gi.nf++] = gi.nbc;
+  }
+  if (d->features & MI_FEAT_ZVAR) {
     gi.kind[gi.nf] = MI_FEAT_ZVAR;
-    gi.nb[gi.nf] = nb;
-    gi.nf++;
+    gi.nb[gi.nf++] = gi.nbz;
+  }
+  if (d->features & MI_FEAT_JOINT) {
+    const int nbj = 1 + (gi.nbc - 1) * (gi.nbz - 1);
+    if (nbj > kMaxBins)
+      return fail(MI_E_INVALID, "joint feature has %d bins > 64 ((nbins_count-1)*(nbins_zvar-1)+1)",
+                  nbj);
+    gi.kind[gi.nf] = MI_FEAT_JOINT;
+    gi.nb[gi.nf++] = nbj;
   }
   mi_grid *g = (mi_grid *)malloc(sizeof(mi_grid));
   if (!g) return fail(MI_E_INVALID, "out of host memory");
@@ -375,13 +392,10 @@ extern "C" void mi_grid_destroy(mi_grid *g) { free(g); }
 
 extern "C" mi_status mi_grid_edges(const mi_grid *g, uint32_t *ce, uint64_t *ze) {
   if (!g) return fail(MI_E_INVALID, "mi_grid_edges: NULL grid");
-  for (int f = 0; f < g->gi.nf; ++f) {
-    const int nb = g->gi.nb[f];
-    if (g->gi.kind[f] == MI_FEAT_COUNT && ce)
-      for (int j = 0; j < nb - 1; ++j) ce[j] = g->gi.count_edges[j];
-    if (g->gi.kind[f] == MI_FEAT_ZVAR && ze)
-      for (int j = 0; j < nb - 2; ++j) ze[j] = g->gi.zvar_edges[j];
-  }
+  if (ce)
+    for (int j = 0; j + 1 < g->gi.nbc; ++j) ce[j] = g->gi.count_edges[j];
+  if (ze)
+    for (int j = 0; j + 2 < g->gi.nbz; ++j) ze[j] = g->gi.zvar_edges[j];
   return MI_OK;
 }
 
@@ -470,6 +484,8 @@ extern "C" mi_status mi_features_ref(const mi_grid *g, const float *xyz_a, int64
                              c.used(), ws_bytes);
   rd.nx = gi.dims[0]; rd.ny = gi.dims[1]; rd.nz = gi.dims[2]; rd.nf = gi.nf;
   for (int f = 0; f < 2; ++f) { rd.kind[f] = gi.kind[f]; rd.nb[f] = gi.nb[f]; }
+  rd.nbc = gi.nbc;
+  rd.nbz = gi.nbz;
   rd.s = gi.s;
   for (int a = 0; a < 3; ++a) rd.c0[a] = (0.0 - gi.origin[a]) * gi.s;
   memcpy(rd.count_edges, gi.count_edges, sizeof rd.count_edges);
@@ -778,7 +794,7 @@ mi_status prepare_batch(const mi_work_item *w, int64_t n, uint32_t flags, BatchT
     if (it.K < 0 || it.n_b < 0 || (it.K > 0 && !it.poses))
       return fail(MI_E_INVALID, "work item %lld: bad pose set or scan B", (long long)i);
     const GridInfo &gi = it.ref->g->gi;
-    zvar = zvar || (gi.features & MI_FEAT_ZVAR) != 0;
+    zvar = zvar || (gi.features & (MI_FEAT_ZVAR | MI_FEAT_JOINT)) != 0;
     hist_words = std::max(hist_words, gi.nb[0] * gi.nb[0] + (gi.nf > 1 ? gi.nb[1] * gi.nb[1] : 0));
   }
   B.T.assign((size_t)n, PoseTables());
@@ -1094,6 +1110,8 @@ mi_status create_plan(const mi_work_item *w, int64_t n, uint32_t flags, void *ws
       P.binA[f] = rd.bins[f];
       P.sat[f] = rd.sat[f];
     }
+    P.nbc = gi.nbc;
+    P.nbz = gi.nbz;
     P.voxel = gi.voxel;
     P.abox = rd.abox;
     P.stripe_h = S.stripe_h;
@@ -1103,10 +1121,8 @@ mi_status create_plan(const mi_work_item *w, int64_t n, uint32_t flags, void *ws
     P.ky_bits = S.ky_bits;
     P.plan_stripes = S.plan_stripes;
     P.count_default = 1;
-    for (int f = 0; f < gi.nf; ++f)
-      if (gi.kind[f] == MI_FEAT_COUNT)
-        for (int j = 0; j + 1 < gi.nb[f]; ++j)
-          if (gi.count_edges[j] != (uint32_t)(j + 1)) P.count_default = 0;
+    for (int j = 0; j + 1 < gi.nbc; ++j)
+      if (gi.count_edges[j] != (uint32_t)(j + 1)) P.count_default = 0;
     P.nonfinite = PL.nonfinite + 2 * i;
     P.n_b = w[i].n_b;
     P.mi_out = w[i].mi_out;
@@ -1473,6 +1489,8 @@ extern "C" mi_status mi_eval_poses_plain(const mi_ref *r, const float *xyz_b, in
     pd.nb[f] = gi.nb[f];
     pd.binA[f] = r->rd.bins[f];
   }
+  pd.nbc = gi.nbc;
+  pd.nbz = gi.nbz;
   pd.voxel = gi.voxel;
   pd.s = gi.s;
   pd.abox = r->rd.abox;
@@ -1508,9 +1526,27 @@ extern "C" mi_status mi_eval_poses_plain(const mi_ref *r, const float *xyz_b, in
 // ------------------------------------------------------------ coarse-to-fine
 
 namespace {
+// A search's objective: one feature slot, or the weighted slots (finite weights).
+bool slot_ok(int32_t slot, const double w[2], int nf) {
+  if (slot == MI_SLOT_WEIGHTED) return std::isfinite(w[0]) && std::isfinite(w[1]);
+  return slot >= 0 && slot < nf;
+}
+
+// Row of a search's objective within mi [nf + 1][K]: the slot's row, or row nf
+// after the weighted objective is written there.
+hipError_t objective_row(double *mi, int64_t K, int nf, int32_t slot, const double w[2],
+                         const double **row, hipStream_t s) {
+  if (slot != MI_SLOT_WEIGHTED) {
+    *row = mi + (int64_t)slot * K;
+    return hipSuccess;
+  }
+  *row = mi + (int64_t)nf * K;
+  return launch_weighted(mi, K, nf, w[0], w[1], mi + (int64_t)nf * K, s);
+}
+
 bool c2f_ok(const mi_c2f_desc *d, int nf) {
   if (!d || d->levels < 1 || !(d->shrink > 0.0) || !std::isfinite(d->shrink)) return false;
-  if (d->feature_slot < 0 || d->feature_slot >= nf) return false;
+  if (!slot_ok(d->feature_slot, d->weight, nf)) return false;
   for (int a = 0; a < 6; ++a)
     if (d->samples[a] < 1 || d->samples[a] > 1024 || !std::isfinite(d->half_range[a]) ||
         d->half_range[a] < 0.0)
@@ -1560,7 +1596,7 @@ extern "C" size_t mi_align_workspace(const mi_ref *r, int64_t n_b, const mi_c2f_
   if (build_tables(gi, P.data(), K, T)) return 0;
   const int64_t ncols = (int64_t)(T.ncx + 2) * (T.ncy + 2);
   Carver c(nullptr, 0);
-  c.take<double>((size_t)gi.nf * (size_t)K);
+  c.take<double>(((size_t)gi.nf + 1) * (size_t)K);
   c.take<int64_t>(2 * 8);
   return c.used() + single_plan_bytes(K, (int32_t)F, ncols, n_b) + 512;
 }
@@ -1577,7 +1613,7 @@ extern "C" mi_status mi_align_coarse_to_fine(const mi_ref *r, const float *xyz_b
   if (!ws || ((uintptr_t)ws & 255)) return fail(MI_E_WORKSPACE, "workspace NULL or not 256-aligned");
   const int64_t K = c2f_count(d);
   Carver c(ws, ws_bytes);
-  double *mi_dev = c.take<double>((size_t)gi.nf * (size_t)K);
+  double *mi_dev = c.take<double>(((size_t)gi.nf + 1) * (size_t)K);
   int64_t *am_dev = c.take<int64_t>(2);
   double *mv_dev = c.take<double>(2);
   c.take<char>(0);
@@ -1597,8 +1633,9 @@ extern "C" mi_status mi_align_coarse_to_fine(const mi_ref *r, const float *xyz_b
     st = mi_plan_execute(p, xyz_b, mi_dev, nullptr, nullptr, nullptr, stream);
     mi_plan_destroy(p);
     if (st != MI_OK) return st;
-    HIP_TRY(launch_argmax(mi_dev + (int64_t)d->feature_slot * K, K, 1, am_dev, mv_dev, s),
-            "argmax");
+    const double *obj = nullptr;
+    HIP_TRY(objective_row(mi_dev, K, gi.nf, d->feature_slot, d->weight, &obj, s), "objective");
+    HIP_TRY(launch_argmax(obj, K, 1, am_dev, mv_dev, s), "argmax");
     int64_t kbest = 0;
     double mv = 0.0;
     HIP_TRY(hipMemcpyAsync(&kbest, am_dev, sizeof kbest, hipMemcpyDeviceToHost, s), "argmax D2H");
@@ -1713,7 +1750,7 @@ size_t req_step_bytes(const Request &r) {
   const int64_t ncols = (int64_t)(gi.dims[0] + spread_x) * (int64_t)(gi.dims[1] + spread_y);
   const FrameBytes fb = frame_bytes(r.n_b, ncols);
   return al256((size_t)K * sizeof(PoseDev)) + al256(sizeof(PairDev)) +
-         al256((size_t)K * sizeof(FrameDev)) + al256((size_t)gi.nf * K * 8) + 4 * 256 + fb.v +
+         al256((size_t)K * sizeof(FrameDev)) + al256(((size_t)gi.nf + 1) * K * 8) + 4 * 256 + fb.v +
          fb.off + al256(fb.cur) + 4096;
 }
 
@@ -1799,7 +1836,7 @@ mi_status run_level(mi_server *s, Request *const *rs, size_t n,
     Request *r = rs[i];
     c2f_grid(r->ctr, r->h, r->search.samples, r->P);
     const int64_t K = (int64_t)(r->P.size() / 6);
-    mis[i] = c.take<double>((size_t)r->g->gi.nf * (size_t)K);
+    mis[i] = c.take<double>(((size_t)r->g->gi.nf + 1) * (size_t)K);
     ams[i] = c.take<int64_t>(1);
     mvs[i] = c.take<double>(1);
     mi_work_item &w = items[i];
@@ -1835,8 +1872,10 @@ mi_status run_level(mi_server *s, Request *const *rs, size_t n,
   for (size_t i = 0; i < n; ++i) {
     Request *r = rs[i];
     const int64_t K = items[i].K;
-    HIP_TRY(launch_argmax(mis[i] + (int64_t)r->search.feature_slot * K, K, 1, ams[i], mvs[i],
-                          s->stream), "argmax");
+    const double *obj = nullptr;
+    HIP_TRY(objective_row(mis[i], K, r->g->gi.nf, r->search.feature_slot, r->search.weight, &obj,
+                          s->stream), "objective");
+    HIP_TRY(launch_argmax(obj, K, 1, ams[i], mvs[i], s->stream), "argmax");
     char *dst = s->pinned + 16 * r->slot;
     HIP_TRY(hipMemcpyAsync(dst, ams[i], 8, hipMemcpyDeviceToHost, s->stream), "argmax D2H");
     HIP_TRY(hipMemcpyAsync(dst + 8, mvs[i], 8, hipMemcpyDeviceToHost, s->stream), "MI D2H");
@@ -1893,7 +1932,7 @@ extern "C" mi_status mi_server_submit(mi_server *s, const mi_request *q, int64_t
   std::unique_ptr<mi_grid, void (*)(mi_grid *)> gguard(r->g, mi_grid_destroy);
   const GridInfo &gi = r->g->gi;
   if (!c2f_ok(&q->search, gi.nf)) return fail(MI_E_INVALID, "bad search description");
-  if ((gi.features & MI_FEAT_ZVAR) && q->n_b >= MI_MAX_POINTS)
+  if ((gi.features & (MI_FEAT_ZVAR | MI_FEAT_JOINT)) && q->n_b >= MI_MAX_POINTS)
     return fail(MI_E_UNSUPPORTED, "scan B has >= 2^20 points with the z-variance feature");
   r->search = q->search;
   r->n_a = q->n_a;
@@ -2114,7 +2153,7 @@ struct Simplex {
 };
 
 bool nm_ok(const mi_nm_desc *d, int nf) {
-  if (!d || d->max_iter < 0 || d->feature_slot < 0 || d->feature_slot >= nf) return false;
+  if (!d || d->max_iter < 0 || !slot_ok(d->feature_slot, d->weight, nf)) return false;
   if (!(d->ftol >= 0.0) || !(d->xtol >= 0.0)) return false;
   for (int a = 0; a < 6; ++a)
     if (!std::isfinite(d->step[a])) return false;
@@ -2191,12 +2230,23 @@ extern "C" mi_status mi_align_nelder_mead(const mi_ref *r, const float *xyz_b, i
     st = run_plan(p, s);
     mi_plan_destroy(p);
     if (st != MI_OK) return st;
-    host_mi.resize((size_t)K);
-    HIP_TRY(hipMemcpyAsync(host_mi.data(), mi_dev + (int64_t)d->feature_slot * K,
-                           sizeof(double) * (size_t)K, hipMemcpyDeviceToHost, s), "MI D2H");
+    const bool weighted = d->feature_slot == MI_SLOT_WEIGHTED;
+    const int rows = weighted ? gi.nf : 1;
+    host_mi.resize((size_t)rows * (size_t)K);
+    HIP_TRY(hipMemcpyAsync(host_mi.data(), mi_dev + (weighted ? 0 : (int64_t)d->feature_slot * K),
+                           sizeof(double) * (size_t)rows * (size_t)K, hipMemcpyDeviceToHost, s),
+            "MI D2H");
     HIP_TRY(hipStreamSynchronize(s), "simplex round sync");
     vals.resize((size_t)K);
-    for (int64_t k = 0; k < K; ++k) vals[(size_t)k] = -host_mi[(size_t)k];
+    for (int64_t k = 0; k < K; ++k) {
+      double v = host_mi[(size_t)k];
+      if (weighted) {
+        // the weighted objective: each product rounded, then the sum
+        v = d->weight[0] * host_mi[(size_t)k];
+        if (gi.nf > 1) v = v + d->weight[1] * host_mi[(size_t)K + (size_t)k];
+      }
+      vals[(size_t)k] = -v;
+    }
     size_t off = 0;
     for (Simplex &S : sx) {
       if (S.state == Simplex::kDone) continue;

@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "mi.h"
+
 namespace mi {
 
 typedef unsigned __int128 u128;
@@ -91,6 +93,23 @@ __device__ __forceinline__ int bin_zvar_nodiv(uint32_t n, uint64_t s1, uint64_t 
   }
   if (near) lo = bin_zvar_exact(D, (u128)n * (u128)n, m, E);
   return 1 + lo;
+}
+
+// Value of the joint feature (MI_FEAT_JOINT) of an occupied voxel from its
+// count bin bc (>= 1) and z-variance bin bz (>= 1) under nbz z-variance bins.
+__device__ __forceinline__ int joint_value(int bc, int bz, int nbz) {
+  return 1 + (bc - 1) * (nbz - 1) + (bz - 1);
+}
+
+// Bin of a voxel with n points and height sums s1, s2 under a feature kind;
+// nbc / ce and nbz / ze are the grid's count and z-variance bins and edges.
+__device__ __forceinline__ int feature_bin_dev(uint32_t kind, uint32_t n, uint64_t s1, uint64_t s2,
+                                               int nbc, const uint32_t *ce, int nbz,
+                                               const uint64_t *ze) {
+  if (kind == MI_FEAT_COUNT) return bin_count_dev(n, nbc, ce);
+  if (kind == MI_FEAT_ZVAR) return bin_zvar_dev(n, s1, s2, nbz, ze);
+  if (n == 0) return 0;
+  return joint_value(bin_count_dev(n, nbc, ce), bin_zvar_dev(n, s1, s2, nbz, ze), nbz);
 }
 
 // Entropy term -p ln p for a count c out of N (0 ln 0 = 0), Eqs. 3-5.

@@ -25,6 +25,7 @@ struct GridInfo {
   int32_t nf;     // number of enabled features (1 or 2)
   uint32_t kind[2];
   int32_t nb[2];
+  int32_t nbc, nbz;  // count and z-variance bins (also the joint feature's parts)
   int64_t V;
   uint32_t count_edges[kMaxBins];
   uint64_t zvar_edges[kMaxBins];
@@ -36,6 +37,7 @@ struct RefDev {
   int32_t nx, ny, nz, nf;
   uint32_t kind[2];
   int32_t nb[2];
+  int32_t nbc, nbz;
   double s;
   double c0[3];              // fl(fl(0 - origin) * s)
   uint32_t count_edges[kMaxBins];
@@ -79,6 +81,7 @@ struct PairDev {
   int32_t nx, ny, nz, nf;
   uint32_t kind[2];
   int32_t nb[2];
+  int32_t nbc, nbz;
   double voxel;
   const uint8_t *binA[2];
   const uint32_t *sat[2];
@@ -144,6 +147,7 @@ struct PlainDev {
   int32_t nx, ny, nz, nf;
   uint32_t kind[2];
   int32_t nb[2];
+  int32_t nbc, nbz;
   double voxel, s;
   const uint8_t *binA[2];
   const int32_t *abox;
@@ -171,6 +175,9 @@ hipError_t launch_plain_clear_dense(const PlainDev &pd, hipStream_t s);
 hipError_t launch_fill_u32(uint32_t *p, uint32_t value, int64_t n, hipStream_t s);
 hipError_t launch_argmax(const double *mi, int64_t K, int32_t nf, int64_t *out, double *out_val,
                          hipStream_t s);
+// out[k] = w0 * mi[k] + w1 * mi[K + k] (the second term when nf == 2)
+hipError_t launch_weighted(const double *mi, int64_t K, int32_t nf, double w0, double w1,
+                           double *out, hipStream_t s);
 hipError_t launch_bind(PairDev *pair, FrameDev *frames, int32_t n_frames, const float *xyz,
                        double *mi_out, uint32_t *hist_out, mi_pose_stats *stats_out,
                        hipStream_t s);

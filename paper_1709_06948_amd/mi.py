@@ -17,7 +17,8 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libmi355.so")
 
 MI_OK, MI_E_INVALID, MI_E_WORKSPACE, MI_E_DEVICE, MI_E_UNSUPPORTED = 0, -1, -2, -3, -4
-FEAT_COUNT, FEAT_ZVAR = 1, 2
+FEAT_COUNT, FEAT_ZVAR, FEAT_JOINT = 1, 2, 4
+SLOT_WEIGHTED = -1         # searches maximise w0 * MI_0 + w1 * MI_1
 EVAL_NEAR_FACE = 1
 EVAL_PER_POSE = 2          # force per-pose bucketing
 EVAL_SHARED_FRAMES = 4     # force shared rotated frames
@@ -44,7 +45,7 @@ class _GridDesc(C.Structure):
 
 class _C2F(C.Structure):
     _fields_ = [("half_range", C.c_double * 6), ("samples", C.c_int32 * 6), ("levels", C.c_int32),
-                ("shrink", C.c_double), ("feature_slot", C.c_int32)]
+                ("shrink", C.c_double), ("feature_slot", C.c_int32), ("weight", C.c_double * 2)]
 
 
 class _Profile(C.Structure):
@@ -61,7 +62,7 @@ class _WorkItem(C.Structure):
 
 class _NMDesc(C.Structure):
     _fields_ = [("step", C.c_double * 6), ("max_iter", C.c_int32), ("ftol", C.c_double),
-                ("xtol", C.c_double), ("feature_slot", C.c_int32)]
+                ("xtol", C.c_double), ("feature_slot", C.c_int32), ("weight", C.c_double * 2)]
 
 
 class _ServerDesc(C.Structure):
@@ -270,6 +271,8 @@ class Grid:
             out.append((FEAT_COUNT, self.nb_count))
         if self.features & FEAT_ZVAR:
             out.append((FEAT_ZVAR, self.nb_zvar))
+        if self.features & FEAT_JOINT:
+            out.append((FEAT_JOINT, 1 + (self.nb_count - 1) * (self.nb_zvar - 1)))
         return out
 
     @property
@@ -513,16 +516,20 @@ def autotune(items, flags=0, max_poses=4096, stream=None) -> dict:
                 best_ms=rep.best_ms, start_ms=rep.start_ms, tried=rep.tried)
 
 
+def _objective(d, feature_slot, weights):
+    if weights is None:
+        d.feature_slot = int(feature_slot)
+    else:
+        d.feature_slot = SLOT_WEIGHTED
+        d.weight[:] = [float(v) for v in weights]
+
+
 def align_coarse_to_fine(ref: Ref, xyz_b, init, half_range, samples, levels, shrink,
-                         feature_slot=0, stream=None):
-    """mi_align_coarse_to_fine: shrinking grid search for Eq. 1 from T_o."""
+                         feature_slot=0, stream=None, weights=None):
+    """mi_align_coarse_to_fine: shrinking grid search for Eq. 1 from T_o, on
+    one feature slot or, given weights (w0, w1), on w0 * MI_0 + w1 * MI_1."""
     xb = _dev_points(xyz_b)
-    d = _C2F()
-    d.half_range[:] = [float(v) for v in half_range]
-    d.samples[:] = [int(v) for v in samples]
-    d.levels = int(levels)
-    d.shrink = float(shrink)
-    d.feature_slot = int(feature_slot)
+    d = _c2f_desc(half_range, samples, levels, shrink, feature_slot, weights)
     nbytes = _lib.mi_align_workspace(ref._h, xb.shape[1], C.byref(d))
     if nbytes == 0:
         raise MIError(MI_E_INVALID, "mi_align_workspace", "bad arguments")
@@ -539,7 +546,7 @@ def align_coarse_to_fine(ref: Ref, xyz_b, init, half_range, samples, levels, shr
 
 
 def align_nelder_mead(ref: Ref, xyz_b, starts, step, max_iter, ftol, xtol, feature_slot=0,
-                      stream=None):
+                      stream=None, weights=None):
     """mi_align_nelder_mead: simplex search for Eq. 1 (Sec. III-B) from one or
     more starts, the simplexes advancing together in batched evaluations.
     Returns (pose[6], MI, iterations per start)."""
@@ -550,7 +557,7 @@ def align_nelder_mead(ref: Ref, xyz_b, starts, step, max_iter, ftol, xtol, featu
     d.max_iter = int(max_iter)
     d.ftol = float(ftol)
     d.xtol = float(xtol)
-    d.feature_slot = int(feature_slot)
+    _objective(d, feature_slot, weights)
     nbytes = _lib.mi_align_nm_workspace(ref._h, xb.shape[1], S.shape[0])
     if nbytes == 0:
         raise MIError(MI_E_INVALID, "mi_align_nm_workspace", _lib.mi_last_error().decode())
@@ -572,13 +579,13 @@ def align_nelder_mead(ref: Ref, xyz_b, starts, step, max_iter, ftol, xtol, featu
 REQ_QUEUED, REQ_ACTIVE, REQ_DONE, REQ_FAILED = 0, 1, 2, 3
 
 
-def _c2f_desc(half_range, samples, levels, shrink, feature_slot) -> _C2F:
+def _c2f_desc(half_range, samples, levels, shrink, feature_slot, weights=None) -> _C2F:
     d = _C2F()
     d.half_range[:] = [float(v) for v in half_range]
     d.samples[:] = [int(v) for v in samples]
     d.levels = int(levels)
     d.shrink = float(shrink)
-    d.feature_slot = int(feature_slot)
+    _objective(d, feature_slot, weights)
     return d
 
 
@@ -597,7 +604,8 @@ class Server:
         self._h = h
 
     def submit(self, origin, dims, voxel, xyz_a, xyz_b, init, half_range, samples, levels,
-               shrink, features=FEAT_COUNT, nb_count=16, nb_zvar=32, feature_slot=0) -> int:
+               shrink, features=FEAT_COUNT, nb_count=16, nb_zvar=32, feature_slot=0,
+               weights=None) -> int:
         A = np.ascontiguousarray(xyz_a, np.float32)
         B = np.ascontiguousarray(xyz_b, np.float32)
         q = _Request()
@@ -612,7 +620,7 @@ class Server:
         q.xyz_b = B.ctypes.data
         q.n_b = B.shape[1]
         q.init[:] = [float(v) for v in init]
-        q.search = _c2f_desc(half_range, samples, levels, shrink, feature_slot)
+        q.search = _c2f_desc(half_range, samples, levels, shrink, feature_slot, weights)
         rid = C.c_int64()
         _check(_lib.mi_server_submit(self._h, C.byref(q), C.byref(rid)), "mi_server_submit")
         return rid.value

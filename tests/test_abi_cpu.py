@@ -52,7 +52,8 @@ def test_default_edges_equal_oracle(vox, nb):
 
 @pytest.mark.parametrize("bad", [
     dict(dims=(0, 4, 4)), dict(dims=(65536, 65536, 2)), dict(voxel=0.0), dict(voxel=float("nan")),
-    dict(features=0), dict(features=4), dict(nb_count=1), dict(nb_count=65),
+    dict(features=0), dict(features=8), dict(features=7), dict(features=4, nb_count=10, nb_zvar=10),
+    dict(features=4, nb_zvar=1), dict(nb_count=1), dict(nb_count=65),
     dict(features=2, nb_zvar=2), dict(features=2, voxel=0.005),
     dict(count_edges=[0, 1, 2]), dict(count_edges=[3, 2, 5]),
     dict(origin=(float("inf"), 0, 0)),
@@ -63,6 +64,21 @@ def test_grid_validation(bad):
     with pytest.raises(mi.MIError) as e:
         mi.Grid(**kw)
     assert e.value.status == mi.MI_E_INVALID
+
+
+@pytest.mark.parametrize("features,nbc,nbz,slots", [
+    (4, 8, 9, [(4, 57)]), (5, 8, 2, [(1, 8), (4, 8)]), (6, 2, 16, [(2, 16), (4, 16)]),
+    (3, 16, 32, [(1, 16), (2, 32)])])
+def test_joint_feature_slots(features, nbc, nbz, slots):
+    """Slots follow count, z-variance, joint; the joint feature has
+    1 + (nbc - 1)(nbz - 1) bins; both sides agree on the slots and edges."""
+    g = mi.Grid((0, 0, 0), (4, 4, 4), 1.0, features=features, nb_count=nbc, nb_zvar=nbz)
+    og = O.Grid((0, 0, 0), (4, 4, 4), 1.0, features=features, nb_count=nbc, nb_zvar=nbz)
+    assert g.feature_list == slots == og.feature_list
+    ce, ze = g.edges()
+    assert np.array_equal(ce, og.count_edges[:nbc - 1])
+    if nbz >= 3:
+        assert np.array_equal(ze, og.zvar_edges[:nbz - 2])
 
 
 def test_status_strings():
