@@ -30,6 +30,8 @@ Other workloads (same JSON line, their own config):
            the given rates, served by the continuous-batching loop; reports
            throughput and p50/p99 latency per rate against one request at a
            time (batched per request, and the plain per-pose path).
+--features joint|weighted (c2f workload) runs the same search on the joint count x
+z-variance feature, or on both features weighted equally.
 --calibrate-copy runs a plain 1 GiB device copy, the reference kernel that
 scales the HBM byte counters of a profile.
 
@@ -71,6 +73,9 @@ def _args():
     ap.add_argument("--workload", choices=("c2f", "batched", "uneven", "serving", "accuracy",
                                            "surface"), default="c2f")
     ap.add_argument("--seeds", type=int, default=3)
+    ap.add_argument("--features", choices=("count+zvar", "joint", "weighted"), default="count+zvar",
+                    help="c2f workload: the features and objective (default: both features, "
+                         "search on MI-VARZ)")
     ap.add_argument("--pairs", type=int, default=64)
     ap.add_argument("--rates", default="50,200,800")
     ap.add_argument("--requests", type=int, default=150)
@@ -143,8 +148,16 @@ def main():
     torch.cuda.set_device(0)
     pair = synth.urban_pair()
     c2f = synth.urban_c2f_params()
-    grid = mi.Grid(pair.origin, pair.dims, pair.voxel, features=mi.FEAT_COUNT | mi.FEAT_ZVAR,
-                   nb_count=32, nb_zvar=32)
+    # features and search objective: the configured pair of features with the search on
+    # MI-VARZ, the joint feature (8 x 8 part bins, 50 values), or both features weighted equally
+    fkw = dict(features=mi.FEAT_COUNT | mi.FEAT_ZVAR, nb_count=32, nb_zvar=32)
+    slot, weights, fdesc = 1, None, "count + z-variance 32 bins"
+    if a.features == "joint":
+        fkw = dict(features=mi.FEAT_JOINT, nb_count=8, nb_zvar=8)
+        slot, fdesc = 0, "joint count x z-variance feature (8 x 8 part bins, 50 values)"
+    elif a.features == "weighted":
+        weights, fdesc = (0.5, 0.5), "count + z-variance 32 bins, search on 0.5 MI-N + 0.5 MI-VARZ"
+    grid = mi.Grid(pair.origin, pair.dims, pair.voxel, **fkw)
     A = torch.from_numpy(pair.A).cuda()
     B = torch.from_numpy(pair.B).cuda()
     n_b = B.shape[1]
@@ -156,7 +169,7 @@ def main():
     def step():
         ref = mi.Ref(grid, A)
         pose, best = mi.align_coarse_to_fine(ref, B, init, c2f["half"], c2f["samples"], levels,
-                                             c2f["shrink"], feature_slot=1)
+                                             c2f["shrink"], feature_slot=slot, weights=weights)
         return pose, best
 
     for _ in range(a.warmup):
@@ -208,8 +221,7 @@ def main():
     cpu = None
     if not a.no_cpu_baseline:
         import oracle as O
-        og = O.Grid(pair.origin, pair.dims, pair.voxel, features=O.FEAT_COUNT | O.FEAT_ZVAR,
-                    nb_count=32, nb_zvar=32)
+        og = O.Grid(pair.origin, pair.dims, pair.voxel, **fkw)
         P0 = synth.level_poses(init, c2f["half"], c2f["samples"])
         rng = np.random.default_rng(2)
         Ps = P0[np.sort(rng.choice(len(P0), a.cpu_sample, replace=False))]
@@ -236,7 +248,7 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": "urban scan pair, 6-DOF coarse-to-fine: 2 x ~115k-point 64-ring "
-                               "scans, 0.5 m voxels 320x320x20, count + z-variance 32 bins, "
+                               f"scans, 0.5 m voxels 320x320x20, {fdesc}, "
                                "3 levels x 5^6 poses",
                    "evals_per_step": evals_per_step, "n_b": int(n_b), "n_a": int(A.shape[1])},
         "gpoint_transforms_per_s": gpts,

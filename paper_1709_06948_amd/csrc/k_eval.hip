@@ -433,7 +433,7 @@ __global__ void __launch_bounds__(1024) k_eval(const PairDev *__restrict__ pairs
                   if (tot) {
                     uint32_t base = 0;
                     if (lane == 0) base = atomicAdd(&occn[p], tot);
-                    base = __shfl(base, 0, 64);
+                    base = __builtin_amdgcn_readfirstlane(base);  // every lane is active here
   #pragma unroll
                     for (int i = 0; i < 4; ++i) {
                       if (fresh[i]) {
@@ -472,7 +472,8 @@ __global__ void __launch_bounds__(1024) k_eval(const PairDev *__restrict__ pairs
                            (uint32_t)(iy - Y0) < (uint32_t)(Y1 - Y0) && (uint32_t)iz < (uint32_t)nz;
                   key[i] = ((uint32_t)iz << (kxb + kyb)) | ((uint32_t)(iy - SY0) << kxb) |
                            (uint32_t)ix;
-                  q[i] = ZVAR ? (uint32_t)floor((uz - fz) * kQScale) : 0u;
+                  // uz - fz is in [0, 1), so truncation is the floor
+                  q[i] = ZVAR ? (uint32_t)((uz - fz) * kQScale) : 0u;
                   if (NEAR && inb[i] && ix >= alo0 && ix <= ahi0 && iy >= alo1 && iy <= ahi1 &&
                       iz >= alo2 && iz <= ahi2) {
                     double d = 1.0;
@@ -597,16 +598,15 @@ __global__ void __launch_bounds__(1024) k_eval(const PairDev *__restrict__ pairs
                   const int64_t lin = ((int64_t)iz * ny + iy) * nx + ix;
                   // count bins: O(1) with the default edges 1, 2, ..., nb - 1; the
                   // joint feature numbers its (count, z-variance) bin pairs
-                  auto bin_of = [&](uint32_t kind) -> int {
-                    int bc = 0, bz = 0;
-                    if (kind != MI_FEAT_ZVAR)
-                      bc = count_default ? (int)min(n, (uint32_t)(nbc - 1))
+                  auto count_bin = [&]() -> int {
+                    return count_default ? (int)min(n, (uint32_t)(nbc - 1))
                                          : bin_count_dev(n, nbc, cedge);
-                    if (ZVAR && kind != MI_FEAT_COUNT)
-                      bz = bin_zvar_nodiv(n, s1, s2, nbz, zedged, zedge);
-                    if (kind == MI_FEAT_COUNT) return bc;
+                  };
+                  auto bin_of = [&](uint32_t kind) -> int {
+                    if (kind == MI_FEAT_COUNT || !ZVAR) return count_bin();
+                    const int bz = bin_zvar_nodiv(n, s1, s2, nbz, zedged, zedge);
                     if (kind == MI_FEAT_ZVAR) return bz;
-                    return joint_value(bc, bz, nbz);
+                    return joint_value(count_bin(), bz, nbz);
                   };
                   {
                     const int a = ldg(binA0 + lin);
