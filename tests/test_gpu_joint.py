@@ -131,3 +131,43 @@ def test_batch_mixing_feature_sets(M):
     sb = M.eval_poses(M.Ref(gb, q.A), q.B, Pb)
     torch.cuda.synchronize()
     assert torch.equal(ia.mi, sa["mi"]) and torch.equal(ib.mi, sb["mi"])
+
+
+def test_joint_feature_at_64_bins(M):
+    """The largest joint feature, (8 - 1) * (10 - 1) + 1 = 64 values, beside
+    the count feature."""
+    p = synth.tiny_pair(seed=synth.seed_for(1, 3))
+    kw = dict(origin=p.origin, dims=p.dims, voxel=p.voxel, features=M.FEAT_COUNT | M.FEAT_JOINT,
+              nb_count=8, nb_zvar=10)
+    assert M.Grid(**kw).feature_list == [(M.FEAT_COUNT, 8), (M.FEAT_JOINT, 64)]
+    rng = np.random.default_rng(4)
+    P = rng.uniform(-1, 1, (40, 6)) * [2, 2, 0.2, 0.03, 0.03, 0.15]
+    _both_paths(M, O.Grid(**kw), M.Grid(**kw), p.A, p.B, P, "joint64")
+
+
+def test_weighted_single_feature_and_bad_objectives(M):
+    p = synth.tiny_pair()
+    g = M.Grid(p.origin, p.dims, p.voxel, features=M.FEAT_ZVAR, nb_zvar=16)
+    ref = M.Ref(g, p.A)
+    half, samples = [1.0, 1.0, 0.1, 0.02, 0.02, 0.1], [3, 3, 1, 1, 1, 3]
+    a = M.align_coarse_to_fine(ref, p.B, np.zeros(6), half, samples, 2, 3.0, weights=(2.0, 9.0))
+    b = M.align_coarse_to_fine(ref, p.B, np.zeros(6), half, samples, 2, 3.0, feature_slot=0)
+    # one slot: the objective is w0 * MI_0 (w1 is ignored), doubled exactly
+    assert np.array_equal(a[0], b[0]) and a[1] == 2.0 * b[1]
+    for kw in (dict(weights=(float("nan"), 1.0)), dict(feature_slot=1), dict(feature_slot=-2)):
+        with pytest.raises(M.MIError) as e:
+            M.align_coarse_to_fine(ref, p.B, np.zeros(6), half, samples, 2, 3.0, **kw)
+        assert e.value.status == M.MI_E_INVALID
+    with pytest.raises(M.MIError):
+        M.align_nelder_mead(ref, p.B, np.zeros(6), [1, 1, 0.1, 0.03, 0.03, 0.2], 10, 1e-9, 1e-4,
+                            weights=(1.0, float("inf")))
+
+
+def test_joint_feature_size_limit(M):
+    kw = dict(origin=(0.0, 0.0, 0.0), dims=(4, 4, 4), voxel=1.0, features=M.FEAT_JOINT,
+              nb_count=4, nb_zvar=4)
+    ref = M.Ref(M.Grid(**kw), np.zeros((3, 10), np.float32))
+    B = torch.zeros((3, 1 << 20), dtype=torch.float32, device="cuda")
+    with pytest.raises(M.MIError) as e:
+        M.eval_poses(ref, B, np.zeros((1, 6)))
+    assert e.value.status == M.MI_E_UNSUPPORTED
