@@ -1919,12 +1919,16 @@ extern "C" mi_status mi_server_submit(mi_server *s, const mi_request *q, int64_t
   std::unique_ptr<Request> r(new (std::nothrow) Request());
   if (!r) return fail(MI_E_INVALID, "out of host memory");
   r->gd = q->grid;
+  // the request keeps its own copy of the edges (at most as many as a valid
+  // grid reads; mi_grid_create rejects larger bin counts)
   if (q->grid.count_edges && q->grid.nbins_count > 1) {
-    r->ce.assign(q->grid.count_edges, q->grid.count_edges + (q->grid.nbins_count - 1));
+    const int ne = std::min(q->grid.nbins_count, kMaxBins) - 1;
+    r->ce.assign(q->grid.count_edges, q->grid.count_edges + ne);
     r->gd.count_edges = r->ce.data();
   }
   if (q->grid.zvar_edges && q->grid.nbins_zvar > 2) {
-    r->ze.assign(q->grid.zvar_edges, q->grid.zvar_edges + (q->grid.nbins_zvar - 2));
+    const int ne = std::min(q->grid.nbins_zvar, kMaxBins) - 2;
+    r->ze.assign(q->grid.zvar_edges, q->grid.zvar_edges + ne);
     r->gd.zvar_edges = r->ze.data();
   }
   mi_status st = mi_grid_create(&r->gd, &r->g);

@@ -7,7 +7,10 @@ there is no CPU fallback.
 """
 from __future__ import annotations
 
+import contextlib
 import ctypes as C
+import functools
+import inspect
 import os
 
 import numpy as np
@@ -181,6 +184,35 @@ def _stream(stream=None):
     return C.c_void_p(s.cuda_stream)
 
 
+def _on(stream):
+    """Make `stream` current for torch's allocations and copies, so that they
+    are ordered with the library calls issued on it and the caching allocator
+    reuses their memory only after that stream's work."""
+    return torch.cuda.stream(stream) if stream is not None else contextlib.nullcontext()
+
+
+def _stream_ordered(fn):
+    """Run a wrapper whose allocations and copies feed one library call under
+    _on(its `stream` argument)."""
+    sig = inspect.signature(fn)
+
+    @functools.wraps(fn)
+    def run(*args, **kw):
+        with _on(sig.bind(*args, **kw).arguments.get("stream")):
+            return fn(*args, **kw)
+    return run
+
+
+def _used_on(stream, *tensors):
+    """Tensors made on another stream and used by work on `stream`: tell the
+    caching allocator not to reuse them before that work ends."""
+    if stream is None or stream == torch.cuda.current_stream():
+        return
+    for t in tensors:
+        if t is not None:
+            t.record_stream(stream)
+
+
 def _dev_points(xyz) -> torch.Tensor:
     if not isinstance(xyz, torch.Tensor):
         xyz = torch.from_numpy(np.ascontiguousarray(xyz, np.float32))
@@ -302,15 +334,17 @@ class Ref:
 
     def __init__(self, grid: Grid, xyz_a, stream=None):
         self.grid = grid
-        self.xyz_a = _dev_points(xyz_a)
-        n = self.xyz_a.shape[1]
-        pers = C.c_size_t()
-        nbytes = _lib.mi_features_ref_workspace(grid._h, n, C.byref(pers))
-        self.ws = _workspace(nbytes)
-        self.persistent_bytes = pers.value
-        h = C.c_void_p()
-        _check(_lib.mi_features_ref(grid._h, _dptr(self.xyz_a), n, _dptr(self.ws), self.ws.numel(),
-                                    _stream(stream), C.byref(h)), "mi_features_ref")
+        with _on(stream):
+            self.xyz_a = _dev_points(xyz_a)
+            n = self.xyz_a.shape[1]
+            pers = C.c_size_t()
+            nbytes = _lib.mi_features_ref_workspace(grid._h, n, C.byref(pers))
+            self.ws = _workspace(nbytes)
+            self.persistent_bytes = pers.value
+            h = C.c_void_p()
+            _check(_lib.mi_features_ref(grid._h, _dptr(self.xyz_a), n, _dptr(self.ws),
+                                        self.ws.numel(), _stream(stream), C.byref(h)),
+                   "mi_features_ref")
         self._h = h
 
     def __del__(self):
@@ -364,6 +398,7 @@ def stats_to_numpy(stats_raw: torch.Tensor, K: int) -> np.ndarray:
     return stats_raw[:K * 64].cpu().numpy().view(STATS_DTYPE)
 
 
+@_stream_ordered
 def eval_poses(ref: Ref, xyz_b, poses, flags=0, want_hist=False, want_stats=False,
                want_argmax=True, stream=None, frame_budget=0):
     """mi_eval_poses: MI per feature of every pose (Eqs. 1-5)."""
@@ -383,6 +418,7 @@ def eval_poses(ref: Ref, xyz_b, poses, flags=0, want_hist=False, want_stats=Fals
     return out
 
 
+@_stream_ordered
 def eval_poses_plain(ref: Ref, xyz_b, poses, flags=0, want_hist=False, want_stats=False,
                      want_argmax=True, stream=None):
     """mi_eval_poses_plain: the per-pose stage sequence (same results)."""
@@ -405,6 +441,7 @@ class Plan:
     """mi_plan: pose tables uploaded once; execute() only launches kernels
     (capturable in a HIP graph)."""
 
+    @_stream_ordered
     def __init__(self, ref: Ref, n_b: int, poses, flags=0, stream=None, frame_budget=0):
         self.ref = ref
         P = _poses(poses)
@@ -422,6 +459,7 @@ class Plan:
 
     def execute(self, xyz_b: torch.Tensor, mi: torch.Tensor, argmax=None, hist=None, stats=None,
                 stream=None):
+        _used_on(stream, self.ws)
         _check(_lib.mi_plan_execute(self._h, _dptr(xyz_b), _dptr(mi), _dptr(argmax), _dptr(hist),
                                     _dptr(stats), _stream(stream)), "mi_plan_execute")
 
@@ -464,6 +502,7 @@ class Batch:
     """mi_batch_*: the poses of many scan pairs in one schedule; execute()
     only launches kernels (capturable in a HIP graph)."""
 
+    @_stream_ordered
     def __init__(self, items, flags=0, stream=None, frame_budget=0):
         self.items = list(items)
         arr = _items_array(self.items)
@@ -477,6 +516,9 @@ class Batch:
         self._h = h
 
     def execute(self, stream=None):
+        _used_on(stream, self.ws, *[t for it in self.items
+                                    for t in (it.xyz_b, it.mi, it.argmax, it.hist_raw,
+                                              it.stats_raw)])
         _check(_lib.mi_batch_execute(self._h, _stream(stream)), "mi_batch_execute")
 
     def __del__(self):
@@ -485,6 +527,7 @@ class Batch:
             self._h = None
 
 
+@_stream_ordered
 def eval_batch(items, flags=0, stream=None):
     """mi_eval_batch: create, execute and release a batch in one call."""
     items = list(items)
@@ -498,6 +541,7 @@ def eval_batch(items, flags=0, stream=None):
     return ws
 
 
+@_stream_ordered
 def autotune(items, flags=0, max_poses=4096, stream=None) -> dict:
     """mi_autotune: time candidate tunings on a sample of the workload and make
     the fastest current.  Returns the chosen tuning and the timings."""
@@ -524,6 +568,7 @@ def _objective(d, feature_slot, weights):
         d.weight[:] = [float(v) for v in weights]
 
 
+@_stream_ordered
 def align_coarse_to_fine(ref: Ref, xyz_b, init, half_range, samples, levels, shrink,
                          feature_slot=0, stream=None, weights=None):
     """mi_align_coarse_to_fine: shrinking grid search for Eq. 1 from T_o, on
@@ -545,6 +590,7 @@ def align_coarse_to_fine(ref: Ref, xyz_b, init, half_range, samples, levels, shr
     return out, float(best[0])
 
 
+@_stream_ordered
 def align_nelder_mead(ref: Ref, xyz_b, starts, step, max_iter, ftol, xtol, feature_slot=0,
                       stream=None, weights=None):
     """mi_align_nelder_mead: simplex search for Eq. 1 (Sec. III-B) from one or
@@ -594,8 +640,9 @@ class Server:
     device arena (torch-allocated here) and one stream."""
 
     def __init__(self, arena_bytes: int, max_active: int, step_bytes: int = 0, stream=None):
-        self.arena = _workspace(arena_bytes)
         self.stream = stream if stream is not None else torch.cuda.current_stream()
+        with _on(self.stream):
+            self.arena = _workspace(arena_bytes)
         d = _ServerDesc(_dptr(self.arena).value, self.arena.numel(), int(step_bytes),
                         int(max_active))
         h = C.c_void_p()
