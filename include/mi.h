@@ -328,9 +328,9 @@ mi_status mi_autotune(const mi_work_item *items, int64_t n_items, uint32_t flags
  * per level.  ws from mi_align_workspace. */
 typedef struct mi_c2f_desc {
   double half_range[6];
-  int32_t samples[6];
-  int32_t levels;
-  double shrink;
+  int32_t samples[6];           /* each 1..1024, product < 2^31 */
+  int32_t levels;               /* >= 1 */
+  double shrink;                /* > 0 */
   int32_t feature_slot;         /* 0 .. slots-1, or MI_SLOT_WEIGHTED */
   double weight[2];             /* per slot, when feature_slot == MI_SLOT_WEIGHTED */
 } mi_c2f_desc;

@@ -16,6 +16,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <memory>
+#include <new>
 #include <mutex>
 #include <string>
 #include <unordered_map>
@@ -44,6 +45,29 @@ static mi_status fail(mi_status s, const char *fmt, ...) {
 
 static mi_status dev_fail(hipError_t e, const char *where) {
   return fail(MI_E_DEVICE, "%s: %s", where, hipGetErrorString(e));
+}
+
+// Every entry point runs its body under guarded(): a host allocation that
+// fails (std::bad_alloc from a container) becomes a status, and no exception
+// crosses the C ABI.  A size query reports 0, as for bad arguments.
+template <class F>
+static mi_status guarded(const char *where, F &&body) noexcept {
+  try {
+    return body();
+  } catch (const std::bad_alloc &) {
+    return fail(MI_E_INVALID, "%s: out of host memory", where);
+  } catch (...) {
+    return fail(MI_E_INVALID, "%s: unexpected host error", where);
+  }
+}
+
+template <class F>
+static size_t guarded_size(F &&body) noexcept {
+  try {
+    return body();
+  } catch (...) {
+    return 0;
+  }
 }
 
 #define HIP_TRY(expr, where)                   \
@@ -167,6 +191,7 @@ int max_lds_per_block() {
 }  // namespace
 
 extern "C" mi_status mi_tuning_set(const mi_tuning *t) {
+  return guarded("mi_tuning_set", [&]() -> mi_status {
   if (!t) return fail(MI_E_INVALID, "mi_tuning_set: NULL");
   if (t->waves < 1 || t->waves > 16) return fail(MI_E_INVALID, "waves must be 1..16");
   if (t->hash_bytes < 1024 || t->hash_bytes > 160 * 1024)
@@ -181,9 +206,11 @@ extern "C" mi_status mi_tuning_set(const mi_tuning *t) {
   g_tuning.stripe_rows = t->stripe_rows;
   g_tuning.wgs_per_cu = t->wgs_per_cu;
   return MI_OK;
+  });
 }
 
 extern "C" mi_status mi_tuning_get(mi_tuning *t) {
+  return guarded("mi_tuning_get", [&]() -> mi_status {
   if (!t) return fail(MI_E_INVALID, "mi_tuning_get: NULL");
   std::lock_guard<std::mutex> lk(g_tuning_mu);
   t->waves = g_tuning.waves;
@@ -192,6 +219,7 @@ extern "C" mi_status mi_tuning_get(mi_tuning *t) {
   t->stripe_rows = g_tuning.stripe_rows;
   t->wgs_per_cu = g_tuning.wgs_per_cu;
   return MI_OK;
+  });
 }
 
 static Tuning tuning_now() {
@@ -253,6 +281,7 @@ void prof_end(hipStream_t s, hipEvent_t a, int stage, int64_t poses, int64_t poi
 }  // namespace
 
 extern "C" mi_status mi_profile_enable(int32_t on) {
+  return guarded("mi_profile_enable", [&]() -> mi_status {
   std::lock_guard<std::mutex> lk(g_prof_mu);
   for (auto &sp : g_spans) {
     hipEventSynchronize(sp.b);
@@ -263,9 +292,11 @@ extern "C" mi_status mi_profile_enable(int32_t on) {
   for (auto &c : g_prof_counts) c = 0;
   g_prof_on = on != 0;
   return MI_OK;
+  });
 }
 
 extern "C" mi_status mi_profile_read(mi_profile *out) {
+  return guarded("mi_profile_read", [&]() -> mi_status {
   if (!out) return fail(MI_E_INVALID, "mi_profile_read: NULL");
   std::lock_guard<std::mutex> lk(g_prof_mu);
   double ms[3] = {0, 0, 0};
@@ -288,6 +319,7 @@ extern "C" mi_status mi_profile_read(mi_profile *out) {
   out->point_poses = g_prof_counts[4];
   for (auto &c : g_prof_counts) c = 0;
   return MI_OK;
+  });
 }
 
 // -------------------------------------------------------------------- grid
@@ -313,6 +345,7 @@ static int default_zvar_edges(double voxel, int nb, uint64_t *E) {
 }
 
 extern "C" mi_status mi_grid_create(const mi_grid_desc *d, mi_grid **out) {
+  return guarded("mi_grid_create", [&]() -> mi_status {
   if (!d || !out) return fail(MI_E_INVALID, "mi_grid_create: NULL argument");
   *out = nullptr;
   GridInfo gi;
@@ -386,17 +419,20 @@ extern "C" mi_status mi_grid_create(const mi_grid_desc *d, mi_grid **out) {
   g->gi = gi;
   *out = g;
   return MI_OK;
+  });
 }
 
 extern "C" void mi_grid_destroy(mi_grid *g) { free(g); }
 
 extern "C" mi_status mi_grid_edges(const mi_grid *g, uint32_t *ce, uint64_t *ze) {
+  return guarded("mi_grid_edges", [&]() -> mi_status {
   if (!g) return fail(MI_E_INVALID, "mi_grid_edges: NULL grid");
   if (ce)
     for (int j = 0; j + 1 < g->gi.nbc; ++j) ce[j] = g->gi.count_edges[j];
   if (ze)
     for (int j = 0; j + 2 < g->gi.nbz; ++j) ze[j] = g->gi.zvar_edges[j];
   return MI_OK;
+  });
 }
 
 // ---------------------------------------------------------------- pose
@@ -418,6 +454,7 @@ static void pose_rotation(const double eta[6], double R[9]) {
 }
 
 extern "C" mi_status mi_pose_to_matrix(const double eta[6], double rt[12]) {
+  return guarded("mi_pose_to_matrix", [&]() -> mi_status {
   if (!eta || !rt) return fail(MI_E_INVALID, "mi_pose_to_matrix: NULL");
   double R[9];
   pose_rotation(eta, R);
@@ -426,6 +463,7 @@ extern "C" mi_status mi_pose_to_matrix(const double eta[6], double rt[12]) {
     rt[4 * r + 3] = eta[r];
   }
   return MI_OK;
+  });
 }
 
 // -------------------------------------------------------------- reference
@@ -461,15 +499,18 @@ static size_t ref_layout(const GridInfo &gi, Carver &c, RefDev *rd) {
 }
 
 extern "C" size_t mi_features_ref_workspace(const mi_grid *g, int64_t, size_t *persistent_bytes) {
+  return guarded_size([&]() -> size_t {
   if (!g) return 0;
   Carver c(nullptr, 0);
   const size_t pers = ref_layout(g->gi, c, nullptr);
   if (persistent_bytes) *persistent_bytes = pers;
   return c.used() + 256;
+  });
 }
 
 extern "C" mi_status mi_features_ref(const mi_grid *g, const float *xyz_a, int64_t n_a, void *ws,
                                      size_t ws_bytes, void *stream, mi_ref **out) {
+  return guarded("mi_features_ref", [&]() -> mi_status {
   if (!g || !out) return fail(MI_E_INVALID, "mi_features_ref: NULL argument");
   *out = nullptr;
   if (n_a < 0 || (n_a > 0 && !xyz_a)) return fail(MI_E_INVALID, "bad scan A");
@@ -498,19 +539,23 @@ extern "C" mi_status mi_features_ref(const mi_grid *g, const float *xyz_a, int64
   r->n_a = n_a;
   *out = r;
   return MI_OK;
+  });
 }
 
 extern "C" void mi_ref_destroy(mi_ref *r) { free(r); }
 
 extern "C" mi_status mi_ref_bins(const mi_ref *r, int32_t f, const uint8_t **dev_bins) {
+  return guarded("mi_ref_bins", [&]() -> mi_status {
   if (!r || !dev_bins || f < 0 || f >= r->g->gi.nf)
     return fail(MI_E_INVALID, "mi_ref_bins: bad argument");
   *dev_bins = r->rd.bins[f];
   return MI_OK;
+  });
 }
 
 extern "C" mi_status mi_ref_summary(const mi_ref *r, void *stream, int32_t box[6],
                                     int64_t counters[4]) {
+  return guarded("mi_ref_summary", [&]() -> mi_status {
   if (!r || !box || !counters) return fail(MI_E_INVALID, "mi_ref_summary: NULL");
   HIP_TRY(hipStreamSynchronize((hipStream_t)stream), "ref summary sync");
   HIP_TRY(hipMemcpy(box, r->rd.abox, 6 * sizeof(int32_t), hipMemcpyDeviceToHost), "ref box");
@@ -518,6 +563,7 @@ extern "C" mi_status mi_ref_summary(const mi_ref *r, void *stream, int32_t box[6
   HIP_TRY(hipMemcpy(c, r->rd.counters, sizeof c, hipMemcpyDeviceToHost), "ref counters");
   for (int i = 0; i < 4; ++i) counters[i] = (int64_t)c[i];
   return MI_OK;
+  });
 }
 
 // ------------------------------------------------------------------ plans
@@ -1199,14 +1245,17 @@ mi_status run_plan(mi_plan *p, hipStream_t s) {
 
 extern "C" size_t mi_batch_workspace(const mi_work_item *items, int64_t n_items, uint32_t flags,
                                      size_t budget) {
+  return guarded_size([&]() -> size_t {
   BatchTables B;
   if (prepare_batch(items, n_items, flags, B) != MI_OK) return 0;
   return batch_bytes(B, items, n_items, budget);
+  });
 }
 
 extern "C" mi_status mi_batch_create(const mi_work_item *items, int64_t n_items, uint32_t flags,
                                      void *ws, size_t ws_bytes, size_t budget, void *stream,
                                      mi_plan **out) {
+  return guarded("mi_batch_create", [&]() -> mi_status {
   for (int64_t i = 0; i < n_items && items; ++i) {
     if (items[i].K > 0 && !items[i].mi_out)
       return fail(MI_E_INVALID, "work item %lld: mi_out is NULL", (long long)i);
@@ -1214,23 +1263,28 @@ extern "C" mi_status mi_batch_create(const mi_work_item *items, int64_t n_items,
       return fail(MI_E_INVALID, "work item %lld: xyz_b is NULL", (long long)i);
   }
   return create_plan(items, n_items, flags, ws, ws_bytes, budget, stream, false, out);
+  });
 }
 
 extern "C" mi_status mi_batch_execute(mi_plan *p, void *stream) {
+  return guarded("mi_batch_execute", [&]() -> mi_status {
   if (!p) return fail(MI_E_INVALID, "mi_batch_execute: NULL plan");
   if (p->bind_per_execution)
     return fail(MI_E_INVALID, "plan from mi_plan_create: execute it with mi_plan_execute");
   return run_plan(p, (hipStream_t)stream);
+  });
 }
 
 extern "C" mi_status mi_eval_batch(const mi_work_item *items, int64_t n_items, uint32_t flags,
                                    void *ws, size_t ws_bytes, void *stream) {
+  return guarded("mi_eval_batch", [&]() -> mi_status {
   mi_plan *p = nullptr;
   mi_status st = mi_batch_create(items, n_items, flags, ws, ws_bytes, 0, stream, &p);
   if (st != MI_OK) return st;
   st = run_plan(p, (hipStream_t)stream);
   mi_plan_destroy(p);
   return st;
+  });
 }
 
 // ----------------------------------------------------------------- autotune
@@ -1272,17 +1326,20 @@ size_t sample_out_bytes(const Sample &S) {
 
 extern "C" size_t mi_autotune_workspace(const mi_work_item *items, int64_t n_items, uint32_t flags,
                                         int64_t max_poses) {
+  return guarded_size([&]() -> size_t {
   if (n_items <= 0 || !items) return 0;
   Sample S;
   make_sample(items, n_items, max_poses, S);
   BatchTables B;
   if (prepare_batch(S.items.data(), n_items, flags, B) != MI_OK) return 0;
   return sample_out_bytes(S) + batch_bytes(B, S.items.data(), n_items, 0) + 512;
+  });
 }
 
 extern "C" mi_status mi_autotune(const mi_work_item *items, int64_t n_items, uint32_t flags,
                                  int64_t max_poses, void *ws, size_t ws_bytes, void *stream,
                                  mi_autotune_report *out) {
+  return guarded("mi_autotune", [&]() -> mi_status {
   if (!items || n_items <= 0 || !out) return fail(MI_E_INVALID, "mi_autotune: bad arguments");
   if (!ws || ((uintptr_t)ws & 255)) return fail(MI_E_WORKSPACE, "workspace NULL or not 256-aligned");
   hipStream_t s = (hipStream_t)stream;
@@ -1370,31 +1427,37 @@ extern "C" mi_status mi_autotune(const mi_work_item *items, int64_t n_items, uin
   out->start_ms = start_ms;
   out->tried = tried;
   return MI_OK;
+  });
 }
 
 extern "C" size_t mi_eval_poses_workspace(const mi_ref *r, int64_t n_b, const double *poses,
                                           int64_t K, uint32_t flags, size_t budget) {
+  return guarded_size([&]() -> size_t {
   if (!r) return 0;
   mi_work_item w;
   memset(&w, 0, sizeof w);
   w.ref = r; w.n_b = n_b; w.poses = poses; w.K = K;
   return mi_batch_workspace(&w, 1, flags, budget);
+  });
 }
 
 extern "C" mi_status mi_plan_create(const mi_ref *r, int64_t n_b, const double *poses, int64_t K,
                                     uint32_t flags, void *ws, size_t ws_bytes, size_t budget,
                                     void *stream, mi_plan **out) {
+  return guarded("mi_plan_create", [&]() -> mi_status {
   if (!r || !out) return fail(MI_E_INVALID, "mi_plan_create: NULL argument");
   *out = nullptr;
   mi_work_item w;
   memset(&w, 0, sizeof w);
   w.ref = r; w.n_b = n_b; w.poses = poses; w.K = K;
   return create_plan(&w, 1, flags, ws, ws_bytes, budget, stream, true, out);
+  });
 }
 
 extern "C" mi_status mi_plan_execute(mi_plan *p, const float *xyz_b, double *mi_out,
                                      int64_t *argmax_out, uint32_t *hist_out,
                                      mi_pose_stats *stats_out, void *stream) {
+  return guarded("mi_plan_execute", [&]() -> mi_status {
   if (!p) return fail(MI_E_INVALID, "mi_plan_execute: NULL plan");
   if (!p->bind_per_execution) return fail(MI_E_INVALID, "batch plan: execute it with mi_batch_execute");
   PairHost &ph = p->pairs[0];
@@ -1407,6 +1470,7 @@ extern "C" mi_status mi_plan_execute(mi_plan *p, const float *xyz_b, double *mi_
   ph.mi_out = mi_out;
   ph.argmax_out = argmax_out;
   return run_plan(p, s);
+  });
 }
 
 extern "C" void mi_plan_destroy(mi_plan *p) { delete p; }
@@ -1416,12 +1480,14 @@ extern "C" mi_status mi_eval_poses(const mi_ref *r, const float *xyz_b, int64_t 
                                    int64_t *argmax_out, uint32_t *hist_out,
                                    mi_pose_stats *stats_out, void *ws, size_t ws_bytes,
                                    void *stream) {
+  return guarded("mi_eval_poses", [&]() -> mi_status {
   mi_plan *p = nullptr;
   mi_status st = mi_plan_create(r, n_b, poses, K, flags, ws, ws_bytes, 0, stream, &p);
   if (st != MI_OK) return st;
   st = mi_plan_execute(p, xyz_b, mi_out, argmax_out, hist_out, stats_out, stream);
   mi_plan_destroy(p);
   return st;
+  });
 }
 
 // ---------------------------------------------------------------- plain
@@ -1454,10 +1520,12 @@ void plain_layout(const GridInfo &gi, int64_t n_b, int64_t K, Carver &c, PlainLa
 }  // namespace
 
 extern "C" size_t mi_eval_poses_plain_workspace(const mi_ref *r, int64_t n_b, int64_t K) {
+  return guarded_size([&]() -> size_t {
   if (!r || n_b < 0 || K < 0) return 0;
   Carver c(nullptr, 0);
   plain_layout(r->g->gi, n_b, K, c, nullptr);
   return c.used() + 256;
+  });
 }
 
 extern "C" mi_status mi_eval_poses_plain(const mi_ref *r, const float *xyz_b, int64_t n_b,
@@ -1465,6 +1533,7 @@ extern "C" mi_status mi_eval_poses_plain(const mi_ref *r, const float *xyz_b, in
                                          double *mi_out, int64_t *argmax_out, uint32_t *hist_out,
                                          mi_pose_stats *stats_out, void *ws, size_t ws_bytes,
                                          void *stream) {
+  return guarded("mi_eval_poses_plain", [&]() -> mi_status {
   if (!r) return fail(MI_E_INVALID, "mi_eval_poses_plain: NULL ref");
   if (K < 0 || n_b < 0 || (K > 0 && (!poses || !mi_out)) || (n_b > 0 && !xyz_b))
     return fail(MI_E_INVALID, "bad arguments");
@@ -1521,6 +1590,7 @@ extern "C" mi_status mi_eval_poses_plain(const mi_ref *r, const float *xyz_b, in
   if (timed) prof_end(s, a, kStagePlain, K, K * n_b);
   if (argmax_out) HIP_TRY(launch_argmax(mi_out, K, gi.nf, argmax_out, nullptr, s), "argmax");
   return MI_OK;
+  });
 }
 
 // ------------------------------------------------------------ coarse-to-fine
@@ -1547,11 +1617,14 @@ hipError_t objective_row(double *mi, int64_t K, int nf, int32_t slot, const doub
 bool c2f_ok(const mi_c2f_desc *d, int nf) {
   if (!d || d->levels < 1 || !(d->shrink > 0.0) || !std::isfinite(d->shrink)) return false;
   if (!slot_ok(d->feature_slot, d->weight, nf)) return false;
-  for (int a = 0; a < 6; ++a)
+  int64_t K = 1;
+  for (int a = 0; a < 6; ++a) {
     if (d->samples[a] < 1 || d->samples[a] > 1024 || !std::isfinite(d->half_range[a]) ||
         d->half_range[a] < 0.0)
       return false;
-  return true;
+    K *= d->samples[a];
+  }
+  return K < ((int64_t)1 << 31);  // a level is one plan of fewer than 2^31 poses
 }
 
 int64_t c2f_count(const mi_c2f_desc *d) {
@@ -1584,6 +1657,7 @@ void c2f_grid(const double c[6], const double h[6], const int32_t samples[6],
 }  // namespace
 
 extern "C" size_t mi_align_workspace(const mi_ref *r, int64_t n_b, const mi_c2f_desc *d) {
+  return guarded_size([&]() -> size_t {
   if (!r || n_b < 0 || !c2f_ok(d, r->g->gi.nf)) return 0;
   const GridInfo &gi = r->g->gi;
   const int64_t K = c2f_count(d);
@@ -1599,12 +1673,14 @@ extern "C" size_t mi_align_workspace(const mi_ref *r, int64_t n_b, const mi_c2f_
   c.take<double>(((size_t)gi.nf + 1) * (size_t)K);
   c.take<int64_t>(2 * 8);
   return c.used() + single_plan_bytes(K, (int32_t)F, ncols, n_b) + 512;
+  });
 }
 
 extern "C" mi_status mi_align_coarse_to_fine(const mi_ref *r, const float *xyz_b, int64_t n_b,
                                              const double init[6], const mi_c2f_desc *d,
                                              double pose_out[6], double *mi_best, void *ws,
                                              size_t ws_bytes, void *stream) {
+  return guarded("mi_align_coarse_to_fine", [&]() -> mi_status {
   if (!r || !init || !pose_out) return fail(MI_E_INVALID, "mi_align_coarse_to_fine: NULL");
   const GridInfo &gi = r->g->gi;
   if (!c2f_ok(d, gi.nf)) return fail(MI_E_INVALID, "bad coarse-to-fine description");
@@ -1649,6 +1725,7 @@ extern "C" mi_status mi_align_coarse_to_fine(const mi_ref *r, const float *xyz_b
   for (int a = 0; a < 6; ++a) pose_out[a] = ctr[a];
   if (mi_best) *mi_best = best;
   return MI_OK;
+  });
 }
 
 // ---------------------------------------------------------------- serving
@@ -1886,6 +1963,7 @@ mi_status run_level(mi_server *s, Request *const *rs, size_t n,
 }  // namespace
 
 extern "C" mi_status mi_server_create(const mi_server_desc *d, void *stream, mi_server **out) {
+  return guarded("mi_server_create", [&]() -> mi_status {
   if (!d || !out) return fail(MI_E_INVALID, "mi_server_create: NULL argument");
   *out = nullptr;
   if (!d->arena || ((uintptr_t)d->arena & 255)) return fail(MI_E_WORKSPACE, "arena NULL or not 256-aligned");
@@ -1907,9 +1985,11 @@ extern "C" mi_status mi_server_create(const mi_server_desc *d, void *stream, mi_
           "pinned results");
   *out = s.release();
   return MI_OK;
+  });
 }
 
 extern "C" mi_status mi_server_submit(mi_server *s, const mi_request *q, int64_t *id) {
+  return guarded("mi_server_submit", [&]() -> mi_status {
   if (!s || !q || !id) return fail(MI_E_INVALID, "mi_server_submit: NULL argument");
   *id = 0;
   if (q->n_a < 0 || q->n_b < 0 || (q->n_a > 0 && !q->xyz_a) || (q->n_b > 0 && !q->xyz_b))
@@ -1965,9 +2045,11 @@ extern "C" mi_status mi_server_submit(mi_server *s, const mi_request *q, int64_t
   s->queue.push_back(r.get());
   s->table.emplace(r->id, std::move(r));
   return MI_OK;
+  });
 }
 
 extern "C" mi_status mi_server_step(mi_server *s, int32_t *n_active, int32_t *n_queued) {
+  return guarded("mi_server_step", [&]() -> mi_status {
   if (!s) return fail(MI_E_INVALID, "mi_server_step: NULL server");
   // admission: arrival order, while a slot is free and the data fits
   std::vector<Request *> admitted;
@@ -2028,18 +2110,22 @@ extern "C" mi_status mi_server_step(mi_server *s, int32_t *n_active, int32_t *n_
     if (n_queued) *n_queued = (int32_t)s->queue.size();
   }
   return MI_OK;
+  });
 }
 
 extern "C" mi_status mi_server_poll(mi_server *s, int64_t id, mi_request_state *out) {
+  return guarded("mi_server_poll", [&]() -> mi_status {
   if (!s || !out) return fail(MI_E_INVALID, "mi_server_poll: NULL argument");
   std::lock_guard<std::mutex> lk(s->mu);
   auto it = s->table.find(id);
   if (it == s->table.end()) return fail(MI_E_INVALID, "unknown request %lld", (long long)id);
   *out = it->second->st;
   return MI_OK;
+  });
 }
 
 extern "C" mi_status mi_server_release(mi_server *s, int64_t id) {
+  return guarded("mi_server_release", [&]() -> mi_status {
   if (!s) return fail(MI_E_INVALID, "mi_server_release: NULL server");
   std::lock_guard<std::mutex> lk(s->mu);
   auto it = s->table.find(id);
@@ -2050,6 +2136,7 @@ extern "C" mi_status mi_server_release(mi_server *s, int64_t id) {
   if (it->second->g) mi_grid_destroy(it->second->g);
   s->table.erase(it);
   return MI_OK;
+  });
 }
 
 extern "C" void mi_server_destroy(mi_server *s) {
@@ -2167,6 +2254,7 @@ bool nm_ok(const mi_nm_desc *d, int nf) {
 }  // namespace
 
 extern "C" size_t mi_align_nm_workspace(const mi_ref *r, int64_t n_b, int32_t n_starts) {
+  return guarded_size([&]() -> size_t {
   if (!r || n_b < 0 || n_starts < 1) return 0;
   const int64_t K = 7 * (int64_t)n_starts;
   std::vector<double> P((size_t)K * 6, 0.0);
@@ -2177,6 +2265,7 @@ extern "C" size_t mi_align_nm_workspace(const mi_ref *r, int64_t n_b, int32_t n_
   const size_t b = mi_batch_workspace(&w, 1, MI_EVAL_PER_POSE, 0);
   if (b == 0) return 0;
   return b + al256((size_t)r->g->gi.nf * (size_t)K * sizeof(double)) + 512;
+  });
 }
 
 extern "C" mi_status mi_align_nelder_mead(const mi_ref *r, const float *xyz_b, int64_t n_b,
@@ -2184,6 +2273,7 @@ extern "C" mi_status mi_align_nelder_mead(const mi_ref *r, const float *xyz_b, i
                                           const mi_nm_desc *d, double pose_out[6],
                                           double *mi_best, int32_t *iters_out, void *ws,
                                           size_t ws_bytes, void *stream) {
+  return guarded("mi_align_nelder_mead", [&]() -> mi_status {
   if (!r || !starts || !pose_out || n_starts < 1)
     return fail(MI_E_INVALID, "mi_align_nelder_mead: bad arguments");
   const GridInfo &gi = r->g->gi;
@@ -2268,4 +2358,5 @@ extern "C" mi_status mi_align_nelder_mead(const mi_ref *r, const float *xyz_b, i
   if (iters_out)
     for (int32_t i = 0; i < n_starts; ++i) iters_out[i] = sx[(size_t)i].iters;
   return MI_OK;
+  });
 }
