@@ -2027,10 +2027,13 @@ extern "C" mi_status mi_server_submit(mi_server *s, const mi_request *q, int64_t
   size_t keep = 0;
   r->ref_bytes = mi_features_ref_workspace(r->g, q->n_a, &keep);
   r->ref_keep = al256(keep);
+  // what an empty heap holds (its size is rounded down to 256-byte granules),
+  // so that every accepted request is admitted once the others are done
   const size_t need = req_points_bytes(q->n_a) + req_points_bytes(q->n_b) + al256(r->ref_bytes);
-  if (need > s->arena_bytes - s->step_bytes)
+  const size_t heap_bytes = (s->arena_bytes - s->step_bytes) & ~(size_t)255;
+  if (need > heap_bytes)
     return fail(MI_E_UNSUPPORTED, "request needs %zu bytes of arena, the server has %zu", need,
-                s->arena_bytes - s->step_bytes);
+                heap_bytes);
   if (req_step_bytes(*r) > s->step_bytes)
     return fail(MI_E_UNSUPPORTED, "one search level of the request needs a step region of %zu "
                 "bytes, the server has %zu", req_step_bytes(*r), s->step_bytes);

@@ -106,3 +106,17 @@ def test_identical_points_and_single_pose(M):
               nb_zvar=8)
     _compare(M, kw, A, B, np.zeros((1, 6)), "identical-points",
              flags_extra=(M.EVAL_SHARED_FRAMES, M.EVAL_PER_POSE))
+
+
+def test_coarse_to_fine_level_size_limit(M):
+    """A level of 2^31 or more poses is rejected before any allocation."""
+    kw = dict(origin=(0.0, 0.0, 0.0), dims=(4, 4, 4), voxel=1.0, features=1, nb_count=4)
+    mg = M.Grid(**kw)
+    A = np.random.default_rng(5).uniform(0, 4, (3, 100)).astype(np.float32)
+    ref = M.Ref(mg, A)
+    with pytest.raises(M.MIError) as e:
+        M.align_coarse_to_fine(ref, A, np.zeros(6), [1.0] * 6, [1024, 1024, 1024, 2, 1, 1], 1,
+                               2.0)
+    assert e.value.status == M.MI_E_INVALID
+    pose, best = M.align_coarse_to_fine(ref, A, np.zeros(6), [1.0] * 6, [2, 2, 1, 1, 1, 3], 1, 2.0)
+    assert np.all(np.isfinite(pose)) and np.isfinite(best)
