@@ -82,49 +82,65 @@ __global__ void __launch_bounds__(256) k_frame_count(const FrameDev *__restrict_
   }
 }
 
-// Exclusive scan of the column counts of one frame (one workgroup per frame),
-// in coalesced tiles of 4 columns per thread; off[ncols] = kept points; the
-// cursors start at the offsets.
+// Exclusive scan of the column counts of one frame (one workgroup per frame).
+// A round covers 4 coalesced tiles of 4 columns per thread, all loaded before
+// any is scanned, so a frame of ~10^5 columns waits on memory a handful of
+// times; off[ncols] = kept points; the cursors start at the offsets.
 __global__ void __launch_bounds__(1024) k_frame_scan(const FrameDev *__restrict__ frames) {
+  constexpr int kTiles = 4, kPer = 4;
   const FrameDev &F = frames[blockIdx.x];
   const int64_t ncols = (int64_t)F.ncx * F.ncy;
-  const int T = blockDim.x, tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
-  __shared__ uint32_t wsum[16];
-  __shared__ uint32_t carry_s;
-  if (tid == 0) carry_s = 0u;
-  __syncthreads();
-  for (int64_t t0 = 0; t0 < ncols; t0 += 4 * (int64_t)T) {
-    const int64_t b = t0 + 4 * (int64_t)tid;
-    uint32_t c[4], sum = 0;
+  const int T = blockDim.x, tid = threadIdx.x, lane = tid & 63, wid = tid >> 6, W = T >> 6;
+  // per-wave tile totals, in alternating buffers: one barrier per round
+  // suffices, as a buffer is rewritten only two rounds later
+  __shared__ uint32_t wsum[2][kTiles][16];
+  uint32_t carry = 0u;  // the same in every thread
+  int par = 0;
+  for (int64_t t0 = 0; t0 < ncols; t0 += (int64_t)kTiles * kPer * T) {
+    uint32_t c[kTiles][kPer], inc[kTiles], sum[kTiles];
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      c[j] = b + j < ncols ? F.cur[b + j] : 0u;
-      sum += c[j];
+    for (int r = 0; r < kTiles; ++r) {
+      const int64_t b = t0 + (int64_t)r * kPer * T + kPer * (int64_t)tid;
+#pragma unroll
+      for (int j = 0; j < kPer; ++j) c[r][j] = b + j < ncols ? F.cur[b + j] : 0u;
     }
-    uint32_t inc = sum;
 #pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-      const uint32_t v = __shfl_up(inc, o, 64);
-      if (lane >= o) inc += v;
-    }
-    if (lane == 63) wsum[wid] = inc;
-    __syncthreads();
-    uint32_t wbase = carry_s;
-    for (int w = 0; w < wid; ++w) wbase += wsum[w];
-    uint32_t run = wbase + inc - sum;
+    for (int r = 0; r < kTiles; ++r) {
+      sum[r] = 0u;
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      if (b + j < ncols) {
-        F.off[b + j] = run;
-        F.cur[b + j] = run;
+      for (int j = 0; j < kPer; ++j) sum[r] += c[r][j];
+      inc[r] = sum[r];
+#pragma unroll
+      for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t v = __shfl_up(inc[r], o, 64);
+        if (lane >= o) inc[r] += v;
       }
-      run += c[j];
+      if (lane == 63) wsum[par][r][wid] = inc[r];
     }
     __syncthreads();
-    if (tid == T - 1) carry_s = run;
-    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < kTiles; ++r) {
+      uint32_t wbase = carry, tot = 0u;
+      for (int w = 0; w < W; ++w) {
+        const uint32_t x = wsum[par][r][w];
+        if (w < wid) wbase += x;
+        tot += x;
+      }
+      const int64_t b = t0 + (int64_t)r * kPer * T + kPer * (int64_t)tid;
+      uint32_t run = wbase + inc[r] - sum[r];
+#pragma unroll
+      for (int j = 0; j < kPer; ++j) {
+        if (b + j < ncols) {
+          F.off[b + j] = run;
+          F.cur[b + j] = run;
+        }
+        run += c[r][j];
+      }
+      carry += tot;
+    }
+    par ^= 1;
   }
-  if (tid == 0) F.off[ncols] = carry_s;
+  if (tid == 0) F.off[ncols] = carry;
 }
 
 __global__ void __launch_bounds__(256) k_frame_scatter(const FrameDev *__restrict__ frames) {

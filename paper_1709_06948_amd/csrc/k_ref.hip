@@ -116,9 +116,16 @@ __global__ void __launch_bounds__(256) k_sat_y(uint32_t *S, int nx, int ny, int 
     const int64_t zz = r / (nx + 1), x = r % (nx + 1);
     uint32_t *p = S + a1 * plane + zz * cols + x;
     uint32_t run = 0;
-    for (int yy = 0; yy <= ny; ++yy) {
-      run += p[(int64_t)yy * (nx + 1)];
-      p[(int64_t)yy * (nx + 1)] = run;
+    // eight rows' loads in flight at a time (the sums only chain the adds)
+    for (int y0 = 0; y0 <= ny; y0 += 8) {
+      uint32_t v[8];
+#pragma unroll
+      for (int j = 0; j < 8; ++j) v[j] = y0 + j <= ny ? p[(int64_t)(y0 + j) * (nx + 1)] : 0u;
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        run += v[j];
+        if (y0 + j <= ny) p[(int64_t)(y0 + j) * (nx + 1)] = run;
+      }
     }
   }
 }
