@@ -578,19 +578,53 @@ struct PoseTables {
   int32_t gx = 0, gy = 0, ncx = 1, ncy = 1, zlo = 0, zhi = 0;
 };
 
-struct BitsKey {
-  uint64_t w[9];
-  bool operator==(const BitsKey &o) const { return memcmp(w, o.w, sizeof w) == 0; }
-};
-struct BitsHash {
-  size_t operator()(const BitsKey &k) const {
-    uint64_t h = 1469598103934665603ull;
-    for (int i = 0; i < 9; ++i) {
-      h ^= k.w[i];
-      h *= 1099511628211ull;
+// Open-addressing index from keys of N 64-bit words to int32 values (linear
+// probing, power-of-two capacity kept at most half full).  Plan creation looks
+// up every pose's rotation in it: a search level of 15,625 poses shares 125.
+template <int N>
+class WordIndex {
+ public:
+  WordIndex() { rehash(256); }
+  int32_t find(const uint64_t *k) const {  // the key's value, or -1
+    for (size_t i = slot_of(k);; i = (i + 1) & mask_) {
+      const int32_t v = vals_[i];
+      if (v < 0) return -1;
+      if (memcmp(&keys_[i * N], k, N * sizeof(uint64_t)) == 0) return v;
     }
-    return (size_t)h;
   }
+  void insert(const uint64_t *k, int32_t v) {  // a key not yet present, v >= 0
+    if (2 * (count_ + 1) > vals_.size()) rehash(2 * vals_.size());
+    size_t i = slot_of(k);
+    while (vals_[i] >= 0) i = (i + 1) & mask_;
+    memcpy(&keys_[i * N], k, N * sizeof(uint64_t));
+    vals_[i] = v;
+    ++count_;
+  }
+
+ private:
+  size_t slot_of(const uint64_t *k) const {
+    uint64_t h = 0x9e3779b97f4a7c15ull;
+    for (int j = 0; j < N; ++j) {
+      h = (h ^ k[j]) * 0xff51afd7ed558ccdull;
+      h ^= h >> 32;
+    }
+    return (size_t)h & mask_;
+  }
+  void rehash(size_t cap) {
+    std::vector<uint64_t> old_keys;
+    std::vector<int32_t> old_vals;
+    old_keys.swap(keys_);
+    old_vals.swap(vals_);
+    keys_.assign(cap * N, 0);
+    vals_.assign(cap, -1);
+    mask_ = cap - 1;
+    count_ = 0;
+    for (size_t i = 0; i < old_vals.size(); ++i)
+      if (old_vals[i] >= 0) insert(&old_keys[i * N], old_vals[i]);
+  }
+  std::vector<uint64_t> keys_;
+  std::vector<int32_t> vals_;
+  size_t mask_ = 0, count_ = 0;
 };
 
 // Distinct rotations, per-pose translation offsets c = fl(fl(t - origin) * s),
@@ -603,46 +637,28 @@ int build_tables(const GridInfo &gi, const double *poses, int64_t K, PoseTables 
   T.K = K;
   T.R.clear();
   std::vector<PoseDev> items((size_t)K);
-  struct AngKey {
-    uint64_t w[3];
-    bool operator==(const AngKey &o) const { return w[0] == o.w[0] && w[1] == o.w[1] && w[2] == o.w[2]; }
-  };
-  struct AngHash {
-    size_t operator()(const AngKey &k) const {
-      uint64_t h = 1469598103934665603ull;
-      for (int i = 0; i < 3; ++i) { h ^= k.w[i]; h *= 1099511628211ull; }
-      return (size_t)h;
-    }
-  };
-  std::unordered_map<AngKey, int32_t, AngHash> by_angles;
-  std::unordered_map<BitsKey, int32_t, BitsHash> by_matrix;
-  by_angles.reserve(1024);
-  by_matrix.reserve(1024);
+  WordIndex<3> by_angles;
+  WordIndex<9> by_matrix;
   double cmin[3] = {INFINITY, INFINITY, INFINITY}, cmax[3] = {-INFINITY, -INFINITY, -INFINITY};
   for (int64_t k = 0; k < K; ++k) {
     const double *eta = poses + 6 * k;
     for (int a = 0; a < 6; ++a)
       if (!std::isfinite(eta[a])) return -1;
-    AngKey ak;
-    memcpy(ak.w, eta + 3, sizeof ak.w);
-    int32_t fidx;
-    auto ia = by_angles.find(ak);
-    if (ia != by_angles.end()) {
-      fidx = ia->second;
-    } else {
+    uint64_t ak[3];
+    memcpy(ak, eta + 3, sizeof ak);
+    int32_t fidx = by_angles.find(ak);
+    if (fidx < 0) {
       double R[9];
       pose_rotation(eta, R);
-      BitsKey key;
-      memcpy(key.w, R, sizeof key.w);
-      auto im = by_matrix.find(key);
-      if (im == by_matrix.end()) {
+      uint64_t key[9];
+      memcpy(key, R, sizeof key);
+      fidx = by_matrix.find(key);
+      if (fidx < 0) {
         fidx = (int32_t)(T.R.size() / 9);
-        by_matrix.emplace(key, fidx);
+        by_matrix.insert(key, fidx);
         T.R.insert(T.R.end(), R, R + 9);
-      } else {
-        fidx = im->second;
       }
-      by_angles.emplace(ak, fidx);
+      by_angles.insert(ak, fidx);
     }
     PoseDev &p = items[(size_t)k];
     p.pair = 0;
@@ -1640,17 +1656,19 @@ void c2f_grid(const double c[6], const double h[6], const int32_t samples[6],
   int64_t K = 1;
   for (int a = 0; a < 6; ++a) K *= samples[a];
   P.resize((size_t)K * 6);
+  std::vector<double> node[6];
+  for (int a = 0; a < 6; ++a) {
+    const int32_t sa = samples[a];
+    node[a].resize((size_t)sa);
+    for (int32_t j = 0; j < sa; ++j)
+      node[a][(size_t)j] = sa == 1 ? c[a] : c[a] + h[a] * (-1.0 + (2.0 * j) / (double)(sa - 1));
+  }
+  int32_t j[6] = {0, 0, 0, 0, 0, 0};
   for (int64_t k = 0; k < K; ++k) {
-    int64_t r = k;
-    int32_t j[6];
-    for (int a = 5; a >= 0; --a) {
-      j[a] = (int32_t)(r % samples[a]);
-      r /= samples[a];
-    }
-    for (int a = 0; a < 6; ++a) {
-      const int32_t sa = samples[a];
-      P[(size_t)k * 6 + a] =
-          sa == 1 ? c[a] : c[a] + h[a] * (-1.0 + (2.0 * j[a]) / (double)(sa - 1));
+    for (int a = 0; a < 6; ++a) P[(size_t)k * 6 + a] = node[a][(size_t)j[a]];
+    for (int a = 5; a >= 0; --a) {  // yaw fastest
+      if (++j[a] < samples[a]) break;
+      j[a] = 0;
     }
   }
 }
