@@ -216,8 +216,9 @@ __global__ void __launch_bounds__(1024) k_eval(const PairDev *__restrict__ pairs
     unsigned long long nin = 0, nnear = 0;
     int parity = 0;
     // Pieces a stripe's first brick spans: the span that last fitted, doubled
-    // after a brick that used under a third of the slots (adapts to how many
-    // voxels the points fill, so that overflow retries stay rare).
+    // after a brick that used under a third of the slots and halved after one
+    // that used over half (adapts to how many voxels the points fill, so that
+    // overflow retries stay rare and probe sequences short).
     int span = 1 << 30;
     int last_occ = 0;
 
@@ -633,6 +634,7 @@ __global__ void __launch_bounds__(1024) k_eval(const PairDev *__restrict__ pairs
               if (whole) {
                 span = qend - qa;
                 if (3 * last_occ < cap) span = min(2 * span, Q);
+                else if (2 * last_occ > cap) span = max(span / 2, 1);
               }
               qa = qend;
               break;
