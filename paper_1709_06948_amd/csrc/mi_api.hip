@@ -639,27 +639,42 @@ int build_tables(const GridInfo &gi, const double *poses, int64_t K, PoseTables 
   std::vector<PoseDev> items((size_t)K);
   WordIndex<3> by_angles;
   WordIndex<9> by_matrix;
+  // Pose sets often cycle through their rotations (a pose grid varies the
+  // angles fastest): once a rotation repeats, the pose one cycle back is
+  // compared first, and the index is searched only when it differs.
+  std::vector<int64_t> last_use;  // per frame: the latest pose with its rotation
+  int64_t period = 0;
   double cmin[3] = {INFINITY, INFINITY, INFINITY}, cmax[3] = {-INFINITY, -INFINITY, -INFINITY};
   for (int64_t k = 0; k < K; ++k) {
     const double *eta = poses + 6 * k;
     for (int a = 0; a < 6; ++a)
       if (!std::isfinite(eta[a])) return -1;
-    uint64_t ak[3];
-    memcpy(ak, eta + 3, sizeof ak);
-    int32_t fidx = by_angles.find(ak);
-    if (fidx < 0) {
-      double R[9];
-      pose_rotation(eta, R);
-      uint64_t key[9];
-      memcpy(key, R, sizeof key);
-      fidx = by_matrix.find(key);
-      if (fidx < 0) {
-        fidx = (int32_t)(T.R.size() / 9);
-        by_matrix.insert(key, fidx);
-        T.R.insert(T.R.end(), R, R + 9);
+    int32_t fidx = -1;
+    if (period > 0 && k >= period &&
+        memcmp(poses + 6 * (k - period) + 3, eta + 3, 3 * sizeof(double)) == 0) {
+      fidx = items[(size_t)(k - period)].frame;
+    } else {
+      uint64_t ak[3];
+      memcpy(ak, eta + 3, sizeof ak);
+      fidx = by_angles.find(ak);
+      if (fidx >= 0) {
+        period = k - last_use[(size_t)fidx];
+      } else {
+        double R[9];
+        pose_rotation(eta, R);
+        uint64_t key[9];
+        memcpy(key, R, sizeof key);
+        fidx = by_matrix.find(key);
+        if (fidx < 0) {
+          fidx = (int32_t)(T.R.size() / 9);
+          by_matrix.insert(key, fidx);
+          T.R.insert(T.R.end(), R, R + 9);
+          last_use.push_back(k);
+        }
+        by_angles.insert(ak, fidx);
       }
-      by_angles.insert(ak, fidx);
     }
+    last_use[(size_t)fidx] = k;
     PoseDev &p = items[(size_t)k];
     p.pair = 0;
     p.frame = fidx;
@@ -1072,8 +1087,11 @@ mi_status create_plan(const mi_work_item *w, int64_t n, uint32_t flags, void *ws
 
   // pose items: frame-mode pairs in order, each pair's items sorted by frame
   // (so the items of a frame chunk are contiguous), then per-pose pairs
-  std::vector<PoseDev> items((size_t)B.n_items);
-  {
+  std::vector<PoseDev> items;
+  if (n == 1 && !B.direct[0]) {
+    items.swap(B.T[0].items);  // one pair of frames: pair 0, frames from 0, already in order
+  } else {
+    items.resize((size_t)B.n_items);
     size_t k = 0;
     for (int pass = 0; pass < 2; ++pass)
       for (int64_t i = 0; i < n; ++i) {
