@@ -128,7 +128,10 @@ const char *mi_last_error(void);
  * of bricks;
  * wgs_per_cu: 0 launches one workgroup per pose, 1..16 a persistent grid of
  * that many workgroups per compute unit, each looping over poses.  Every
- * setting gives bit-identical histograms. */
+ * setting gives bit-identical histograms.  Until mi_tuning_set is called the
+ * default hash (66 KiB) falls back to 60 KiB in launches whose histograms and
+ * plan entries would otherwise leave room for only one workgroup per compute
+ * unit; sizes set here are used as given. */
 typedef struct mi_tuning {
   int32_t waves;
   int32_t hash_bytes;

@@ -165,12 +165,21 @@ hipError_t staging_upload(Staging *s, const Upload *ups, int n, hipStream_t st) 
 // ------------------------------------------------------------------ tuning
 
 namespace {
+// Default hash: 66 KiB, which with the histograms and plan entries of a
+// 32-bin, two-feature launch still leaves two 80 KiB workgroups per compute
+// unit.  A launch whose other LDS needs are larger falls back to kFitHashBytes
+// while the default is in force (hash_fit); a size set by mi_tuning_set is
+// used as given.
+constexpr int32_t kDefaultHashBytes = 66 * 1024;
+constexpr int32_t kFitHashBytes = 60 * 1024;
+constexpr int64_t kTwoWorkgroupLds = 80 * 1024;
 struct Tuning {
   int32_t waves = 8;
-  int32_t hash_bytes = 60 * 1024;
+  int32_t hash_bytes = kDefaultHashBytes;
   int32_t hist_copies = 1;
   int32_t stripe_rows = 16;
   int32_t wgs_per_cu = 0;
+  bool hash_fit = true;
 };
 Tuning g_tuning;
 std::mutex g_tuning_mu;
@@ -205,6 +214,7 @@ extern "C" mi_status mi_tuning_set(const mi_tuning *t) {
   g_tuning.hist_copies = t->hist_copies;
   g_tuning.stripe_rows = t->stripe_rows;
   g_tuning.wgs_per_cu = t->wgs_per_cu;
+  g_tuning.hash_fit = false;
   return MI_OK;
   });
 }
@@ -752,7 +762,7 @@ bool choose_stripes(const GridInfo &gi, const Tuning &tu, bool zvar, StripeShape
   if (S.kx_bits + S.ky_bits + bits_for(nz) > 31) { *why = "grid dims exceed the voxel key"; return false; }
   S.plan_entries = (S.stripe_h + 2) * (S.pieces + 1);
   S.plan_stripes = (int)std::max<int64_t>(1, std::min<int64_t>(S.n_stripes,
-                                                                8192 / (S.plan_entries * 8)));
+                                                                4096 / (S.plan_entries * 8)));
   return true;
 }
 
@@ -878,7 +888,30 @@ mi_status prepare_batch(const mi_work_item *w, int64_t n, uint32_t flags, BatchT
   B.SS.assign((size_t)n, StripeShape());
   B.direct.assign((size_t)n, 0);
   B.frame_start.assign((size_t)n, 0);
-  const Tuning tu = tuning_now();
+  Tuning tu = tuning_now();
+  if (tu.hash_fit && tu.hash_bytes > kFitHashBytes) {
+    // the default hash only where the launch keeps two workgroups per CU
+    // (plan entries as for shared frames, the larger of the two forms)
+    int plan_max = 8;
+    int32_t cap = 64;
+    for (int64_t i = 0; i < n; ++i) {
+      StripeShape S;
+      const char *why = "";
+      if (!choose_stripes(w[i].ref->g->gi, tu, zvar, S, &why)) continue;
+      plan_max = std::max(plan_max, S.plan_stripes * S.plan_entries * 8);
+      cap = S.cap;
+    }
+    EvalLaunch L0;
+    L0.waves = tu.waves;
+    L0.cap = cap;
+    L0.hist_copies = tu.hist_copies;
+    L0.hist_words = hist_words;
+    L0.plan_bytes = plan_max;
+    L0.wgs_per_cu = tu.wgs_per_cu;
+    L0.zvar = zvar;
+    L0.near_face = false;
+    if ((int64_t)eval_lds_bytes(L0) > kTwoWorkgroupLds) tu.hash_bytes = kFitHashBytes;
+  }
   int plan_bytes_max = 8;
   for (int64_t i = 0; i < n; ++i) {
     const mi_work_item &it = w[i];
