@@ -1465,7 +1465,7 @@ extern "C" mi_status mi_autotune(const mi_work_item *items, int64_t n_items, uin
   if (st == MI_OK && start_ms >= 0.0) { best_ms = start_ms; best = start; }
   // stage 1: workgroup size and hash capacity
   const int waves[3] = {4, 8, 16};
-  const int hashk[7] = {24, 32, 48, 56, 60, 64, 96};
+  const int hashk[8] = {24, 32, 48, 56, 60, 64, 66, 96};
   for (int w : waves)
     for (int hk : hashk) consider(mi_tuning{w, hk * 1024, 1, 12, 0});
   // stage 2: stripe height and histogram privatization around the best
