@@ -97,3 +97,41 @@ def evaluate(A, B, origin, dims, voxel, R, t, kind, nb, edges):
                     H[bins_of(ta, key, kind, edges), bins_of(tb, key, kind, edges)] += 1
     mi = 0.0 if H.sum() == 0 else float(mutual_info_score(None, None, contingency=H))
     return H, lo, hi, mi
+
+
+NEAR_FACE_M = Fraction(1, 100000)
+
+
+def near_face_count(B, origin, dims, voxel, R, t, lo, hi):
+    """B points inside the overlap box [lo, hi] (voxel indices) whose distance
+    to the nearest face of their voxel is under 1e-5 m, from exact rationals:
+    the float32 coordinates, the entries of R and t and the voxel size are
+    converted exactly, the voxel coordinate (R p + t - origin) / voxel is
+    formed without rounding, and the voxel is its floor (no floating point
+    decides anything here)."""
+    if any(lo[a] > hi[a] for a in range(3)):
+        return 0
+    vox = Fraction(float(voxel))
+    Rq = [[Fraction(float(R[r][c])) for c in range(3)] for r in range(3)]
+    tq = [Fraction(float(t[a])) for a in range(3)]
+    oq = [Fraction(float(origin[a])) for a in range(3)]
+    P = np.asarray(B, np.float32)
+    count = 0
+    for i in range(P.shape[1]):
+        p = [float(P[a, i]) for a in range(3)]
+        if not all(math.isfinite(v) for v in p):
+            continue
+        pq = [Fraction(v) for v in p]
+        near, inside = False, True
+        for a in range(3):
+            u = (sum(Rq[a][b] * pq[b] for b in range(3)) + tq[a] - oq[a]) / vox
+            iu = math.floor(u)
+            if not (lo[a] <= iu <= hi[a] and 0 <= iu < dims[a]):
+                inside = False
+                break
+            fr = u - iu
+            if min(fr, 1 - fr) * vox < NEAR_FACE_M:
+                near = True
+        if inside and near:
+            count += 1
+    return count

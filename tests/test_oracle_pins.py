@@ -171,6 +171,73 @@ def test_hand_derived_cases(case):
     assert abs(mi[0][0] - case["mi"]) < 1e-12
 
 
+def _near_face_golden():
+    with open(os.path.join(GOLDEN, "near_face_cases.json")) as fh:
+        return json.load(fh)
+
+
+@pytest.mark.parametrize("voxel", _near_face_golden()["voxels"])
+def test_near_face_hand_cases(voxel):
+    # Alg. 1 overlap step: B points in O within 1e-5 m of a voxel face are
+    # counted (stats field 10); the case file gives every point and the count
+    # worked out by hand, at voxels of 1, 0.5, 0.25 and 4 m.
+    gc = _near_face_golden()
+    v = float(voxel)
+    g = O.Grid((0.0, 0.0, 0.0), (4, 4, 4), v, features=O.FEAT_COUNT, nb_count=4)
+    A = np.array([[(c[a] + 0.5) * v for c in gc["A_cells"]] for a in range(3)], np.float32)
+    pts = [[pt["v_units"][a] * v + pt["offset_m"][a] for a in range(3)] for pt in gc["B_points"]]
+    B = np.array(pts, np.float64).T.astype(np.float32)
+    _, _, st = O.eval_poses(g, A, B, np.zeros((1, 6)), want_stats=True)
+    ex = gc["expected"]
+    assert list(st[0][:6]) == ex["overlap"]
+    assert st[0][7] == ex["n_in_grid"] and st[0][8] == ex["n_out_of_grid"]
+    assert st[0][10] == ex["n_near_face"]
+    # the exact-rational tally agrees on the same input
+    lo, hi = ex["overlap"][:3], ex["overlap"][3:]
+    assert BF.near_face_count(B, (0.0, 0.0, 0.0), (4, 4, 4), v, np.eye(3), (0.0, 0.0, 0.0),
+                              lo, hi) == ex["n_near_face"]
+
+
+def test_near_face_moves_with_the_pose():
+    # A pure translation by whole voxels keeps every fractional part, so the
+    # hand cases keep their near-face count; a move by a quarter voxel on all
+    # three axes puts every fractional part near 1/4 or 3/4, away from every
+    # face (0 near).
+    gc = _near_face_golden()
+    v = 0.5
+    g = O.Grid((0.0, 0.0, 0.0), (4, 4, 4), v, features=O.FEAT_COUNT, nb_count=4)
+    A = np.array([[(c[a] + 0.5) * v for c in gc["A_cells"]] for a in range(3)], np.float32)
+    pts = [[pt["v_units"][a] * v + pt["offset_m"][a] for a in range(3)] for pt in gc["B_points"]]
+    B = np.array(pts, np.float64).T.astype(np.float32)
+    # B moved down by one voxel in z, brought back by the pose
+    Bm = B.copy()
+    Bm[2] -= np.float32(v)
+    _, _, st = O.eval_poses(g, A, Bm, np.array([[0, 0, v, 0, 0, 0]]), want_stats=True)
+    assert st[0][10] == gc["expected"]["n_near_face"]
+    assert list(st[0][:6]) == gc["expected"]["overlap"]
+    _, _, st = O.eval_poses(g, A, B, np.array([[v / 4, v / 4, v / 4, 0, 0, 0]]), want_stats=True)
+    assert st[0][6] > 0 and st[0][10] == 0
+
+
+def test_near_face_threshold_is_strict():
+    # "Within 1e-5 m" is read as a distance strictly below 1e-5 m.  A point at
+    # the grid origin moved by tx = 1e-5 lands at u_x = 1e-5 exactly (the
+    # voxel coordinate is fl(fl(x * s) + c) with x = 0 and c = 1e-5), so its
+    # distance to the face is the double 1e-5: not near.  One ulp closer is.
+    g = O.Grid((0.0, 0.0, 0.0), (2, 2, 2), 1.0, features=O.FEAT_COUNT, nb_count=4)
+    A = np.array([[0.5, 1.5], [0.5, 1.5], [0.5, 1.5]], np.float32)
+    B = np.array([[0.0], [0.5], [0.5]], np.float32)
+    tx_at = 1e-5
+    tx_in = np.nextafter(1e-5, 0.0)
+    _, _, st = O.eval_poses(g, A, B, np.array([[tx_at, 0, 0, 0, 0, 0], [tx_in, 0, 0, 0, 0, 0]]),
+                            want_stats=True)
+    assert st[0][7] == 1 and st[1][7] == 1
+    assert st[0][10] == 0 and st[1][10] == 1
+    for k, tx in enumerate((tx_at, tx_in)):
+        assert BF.near_face_count(B, g.origin, g.dims, 1.0, np.eye(3), (tx, 0.0, 0.0),
+                                  st[k][:3], st[k][3:6]) == st[k][10]
+
+
 # ------------------------------------------------------------ brute force
 
 def _tiny_cloud(rng, n, lo, hi):
@@ -192,6 +259,12 @@ def test_bruteforce_4x4x4(kind, seed):
     A = _tiny_cloud(rng, 60, -0.5, 4.5)
     B = _tiny_cloud(rng, 50, -0.5, 4.5)
     A[:, 5] = [np.nan, 1.0, 1.0]             # non-finite point is skipped
+    # points 5e-6 m and 2e-5 m from faces (near-face count of the overlap step)
+    B[:, 5] = [1.0 + 5e-6, 1.5, 2.5]
+    B[:, 6] = [2.5, 3.0 - 5e-6, 1.5]
+    B[:, 7] = [1.5, 2.0 + 2e-5, 1.5]
+    B[:, 8] = [0.5, 2.5, 1.0 - 2e-5]
+    B[:, 9] = [3.0 - 5e-6, 2.0 + 5e-6, 0.5]
     if kind == "count":
         g = O.Grid(origin, dims, vox, features=O.FEAT_COUNT, nb_count=5)
         edges, nb = g.count_edges, 5
@@ -209,6 +282,7 @@ def test_bruteforce_4x4x4(kind, seed):
         Hb, lo, hi, mib = BF.evaluate(A, B, origin, dims, vox, R, p[:3], kind, nb, edges)
         assert np.array_equal(H[0][k].astype(np.int64), Hb), (k, p)
         assert abs(mi[0][k] - mib) < 1e-12
+        assert st[k][10] == BF.near_face_count(B, origin, dims, vox, R, p[:3], lo, hi), (k, p)
         if Hb.sum():
             assert list(st[k][:3]) == lo and list(st[k][3:6]) == hi
             assert st[k][6] == Hb.sum()
@@ -320,6 +394,91 @@ def test_grid_poses_layout():
     assert np.allclose(P[:3, 0], 0.0) and np.allclose(P[3:, 0], 2.0)
     assert np.allclose(P[:3, 5], [0.2, 0.3, 0.4])                  # yaw fastest
     assert np.allclose(P[:, 1], 2.0)
+
+
+def _c2f_scene():
+    """A scene whose MI peaks at a known pose: B is A moved by -t_true, with
+    coordinates on a 1/64 m lattice so that the float32 subtraction is exact.
+    At the pose t_true every B point lands on its A point bit for bit, so the
+    histogram is diagonal and MI = H(A over O) (Eqs. 2-5), the largest value
+    any pose can give.  Blobs of different densities give the count feature
+    many bins."""
+    rng = np.random.default_rng(77)
+    pts = []
+    for _ in range(40):
+        c = rng.uniform([2, 2, 0.5], [14, 14, 3.5])
+        n = int(rng.integers(3, 40))
+        pts.append(c + rng.normal(0, 0.6, (n, 3)))
+    P = np.concatenate(pts).T
+    P = np.round(P * 64) / 64
+    A = P.astype(np.float32)
+    t_true = np.array([-1.375, 2.625, 0.0, 0.0, 0.0, 0.0])
+    B = (P - t_true[:3, None]).astype(np.float32)
+    assert np.array_equal(B.astype(np.float64) + t_true[:3, None], A.astype(np.float64))
+    g = O.Grid((0.0, 0.0, 0.0), (16, 16, 4), 1.0, features=O.FEAT_COUNT, nb_count=8)
+    return g, A, B, t_true
+
+
+def test_c2f_level_loop_reaches_the_true_pose():
+    # Alg. 1 outer loop as a shrinking grid: level 0 centred on T_o = 0 with
+    # half-range 4 m has nodes -4, -2, 0, 2, 4; the truth (-1.375, 2.625) is a
+    # node only of level 2 (centre -1.5, 2.5; h = 0.25; nodes step 0.125), so
+    # the search reaches it only if every level moves its centre to the best
+    # node and divides h by the shrink factor.  The centre moves off-centre at
+    # every level: (-2, 2), then (-1.5, 2.5), then the truth.
+    g, A, B, t_true = _c2f_scene()
+    half = [4.0, 4.0, 0.0, 0.0, 0.0, 0.0]
+    samples = [5, 5, 1, 1, 1, 1]
+    pose, best = O.align_c2f(g, A, B, np.zeros(6), half, samples, 3, 4.0, feature_slot=0)
+    assert np.array_equal(pose, t_true), pose
+    # the objective at the final pose is MI at exact alignment = H(A over O),
+    # pinned against the brute-force evaluator
+    _, lo, hi, mib = BF.evaluate(A, B, g.origin, g.dims, g.voxel, np.eye(3), t_true[:3], "count",
+                                 8, g.count_edges)
+    assert abs(best - mib) < 1e-12
+    _, H, _ = O.eval_poses(g, A, B, t_true[None, :], want_hist=True)
+    h = H[0][0]
+    assert np.count_nonzero(h - np.diag(np.diag(h))) == 0
+
+
+def test_c2f_levels_rebuilt_step_by_step():
+    # The same search rebuilt outside the oracle's loop: each level's nodes are
+    # written out per axis (centre + h * (-1, -1/2, 0, 1/2, 1) for 5 samples),
+    # evaluated, and the next centre is the first pose within 1e-12 of the
+    # level's maximum (Eq. 1 over the level); h is divided by the shrink.  The
+    # centres must move off-centre on every level and the oracle's search must
+    # return the same pose bit for bit.
+    g, A, B, t_true = _c2f_scene()
+    c = np.zeros(6)
+    h = np.array([4.0, 4.0, 0.0, 0.0, 0.0, 0.0])
+    centres = []
+    for level in range(3):
+        xs = c[0] + h[0] * np.array([-1.0, -0.5, 0.0, 0.5, 1.0])
+        ys = c[1] + h[1] * np.array([-1.0, -0.5, 0.0, 0.5, 1.0])
+        P = np.array([[x, y, 0, 0, 0, 0] for x in xs for y in ys], np.float64)
+        mi, _, _ = O.eval_poses(g, A, B, P)
+        m = mi[0]
+        k = int(np.flatnonzero(m >= m.max() - 1e-12)[0])
+        assert k != 12, f"level {level}: the best node is the centre"
+        c = P[k].copy()
+        h = h / 4.0
+        centres.append(c[:2].copy())
+    assert np.array_equal(centres[0], [-2.0, 2.0])
+    assert np.array_equal(centres[1], [-1.5, 2.5])
+    assert np.array_equal(c, t_true)
+    pose, _ = O.align_c2f(g, A, B, np.zeros(6), [4, 4, 0, 0, 0, 0], [5, 5, 1, 1, 1, 1], 3, 4.0)
+    assert np.array_equal(pose, c)
+
+
+def test_c2f_single_level_is_the_grid_argmax():
+    # One level is Eq. 1 over the level's grid: the argmax pose itself.
+    g, A, B, _ = _c2f_scene()
+    half, samples = [3.0, 3.0, 0.0, 0.0, 0.0, 0.05], [4, 4, 1, 1, 1, 3]
+    P = O.grid_poses(np.zeros(6), half, samples)
+    mi, _, _ = O.eval_poses(g, A, B, P)
+    pose, best = O.align_c2f(g, A, B, np.zeros(6), half, samples, 1, 2.0)
+    k = O.argmax(mi[0])
+    assert np.array_equal(pose, P[k]) and best == mi[0][k]
 
 
 @pytest.mark.parametrize("seed", range(10))
