@@ -128,10 +128,11 @@ const char *mi_last_error(void);
  * of bricks;
  * wgs_per_cu: 0 launches one workgroup per pose, 1..16 a persistent grid of
  * that many workgroups per compute unit, each looping over poses.  Every
- * setting gives bit-identical histograms.  Until mi_tuning_set is called the
- * default hash (66 KiB) falls back to 60 KiB in launches whose histograms and
- * plan entries would otherwise leave room for only one workgroup per compute
- * unit; sizes set here are used as given. */
+ * setting gives bit-identical histograms.  hash_bytes = 0 (the default) is
+ * "auto": 66 KiB, falling back to 60 KiB in launches whose histograms and plan
+ * entries would otherwise leave room for only one workgroup per compute unit;
+ * mi_tuning_get reports 0 while it is in force, so a get / set round trip
+ * keeps it.  Other sizes are used as given. */
 typedef struct mi_tuning {
   int32_t waves;
   int32_t hash_bytes;
@@ -248,6 +249,11 @@ mi_status mi_plan_create(const mi_ref *r, int64_t n_b, const double *poses, int6
 mi_status mi_plan_execute(mi_plan *p, const float *xyz_b, double *mi_out, int64_t *argmax_out,
                           uint32_t *hist_out, mi_pose_stats *stats_out, void *stream);
 void mi_plan_destroy(mi_plan *p);
+
+/* The launch shape of a plan (tests, tracing): the tuning in force when it
+ * was created, with the auto hash resolved to the size used, and the LDS bytes
+ * of one evaluator workgroup.  Either output may be NULL. */
+mi_status mi_plan_launch(const mi_plan *p, mi_tuning *t, int32_t *lds_bytes);
 
 /* ------------------------------------------------------------ batches */
 
@@ -437,6 +443,10 @@ mi_status mi_server_submit(mi_server *s, const mi_request *r, int64_t *id);
 mi_status mi_server_step(mi_server *s, int32_t *n_active, int32_t *n_queued);
 mi_status mi_server_poll(mi_server *s, int64_t id, mi_request_state *out);
 mi_status mi_server_release(mi_server *s, int64_t id); /* forget a finished request */
+/* Arena bookkeeping (tests, monitoring): the request heap's size and its free
+ * bytes now.  Once no request is queued or active every block is back, failed
+ * requests included, and heap_free equals heap_bytes. */
+mi_status mi_server_info(mi_server *s, size_t *heap_bytes, size_t *heap_free);
 void mi_server_destroy(mi_server *s);
 
 #ifdef __cplusplus

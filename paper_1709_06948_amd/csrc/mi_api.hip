@@ -165,21 +165,19 @@ hipError_t staging_upload(Staging *s, const Upload *ups, int n, hipStream_t st) 
 // ------------------------------------------------------------------ tuning
 
 namespace {
-// Default hash: 66 KiB, which with the histograms and plan entries of a
-// 32-bin, two-feature launch still leaves two 80 KiB workgroups per compute
-// unit.  A launch whose other LDS needs are larger falls back to kFitHashBytes
-// while the default is in force (hash_fit); a size set by mi_tuning_set is
-// used as given.
-constexpr int32_t kDefaultHashBytes = 66 * 1024;
+// Default hash (hash_bytes = 0, "auto"): 66 KiB, which with the histograms
+// and plan entries of a 32-bin, two-feature launch still leaves two 80 KiB
+// workgroups per compute unit; a launch whose other LDS needs are larger
+// falls back to kFitHashBytes.  A size set by mi_tuning_set is used as given.
+constexpr int32_t kAutoHashBytes = 66 * 1024;
 constexpr int32_t kFitHashBytes = 60 * 1024;
 constexpr int64_t kTwoWorkgroupLds = 80 * 1024;
 struct Tuning {
   int32_t waves = 8;
-  int32_t hash_bytes = kDefaultHashBytes;
+  int32_t hash_bytes = 0;  // 0: auto
   int32_t hist_copies = 1;
   int32_t stripe_rows = 16;
   int32_t wgs_per_cu = 0;
-  bool hash_fit = true;
 };
 Tuning g_tuning;
 std::mutex g_tuning_mu;
@@ -203,8 +201,8 @@ extern "C" mi_status mi_tuning_set(const mi_tuning *t) {
   return guarded("mi_tuning_set", [&]() -> mi_status {
   if (!t) return fail(MI_E_INVALID, "mi_tuning_set: NULL");
   if (t->waves < 1 || t->waves > 16) return fail(MI_E_INVALID, "waves must be 1..16");
-  if (t->hash_bytes < 1024 || t->hash_bytes > 160 * 1024)
-    return fail(MI_E_INVALID, "hash_bytes must be in [1 KiB, 160 KiB]");
+  if (t->hash_bytes != 0 && (t->hash_bytes < 1024 || t->hash_bytes > 160 * 1024))
+    return fail(MI_E_INVALID, "hash_bytes must be 0 (auto) or in [1 KiB, 160 KiB]");
   if (t->hist_copies < 1 || t->hist_copies > 8) return fail(MI_E_INVALID, "hist_copies 1..8");
   if (t->stripe_rows < 1 || t->stripe_rows > 62) return fail(MI_E_INVALID, "stripe_rows 1..62");
   if (t->wgs_per_cu < 0 || t->wgs_per_cu > 16) return fail(MI_E_INVALID, "wgs_per_cu 0..16");
@@ -214,7 +212,6 @@ extern "C" mi_status mi_tuning_set(const mi_tuning *t) {
   g_tuning.hist_copies = t->hist_copies;
   g_tuning.stripe_rows = t->stripe_rows;
   g_tuning.wgs_per_cu = t->wgs_per_cu;
-  g_tuning.hash_fit = false;
   return MI_OK;
   });
 }
@@ -799,6 +796,7 @@ struct mi_plan {
   FrameDev *frames_dev;
   unsigned long long *nonfinite;     // [pairs][2]
   EvalLaunch launch;
+  mi_tuning tuning;                  // the tuning the plan was created under
 };
 
 namespace {
@@ -864,6 +862,7 @@ struct BatchTables {
   int32_t F_built = 0;               // entries of frame-mode pairs (built; they come first)
   int64_t scratch_stride = 0;        // largest n_b of a per-pose pair
   int64_t scratch_slots = 0;         // workgroups of the per-pose launch
+  mi_tuning tuning = {};             // in force, the auto hash resolved to its size
 };
 
 mi_status prepare_batch(const mi_work_item *w, int64_t n, uint32_t flags, BatchTables &B) {
@@ -889,7 +888,8 @@ mi_status prepare_batch(const mi_work_item *w, int64_t n, uint32_t flags, BatchT
   B.direct.assign((size_t)n, 0);
   B.frame_start.assign((size_t)n, 0);
   Tuning tu = tuning_now();
-  if (tu.hash_fit && tu.hash_bytes > kFitHashBytes) {
+  if (tu.hash_bytes == 0) {
+    tu.hash_bytes = kAutoHashBytes;
     // the default hash only where the launch keeps two workgroups per CU
     // (plan entries as for shared frames, the larger of the two forms)
     int plan_max = 8;
@@ -912,6 +912,7 @@ mi_status prepare_batch(const mi_work_item *w, int64_t n, uint32_t flags, BatchT
     L0.near_face = false;
     if ((int64_t)eval_lds_bytes(L0) > kTwoWorkgroupLds) tu.hash_bytes = kFitHashBytes;
   }
+  B.tuning = mi_tuning{tu.waves, tu.hash_bytes, tu.hist_copies, tu.stripe_rows, tu.wgs_per_cu};
   int plan_bytes_max = 8;
   for (int64_t i = 0; i < n; ++i) {
     const mi_work_item &it = w[i];
@@ -1105,6 +1106,7 @@ mi_status create_plan(const mi_work_item *w, int64_t n, uint32_t flags, void *ws
   p->n_items = B.n_items;
   p->F = B.F;
   p->launch = B.L;
+  p->tuning = B.tuning;
   p->items_dev = PL.items;
   p->pairs_dev = PL.pairs;
   p->frames_dev = PL.frames;
@@ -1432,7 +1434,9 @@ extern "C" mi_status mi_autotune(const mi_work_item *items, int64_t n_items, uin
     if (mi_tuning_set(&t) != MI_OK) return MI_OK;
     mi_plan *p = nullptr;
     mi_status st = create_plan(S.items.data(), n_items, flags, bws, bws_bytes, 0, stream, false, &p);
-    if (st == MI_E_UNSUPPORTED) return MI_OK;
+    // a tuning the workload cannot use, or whose plan (per-pose scratch grows
+    // with the resident workgroups) does not fit the workspace, is skipped
+    if (st == MI_E_UNSUPPORTED || st == MI_E_WORKSPACE) return MI_OK;
     if (st != MI_OK) return st;
     st = run_plan(p, s);
     if (st == MI_OK) {
@@ -1465,7 +1469,8 @@ extern "C" mi_status mi_autotune(const mi_work_item *items, int64_t n_items, uin
   if (st == MI_OK && start_ms >= 0.0) { best_ms = start_ms; best = start; }
   // stage 1: workgroup size and hash capacity
   const int waves[3] = {4, 8, 16};
-  const int hashk[8] = {24, 32, 48, 56, 60, 64, 66, 96};
+  // 0 is the auto hash (66 KiB, or 60 KiB where 66 would leave one workgroup per CU)
+  const int hashk[9] = {0, 24, 32, 48, 56, 60, 64, 66, 96};
   for (int w : waves)
     for (int hk : hashk) consider(mi_tuning{w, hk * 1024, 1, 12, 0});
   // stage 2: stripe height and histogram privatization around the best
@@ -1541,6 +1546,15 @@ extern "C" mi_status mi_plan_execute(mi_plan *p, const float *xyz_b, double *mi_
 }
 
 extern "C" void mi_plan_destroy(mi_plan *p) { delete p; }
+
+extern "C" mi_status mi_plan_launch(const mi_plan *p, mi_tuning *t, int32_t *lds_bytes) {
+  return guarded("mi_plan_launch", [&]() -> mi_status {
+  if (!p) return fail(MI_E_INVALID, "mi_plan_launch: NULL plan");
+  if (t) *t = p->tuning;
+  if (lds_bytes) *lds_bytes = (int32_t)eval_lds_bytes(p->launch);
+  return MI_OK;
+  });
+}
 
 extern "C" mi_status mi_eval_poses(const mi_ref *r, const float *xyz_b, int64_t n_b,
                                    const double *poses, int64_t K, uint32_t flags, double *mi_out,
@@ -1840,6 +1854,13 @@ class Arena {
 
  private:
   std::map<size_t, size_t> free_;
+
+ public:
+  size_t free_bytes() const {
+    size_t b = 0;
+    for (const auto &kv : free_) b += kv.second;
+    return b;
+  }
 };
 
 struct Request {
@@ -1856,7 +1877,9 @@ struct Request {
   mi_ref *ref = nullptr;
   size_t ref_bytes = 0, ref_keep = 0;
   size_t off_b = 0, off_a = 0, off_ref = 0;
-  bool holds = false;              // arena blocks held
+  bool holds = false;              // arena blocks of scan B and the resident reference held
+  bool holds_a = false;            // scan A's block held (until its reference is built)
+  bool holds_ref_tail = false;     // the reference workspace's transient tail held
   std::vector<double> P;           // poses of the current level
   size_t slot = 0;                 // place of its argmax in the pinned results
 };
@@ -1900,7 +1923,18 @@ size_t req_step_bytes(const Request &r) {
          fb.off + al256(fb.cur) + 4096;
 }
 
+// Give back every arena block the request still holds: scan B and the
+// resident reference always, scan A and the reference's transient tail when a
+// failure came before the reference was built.
 void req_release(mi_server *s, Request *r) {
+  if (r->holds_a) {
+    s->heap.release(r->off_a, req_points_bytes(r->n_a));
+    r->holds_a = false;
+  }
+  if (r->holds_ref_tail) {
+    s->heap.release(r->off_ref + r->ref_keep, al256(r->ref_bytes) - r->ref_keep);
+    r->holds_ref_tail = false;
+  }
   if (r->holds) {
     s->heap.release(r->off_b, req_points_bytes(r->n_b));
     s->heap.release(r->off_ref, r->ref_keep);
@@ -1934,6 +1968,8 @@ bool req_reserve(mi_server *s, Request *r) {
   r->off_a = oa;
   r->off_ref = orf;
   r->holds = true;
+  r->holds_a = true;
+  r->holds_ref_tail = true;
   return true;
 }
 
@@ -1959,8 +1995,9 @@ mi_status req_start(mi_server *s, Request *r) {
                                  &r->ref);
   if (st != MI_OK) return st;
   s->heap.release(r->off_a, req_points_bytes(r->n_a));
-  const size_t whole = al256(r->ref_bytes);
-  s->heap.release(r->off_ref + r->ref_keep, whole - r->ref_keep);
+  r->holds_a = false;
+  s->heap.release(r->off_ref + r->ref_keep, al256(r->ref_bytes) - r->ref_keep);
+  r->holds_ref_tail = false;
   std::vector<float>().swap(r->a);
   std::vector<float>().swap(r->b);
   return MI_OK;
@@ -2207,6 +2244,16 @@ extern "C" mi_status mi_server_release(mi_server *s, int64_t id) {
     return fail(MI_E_INVALID, "request %lld is still queued or active", (long long)id);
   if (it->second->g) mi_grid_destroy(it->second->g);
   s->table.erase(it);
+  return MI_OK;
+  });
+}
+
+extern "C" mi_status mi_server_info(mi_server *s, size_t *heap_bytes, size_t *heap_free) {
+  return guarded("mi_server_info", [&]() -> mi_status {
+  if (!s) return fail(MI_E_INVALID, "mi_server_info: NULL server");
+  std::lock_guard<std::mutex> lk(s->mu);
+  if (heap_bytes) *heap_bytes = (s->arena_bytes - s->step_bytes) & ~(size_t)255;
+  if (heap_free) *heap_free = s->heap.free_bytes();
   return MI_OK;
   });
 }

@@ -125,6 +125,8 @@ def _load():
         "mi_plan_create": ([vp, i64, dp, i64, u32, vp, sz, sz, vp, C.POINTER(vp)], st),
         "mi_plan_execute": ([vp, vp, vp, vp, vp, vp, vp], st),
         "mi_plan_destroy": ([vp], None),
+        "mi_plan_launch": ([vp, C.POINTER(_Tuning), C.POINTER(C.c_int32)], st),
+        "mi_server_info": ([vp, C.POINTER(sz), C.POINTER(sz)], st),
         "mi_batch_workspace": ([C.POINTER(_WorkItem), i64, u32, sz], sz),
         "mi_batch_create": ([C.POINTER(_WorkItem), i64, u32, vp, sz, sz, vp, C.POINTER(vp)], st),
         "mi_batch_execute": ([vp, vp], st),
@@ -158,6 +160,7 @@ EXPORTED = ("mi_status_str", "mi_last_error", "mi_tuning_set", "mi_tuning_get",
             "mi_features_ref", "mi_ref_destroy", "mi_ref_bins", "mi_ref_summary",
             "mi_eval_poses_workspace", "mi_eval_poses", "mi_eval_poses_plain_workspace",
             "mi_eval_poses_plain", "mi_plan_create", "mi_plan_execute", "mi_plan_destroy",
+            "mi_plan_launch", "mi_server_info",
             "mi_batch_workspace", "mi_batch_create", "mi_batch_execute", "mi_eval_batch",
             "mi_autotune_workspace", "mi_autotune",
             "mi_align_workspace", "mi_align_coarse_to_fine", "mi_align_nm_workspace",
@@ -245,7 +248,7 @@ def tuning_get() -> dict:
                 stripe_rows=t.stripe_rows, wgs_per_cu=t.wgs_per_cu)
 
 
-def tuning_set(waves: int, hash_bytes: int, hist_copies: int = 1, stripe_rows: int = 16,
+def tuning_set(waves: int, hash_bytes: int = 0, hist_copies: int = 1, stripe_rows: int = 16,
                wgs_per_cu: int = 0):
     t = _Tuning(int(waves), int(hash_bytes), int(hist_copies), int(stripe_rows), int(wgs_per_cu))
     _check(_lib.mi_tuning_set(C.byref(t)), "mi_tuning_set")
@@ -463,6 +466,14 @@ class Plan:
         _check(_lib.mi_plan_execute(self._h, _dptr(xyz_b), _dptr(mi), _dptr(argmax), _dptr(hist),
                                     _dptr(stats), _stream(stream)), "mi_plan_execute")
 
+    def launch(self) -> dict:
+        """mi_plan_launch: the tuning the plan runs under (auto hash resolved)
+        and the LDS bytes of one evaluator workgroup."""
+        t, lds = _Tuning(), C.c_int32()
+        _check(_lib.mi_plan_launch(self._h, C.byref(t), C.byref(lds)), "mi_plan_launch")
+        return dict(waves=t.waves, hash_bytes=t.hash_bytes, hist_copies=t.hist_copies,
+                    stripe_rows=t.stripe_rows, wgs_per_cu=t.wgs_per_cu, lds_bytes=lds.value)
+
     def __del__(self):
         if getattr(self, "_h", None) and _lib is not None:
             _lib.mi_plan_destroy(self._h)
@@ -520,6 +531,14 @@ class Batch:
                                     for t in (it.xyz_b, it.mi, it.argmax, it.hist_raw,
                                               it.stats_raw)])
         _check(_lib.mi_batch_execute(self._h, _stream(stream)), "mi_batch_execute")
+
+    def launch(self) -> dict:
+        """mi_plan_launch: the tuning the plan runs under (auto hash resolved)
+        and the LDS bytes of one evaluator workgroup."""
+        t, lds = _Tuning(), C.c_int32()
+        _check(_lib.mi_plan_launch(self._h, C.byref(t), C.byref(lds)), "mi_plan_launch")
+        return dict(waves=t.waves, hash_bytes=t.hash_bytes, hist_copies=t.hist_copies,
+                    stripe_rows=t.stripe_rows, wgs_per_cu=t.wgs_per_cu, lds_bytes=lds.value)
 
     def __del__(self):
         if getattr(self, "_h", None) and _lib is not None:
@@ -686,6 +705,12 @@ class Server:
 
     def release(self, rid: int):
         _check(_lib.mi_server_release(self._h, int(rid)), "mi_server_release")
+
+    def info(self) -> dict:
+        """mi_server_info: bytes of the request heap in all and free now."""
+        tot, free = C.c_size_t(), C.c_size_t()
+        _check(_lib.mi_server_info(self._h, C.byref(tot), C.byref(free)), "mi_server_info")
+        return dict(heap_bytes=tot.value, heap_free=free.value)
 
     def close(self):
         if getattr(self, "_h", None) and _lib is not None:

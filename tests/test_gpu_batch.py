@@ -215,3 +215,32 @@ def test_autotune_changes_speed_only(M):
         _same(after.results(), before.results(), mg, "autotuned vs default")
     finally:
         M.tuning_set(**orig)
+
+
+def test_auto_hash_survives_a_tuning_round_trip(M):
+    # hash_bytes = 0 is the auto size (66 KiB, or 60 KiB where 66 would leave
+    # one workgroup per CU); a get / set round trip keeps it, so a large
+    # z-variance grid (0.25 m, 640 x 640 x 40) still gets the fitting size.
+    rng = np.random.default_rng(5)
+    pair = synth.surface_pair(rng, 30_000, 0.25)
+    mg = M.Grid(pair.origin, pair.dims, pair.voxel, features=3, nb_count=32, nb_zvar=32)
+    assert tuple(mg.dims) == (640, 640, 40)
+    ref = M.Ref(mg, pair.A)
+    P = pair.eta_gt + rng.uniform(-0.05, 0.05, (64, 6))
+    orig = M.tuning_get()
+    try:
+        assert orig["hash_bytes"] == 0, orig
+        item = M.WorkItem(ref, pair.B, P)
+        before = M.Batch([item]).launch()
+        M.tuning_set(**M.tuning_get())
+        assert M.tuning_get()["hash_bytes"] == 0
+        after = M.Batch([item]).launch()
+        _say("launch", before)
+        assert before == after
+        assert before["hash_bytes"] in (60 * 1024, 66 * 1024)
+        assert before["lds_bytes"] <= 80 * 1024
+        # an explicit size is used as given
+        M.tuning_set(**dict(orig, hash_bytes=66 * 1024))
+        assert M.Batch([item]).launch()["hash_bytes"] == 66 * 1024
+    finally:
+        M.tuning_set(**orig)

@@ -325,7 +325,7 @@ def test_urban_full_level_sampled_against_oracle(M, urban):
     P = O.grid_poses(np.zeros(6), c2f["half"], c2f["samples"])
     ref = M.Ref(mg, p.A)
     _say("urban full level", len(P))
-    r = M.eval_poses(ref, p.B, P, want_hist=True)
+    r = M.eval_poses(ref, p.B, P, want_hist=True, want_stats=True)
     torch.cuda.synchronize()
     rng = np.random.default_rng(3)
     idx = np.sort(rng.choice(len(P), 10, replace=False))
@@ -334,13 +334,29 @@ def test_urban_full_level_sampled_against_oracle(M, urban):
         gh = r["hist"][f][torch.from_numpy(idx).cuda()].cpu().numpy().astype(np.int64)
         assert np.array_equal(gh, oh[f].astype(np.int64))
         assert np.max(np.abs(r["mi"][f].cpu().numpy()[idx] - omi[f])) <= MI_TOL
-    # properties that hold at any size: mass = |O| and MI within [0, min(H)]
+    # properties that hold at any size, on every pose of the level (Eqs. 2-5,
+    # overlap step of Alg. 1): histogram mass = |O| from the pose's overlap
+    # box, and 0 <= MI <= min(H(X), H(Y)) with the marginal entropies of each
+    # pose's own histogram
+    st = M.stats_to_numpy(r["stats_raw"], len(P))
+    ext = np.clip(st["hi"] - st["lo"] + 1, 0, None)
+    nO = torch.from_numpy(np.prod(ext.astype(np.int64), axis=1)).cuda()
+    assert torch.equal(torch.from_numpy(st["n_overlap"]).cuda(), nO)
+    assert torch.all(nO > 0)
+
+    def ent(c, N):
+        p = c.to(torch.float64) / N[:, None]
+        return -(torch.where(p > 0, p * torch.log(p), torch.zeros_like(p))).sum(dim=1)
+
     for f, (_, nb) in enumerate(mg.feature_list):
         H = r["hist"][f].to(torch.int64)
         mass = H.sum(dim=(1, 2))
-        assert torch.all(mass > 0)
+        assert torch.equal(mass, nO), f"feature {f}: mass differs from |O|"
+        N = mass.to(torch.float64)
+        hx, hy = ent(H.sum(dim=2), N), ent(H.sum(dim=1), N)
         m = r["mi"][f]
         assert torch.all(m >= -1e-12)
+        assert torch.all(m <= torch.minimum(hx, hy) + 1e-12)
 
 
 def test_coarse_to_fine_matches_oracle(M):

@@ -155,3 +155,45 @@ def test_oversized_request_is_rejected(M):
     na, nq = srv.step()
     assert (na, nq) == (0, 0)
     srv.close()
+
+
+def test_failing_and_degenerate_requests_leave_the_others_unchanged(M):
+    # Failure isolation: in a mix of six, one request fails at its first level
+    # (a grid 1000 voxels tall, more than a brick's voxel hash can hold: the
+    # evaluator rejects it as unsupported), one has an all-NaN scan B (every
+    # point skipped: MI = 0 at every pose) and one an empty scan A (empty
+    # overlap everywhere).  The other three must finish bit-identical to their
+    # runs alone, the degenerate ones must equal theirs alone too, and every
+    # arena block must be back once the server is idle.
+    qs = _requests(3, seed=31)
+    nan_q = dict(qs[0])
+    nan_q["B"] = np.full_like(qs[0]["B"], np.nan)
+    empty_q = dict(qs[1])
+    empty_q["A"] = np.zeros((3, 0), np.float32)
+    tall = dict(qs[2])
+    tall.update(origin=(-1.0, -1.0, -1.0), dims=(8, 8, 1000), voxel=0.25)
+    srv = M.Server(arena_bytes=4 << 30, max_active=8)
+    info0 = srv.info()
+    assert info0["heap_free"] == info0["heap_bytes"]
+    order = [qs[0], tall, nan_q, qs[1], empty_q, qs[2]]
+    ids = [_submit(srv, q) for q in order[:3]]
+    srv.step()
+    ids += [_submit(srv, q) for q in order[3:]]
+    res = _drain(srv, ids)
+    for j, (q, rid) in enumerate(zip(order, ids)):
+        r = res[rid]
+        _say("request", j, "state", r["state"], "status", r["status"], "mi", r["mi"])
+        if q is tall:
+            assert r["state"] == M.REQ_FAILED and r["status"] == M.MI_E_UNSUPPORTED, r
+            continue
+        assert r["state"] == M.REQ_DONE and r["levels_done"] == 3, r
+        pose, best = _alone(M, q)
+        assert np.array_equal(r["pose"], pose), (j, r["pose"], pose)
+        assert r["mi"] == best, (j, r["mi"], best)
+        if q is nan_q or q is empty_q:
+            assert r["mi"] == 0.0
+    info = srv.info()
+    assert info["heap_free"] == info["heap_bytes"], info
+    for rid in ids:
+        srv.release(rid)
+    srv.close()
