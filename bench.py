@@ -1,44 +1,44 @@
 """Benchmark of the MI scan-alignment hot path on one MI355X.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
-                    [--workload c2f|batched|uneven] [--pairs N] [--calibrate-copy]
+                    [--workload all|uneven|c2f|batched|serving|accuracy|surface]
+                    [--calibrate-copy]
 
-Default workload (one step): a full 6-DOF coarse-to-fine alignment of a
-realistic scan pair -- two synthetic 64-ring spinning-scanner scans (~115k
-points each) of a 160 x 160 m urban scene, 0.5 m voxels over 320 x 320 x 20,
-point-count and z-variance features at 32 bins each -- i.e. scan A's resident
-feature map, then 3 levels of 5^6 = 15,625 candidate poses (46,875 MI
-evaluations), each level one batched launch plus the argmax read back.
-Inputs are resident in HBM before the timed region.
+Default (--workload all) prints one JSON line whose headline is the uneven
+batch: 64 surface-sampled scan pairs, points log-uniform in 10k-300k, voxels
+0.25 / 0.5 / 1 m (grids up to 640 x 640 x 40), count + z-variance features at
+32 bins, 4096 candidate 6-DOF poses per pair (262,144 MI evaluations), all in
+one batch per step.  A step is one execution of that batch; K steps are timed
+after W warm-up steps, inputs resident in HBM.  The same line carries, under
+"workloads", the other configured workloads, each with its own throughput,
+roofline and CPU-oracle baseline:
 
-Other workloads (same JSON line, their own config):
-  batched  the tiny scan pair (~20k / ~14k points, 1 m voxels, 64 x 64 x 10,
-           point count at 32 bins) with 8^6 = 262,144 candidate poses in one
-           batch, replayed as one captured HIP graph per step;
-  uneven   N surface-sampled pairs (points log-uniform in 10k-300k, voxels
-           0.25 / 0.5 / 1 m, count + z-variance at 32 bins) with 4096 random
-           poses each, all in one batch per step;
-  accuracy the accuracy protocol of the paper's experiments on synthetic
-           stand-ins: a reference scan and query scans from 1-10 m away (and
-           from 2-20 deg of heading), 1 m voxels, each aligned from the identity
-           by the simplex search with the paper's initial simplex, for both
-           features; reports alignments/s and error / success per level;
-  surface  the cost surfaces of the paper's Fig. 6: MI over a (tx, ty) grid
-           and over heading around the true pose, both features;
+  c2f      a realistic pair: two 64-ring spinning-scanner scans (~115k points
+           each) of a 160 x 160 m urban scene, 0.5 m voxels over 320 x 320 x 20,
+           both features at 32 bins; 3 coarse-to-fine levels of 5^6 poses, and
+           a finer search (7,7,5,5,5,9 nodes, 4 levels, shrink 3) for accuracy;
+  batched  the tiny pair (~20k / ~14k points, 1 m voxels, 64 x 64 x 10, count at
+           32 bins) with 8^6 = 262,144 poses in one batch, replayed as one
+           captured HIP graph;
   serving  alignment requests (surface-sampled pairs, 20k-250k points, 0.5 or
            1 m voxels, 3 levels x 4^6 poses) arriving as Poisson processes at
-           the given rates, served by the continuous-batching loop; reports
-           throughput and p50/p99 latency per rate against one request at a
-           time (batched per request, and the plain per-pose path).
---features joint|weighted (c2f workload) runs the same search on the joint count x
-z-variance feature, or on both features weighted equally.
+           50, 200 and 800 req/s, 2,000 requests per rate, served by the
+           continuous-batching loop: throughput and p50/p99 latency against one
+           request at a time.
+
+Each workload alone: --workload NAME (its own line).  accuracy and surface
+run the paper's accuracy protocol and cost surfaces on synthetic stand-ins.
 --calibrate-copy runs a plain 1 GiB device copy, the reference kernel that
 scales the HBM byte counters of a profile.
 
-Prints one JSON line: MI pose evals/s (value), Gpoint-transforms/s, the
-roofline of the dominant kernel (the batched evaluator, timed with HIP events
-on its own stream), the per-pose plain path on a sample for comparison, and
-the CPU oracle timed on a bounded sample of the same workload.
+Rooflines: the evaluator is bound by FP64/integer ALU work (no dense
+contraction, so no MFMA); achieved = 27 algorithmic FP64 operations per
+(point, pose) x the point-poses of a launch / the launch's mean duration
+(HIP events on the launch stream during the timed region), against
+256 CU x 4 SIMD x 16 lanes x 2.4 GHz.  traffic is the launch's HBM bytes from
+the committed counter profile of that workload, while the kernel source is
+unchanged since it was taken.  cpu_baseline is the FP64 CPU oracle timed on
+a bounded sample of the same workload on this host's cores.
 """
 from __future__ import annotations
 
@@ -61,6 +61,12 @@ PEAK_FP64_OPS = 256 * 4 * 16 * 2.4e9
 # 3 sub + 3 mul + 3 floor for the voxel coordinate and index.
 OPS_PER_POINT_POSE = 27
 
+EVAL_SOURCE = os.path.join(ROOT, "paper_1709_06948_amd", "csrc", "k_eval.hip")
+TRAFFIC_FILES = {
+    "uneven": os.path.join(ROOT, "profiles", "k_eval_uneven_64pairs_traffic.md"),
+    "c2f": os.path.join(ROOT, "profiles", "k_eval_urban_c2f_traffic.md"),
+}
+
 
 def _args():
     ap = argparse.ArgumentParser()
@@ -69,33 +75,37 @@ def _args():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--plain-sample", type=int, default=96)
-    ap.add_argument("--cpu-sample", type=int, default=0,
-                    help="level-0 poses the CPU oracle times (0: all of level 0)")
-    ap.add_argument("--workload", choices=("c2f", "batched", "uneven", "serving", "accuracy",
-                                           "surface"), default="c2f")
+    ap.add_argument("--cpu-per-pair", type=int, default=16,
+                    help="uneven batch: poses of each pair the CPU oracle times")
+    ap.add_argument("--workload", choices=("all", "uneven", "c2f", "batched", "serving",
+                                           "accuracy", "surface"), default="all")
     ap.add_argument("--seeds", type=int, default=3)
     ap.add_argument("--features", choices=("count+zvar", "joint", "weighted"), default="count+zvar",
                     help="c2f workload: the features and objective (default: both features, "
                          "search on MI-VARZ)")
     ap.add_argument("--pairs", type=int, default=64)
     ap.add_argument("--rates", default="50,200,800")
-    ap.add_argument("--requests", type=int, default=150)
+    ap.add_argument("--requests", type=int, default=2000)
     ap.add_argument("--pool", type=int, default=24)
     ap.add_argument("--slots", type=int, default=32)
     ap.add_argument("--calibrate-copy", action="store_true")
     return ap.parse_args()
 
 
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_eval_urban_c2f_traffic.md")
-EVAL_SOURCE = os.path.join(ROOT, "paper_1709_06948_amd", "csrc", "k_eval.hip")
+def _cores() -> int:
+    return len(os.sched_getaffinity(0))
 
 
-def _measured_traffic():
-    """HBM bytes per evaluator launch from the committed counter profile, or
-    None when the kernel source has changed since the counters were taken."""
+def _measured_traffic(workload):
+    """HBM bytes per evaluator launch from the committed counter profile of the
+    workload, or None when there is none or the kernel source has changed
+    since the counters were taken."""
     import hashlib
+    path = TRAFFIC_FILES.get(workload)
+    if not path:
+        return None
     try:
-        text = open(TRAFFIC_FILE).read()
+        text = open(path).read()
         src = hashlib.sha256(open(EVAL_SOURCE, "rb").read()).hexdigest()
     except OSError:
         return None
@@ -112,6 +122,40 @@ def _measured_traffic():
         return None
 
 
+def _roofline(prof, workload, **extra):
+    """ALU roofline of the evaluator from the library's stage timings (HIP
+    events recorded on the launch stream around every evaluator launch)."""
+    launches = max(prof["eval_launches"], 1)
+    ms = prof["eval_ms"] / launches
+    pp = prof["point_poses"] / launches
+    achieved = OPS_PER_POINT_POSE * pp / (ms * 1e-3) if ms > 0 else 0.0
+    out = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP64_OPS / 1e12,
+           "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_OPS,
+           "traffic": _measured_traffic(workload), "kernel": "k_eval", "avg_launch_ms": ms,
+           "point_poses_per_launch": pp, "eval_launches": prof["eval_launches"]}
+    out.update(extra)
+    return out
+
+
+def _parallel(fn, args):
+    """fn over args in forked worker processes (before any GPU work), in order."""
+    import multiprocessing as mp
+    n = max(1, min(16, _cores(), len(args)))
+    if n == 1:
+        return [fn(x) for x in args]
+    with mp.get_context("fork").Pool(n) as pool:
+        return pool.map(fn, args, chunksize=1)
+
+
+def _line(metric, value, unit, steps, warmup, ms_per_step, config, **extra):
+    out = {"metric": metric, "value": value, "unit": unit, "n_gpus": 1, "steps": steps,
+           "warmup": warmup, "ms_per_step": ms_per_step, "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+           "config": config}
+    out.update(extra)
+    return out
+
+
 def _calibrate_copy():
     import torch
     n = 1 << 28  # 1 GiB of float32
@@ -124,35 +168,88 @@ def _calibrate_copy():
           flush=True)
 
 
-def main():
-    a = _args()
-    if a.gpus != 1:
-        print(json.dumps({"error": "this benchmark runs on one GPU only; pose sets are not "
-                                   "sharded over several GPUs",
-                          "n_gpus": a.gpus}), flush=True)
-        sys.exit(2)
-    if a.calibrate_copy:
-        _calibrate_copy()
-        return
-    if a.workload == "serving":
-        return _bench_serving(a)
-    if a.workload == "accuracy":
-        return _bench_accuracy(a)
-    if a.workload == "surface":
-        return _bench_surface(a)
-    if a.workload != "c2f":
-        return _bench_batch(a)
+# --------------------------------------------------------------- uneven batch
+
+UNEVEN_DESC = ("uneven batch: {n} surface-sampled scan pairs, points log-uniform in 10k-300k, "
+               "voxels 0.25/0.5/1 m (grids up to 640x640x40), count + z-variance 32 bins, 4096 "
+               "random 6-DOF poses per pair, all in one batch per step")
+
+
+def _uneven_pair(j):
+    from paper_1709_06948_amd import synth
+    return synth.uneven_pair(j)
+
+
+def _run_uneven(a, work):
+    import torch
+
+    from paper_1709_06948_amd import mi
+
+    items = []
+    for pair, poses in work:
+        grid = mi.Grid(pair.origin, pair.dims, pair.voxel,
+                       features=mi.FEAT_COUNT | mi.FEAT_ZVAR, nb_count=32, nb_zvar=32)
+        items.append(mi.WorkItem(mi.Ref(grid, pair.A), pair.B, poses))
+    torch.cuda.synchronize()
+    batch = mi.Batch(items)
+    K = sum(it.K for it in items)
+    point_poses = sum(it.K * it.xyz_b.shape[1] for it in items)
+    for _ in range(a.warmup):
+        batch.execute()
+    torch.cuda.synchronize()
+    mi.profile_enable(True)
+    t0 = time.perf_counter()
+    for _ in range(a.steps):
+        batch.execute()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    prof = mi.profile_read()
+    mi.profile_enable(False)
+    value = K * a.steps / dt
+    res = {"value": value, "ms_per_step": dt * 1e3 / a.steps, "steps": a.steps,
+           "warmup": a.warmup,
+           "config": {"workload": UNEVEN_DESC.format(n=len(items)), "evals_per_step": K,
+                      "pairs": len(items), "point_poses_per_step": point_poses},
+           "gpoint_transforms_per_s": point_poses * a.steps / dt / 1e9,
+           "roofline": _roofline(prof, "uneven",
+                                 cells_or_frames_ms_per_step=prof["frames_ms"] / a.steps)}
+    del batch
+    res["cpu_baseline"] = None
+    if not a.no_cpu_baseline and a.cpu_per_pair > 0:
+        import oracle as O
+        cores = _cores()
+        n_eval, tc = 0, 0.0
+        for j, (pair, poses) in enumerate(work):
+            og = O.Grid(pair.origin, pair.dims, pair.voxel, features=3, nb_count=32, nb_zvar=32)
+            rng = np.random.default_rng(1000 + j)
+            sel = np.sort(rng.choice(len(poses), min(a.cpu_per_pair, len(poses)), replace=False))
+            t0 = time.perf_counter()
+            O.eval_poses(og, pair.A, pair.B, poses[sel], nthreads=cores)
+            tc += time.perf_counter() - t0
+            n_eval += len(sel)
+        res["cpu_baseline"] = {
+            "value": n_eval / tc, "unit": "MI pose evals/s", "cores": cores, "kind": "oracle",
+            "sample": f"{a.cpu_per_pair} seeded random poses of each of the {len(work)} pairs "
+                      f"({n_eval} evaluations) of the same batch, FP64 dense oracle, {tc:.1f} s"}
+    return res
+
+
+# ------------------------------------------------------------- coarse-to-fine
+
+# A finer search than the configured one (nodes per axis, levels, shrink), with
+# the same level-0 half-ranges: it recovers the urban pair's true pose.
+FINE_SAMPLES = (7, 7, 5, 5, 5, 9)
+FINE_LEVELS, FINE_SHRINK = 4, 3.0
+
+
+def _run_c2f(a, pair):
     import torch
 
     from paper_1709_06948_amd import mi, synth
 
-    torch.cuda.set_device(0)
-    pair = synth.urban_pair()
     c2f = synth.urban_c2f_params()
-    # features and search objective: the configured pair of features with the search on
-    # MI-VARZ, the joint feature (8 x 8 part bins, 50 values), or both features weighted equally
     fkw = dict(features=mi.FEAT_COUNT | mi.FEAT_ZVAR, nb_count=32, nb_zvar=32)
-    slot, weights, fdesc = 1, None, "count + z-variance 32 bins"
+    slot, weights, fdesc = 1, None, "count + z-variance 32 bins, search on MI-VARZ"
     if a.features == "joint":
         fkw = dict(features=mi.FEAT_JOINT, nb_count=8, nb_zvar=8)
         slot, fdesc = 0, "joint count x z-variance feature (8 x 8 part bins, 50 values)"
@@ -165,183 +262,135 @@ def main():
     init = np.zeros(6)
     levels = int(c2f["levels"])
     K_level = int(np.prod(c2f["samples"]))
-    evals_per_step = levels * K_level      # one eval = one pose, both features from one pass
+    evals_per_step = levels * K_level
 
     def step():
         ref = mi.Ref(grid, A)
-        pose, best = mi.align_coarse_to_fine(ref, B, init, c2f["half"], c2f["samples"], levels,
-                                             c2f["shrink"], feature_slot=slot, weights=weights)
-        return pose, best
+        return mi.align_coarse_to_fine(ref, B, init, c2f["half"], c2f["samples"], levels,
+                                       c2f["shrink"], feature_slot=slot, weights=weights)
 
     for _ in range(a.warmup):
         step()
     torch.cuda.synchronize()
     mi.profile_enable(True)
-    torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(a.steps):
         pose, best = step()
     torch.cuda.synchronize()
-    t1 = time.perf_counter()
+    dt = time.perf_counter() - t0
     prof = mi.profile_read()
     mi.profile_enable(False)
-    dt = t1 - t0
-    ms_per_step = dt * 1e3 / a.steps
-    evals = evals_per_step * a.steps
-    value = evals / dt
-    gpts = evals * n_b / dt / 1e9
-
-    eval_ms_avg = prof["eval_ms"] / max(prof["eval_launches"], 1)
-    pp_per_launch = prof["point_poses"] / max(prof["eval_launches"], 1)
-    achieved = OPS_PER_POINT_POSE * pp_per_launch / (eval_ms_avg * 1e-3)
-    roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP64_OPS / 1e12,
-                "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_OPS,
-                "traffic": _measured_traffic(),
-                "kernel": "k_eval", "avg_launch_ms": eval_ms_avg,
-                "point_poses_per_launch": pp_per_launch,
-                "frames_ms_per_step": prof["frames_ms"] / a.steps,
-                "eval_ms_per_step": prof["eval_ms"] / a.steps}
-    err = np.abs(pose - pair.eta_gt)
-
-    # plain per-pose launch path on a sample of level-0 poses
-    plain = None
+    value = evals_per_step * a.steps / dt
+    ref = mi.Ref(grid, A)
+    fine_pose, _ = mi.align_coarse_to_fine(ref, B, init, c2f["half"], FINE_SAMPLES, FINE_LEVELS,
+                                           FINE_SHRINK, feature_slot=slot, weights=weights)
+    res = {"value": value, "unit": "evals/s", "ms_per_step": dt * 1e3 / a.steps,
+           "steps": a.steps, "warmup": a.warmup,
+           "config": {"workload": "urban scan pair, 6-DOF coarse-to-fine: 2 x ~115k-point 64-ring "
+                                  f"scans, 0.5 m voxels 320x320x20, {fdesc}, 3 levels x 5^6 poses",
+                      "evals_per_step": evals_per_step, "n_b": int(n_b), "n_a": int(A.shape[1])},
+           "gpoint_transforms_per_s": evals_per_step * n_b * a.steps / dt / 1e9,
+           "roofline": _roofline(prof, "c2f" if a.features == "count+zvar" else "",
+                                 frames_ms_per_step=prof["frames_ms"] / a.steps,
+                                 eval_ms_per_step=prof["eval_ms"] / a.steps),
+           "result": {"pose": [float(v) for v in pose], "mi": best,
+                      "abs_err_vs_truth": [float(v) for v in np.abs(pose - pair.eta_gt)]},
+           "fine_search": {"samples": list(FINE_SAMPLES), "levels": FINE_LEVELS,
+                           "shrink": FINE_SHRINK, "pose": [float(v) for v in fine_pose],
+                           "abs_err_vs_truth": [float(v) for v in np.abs(fine_pose - pair.eta_gt)]}}
     if a.plain_sample > 0:
         P0 = synth.level_poses(init, c2f["half"], c2f["samples"])
         rng = np.random.default_rng(1)
         Ps = P0[np.sort(rng.choice(len(P0), a.plain_sample, replace=False))]
-        ref = mi.Ref(grid, A)
         mi.eval_poses_plain(ref, B, Ps[:4])
         torch.cuda.synchronize()
         tp0 = time.perf_counter()
         mi.eval_poses_plain(ref, B, Ps)
         torch.cuda.synchronize()
         tp = time.perf_counter() - tp0
-        plain = {"evals_per_s": len(Ps) / tp, "sample": f"{len(Ps)} level-0 poses",
-                 "batched_speedup": value / (len(Ps) / tp)}
-
-    cpu = None
+        res["plain_path"] = {"evals_per_s": len(Ps) / tp, "sample": f"{len(Ps)} level-0 poses",
+                             "batched_speedup": value / (len(Ps) / tp)}
+    res["cpu_baseline"] = None
     if not a.no_cpu_baseline:
         import oracle as O
         og = O.Grid(pair.origin, pair.dims, pair.voxel, **fkw)
-        P0 = synth.level_poses(init, c2f["half"], c2f["samples"])
-        if 0 < a.cpu_sample < len(P0):
-            rng = np.random.default_rng(2)
-            Ps = P0[np.sort(rng.choice(len(P0), a.cpu_sample, replace=False))]
-            what = f"{len(Ps)} random poses of level 0"
-        else:
-            Ps = P0
-            what = f"all {len(Ps)} poses of level 0"
-        cores = len(os.sched_getaffinity(0))
+        Ps = synth.level_poses(init, c2f["half"], c2f["samples"])
+        cores = _cores()
         O.eval_poses(og, pair.A, pair.B, Ps[:cores], nthreads=cores)
         tc0 = time.perf_counter()
         O.eval_poses(og, pair.A, pair.B, Ps, nthreads=cores)
         tc = time.perf_counter() - tc0
-        cpu = {"value": len(Ps) / tc, "unit": "MI pose evals/s", "cores": cores, "kind": "oracle",
-               "sample": f"{what} of the same workload, FP64 dense oracle, {tc:.1f} s"}
-
-    out = {
-        "metric": "MI pose evals/s",
-        "value": value,
-        "unit": "evals/s",
-        "n_gpus": 1,
-        "steps": a.steps,
-        "warmup": a.warmup,
-        "ms_per_step": ms_per_step,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f64",
-        "data": "synthetic",
-        "config": {"workload": "urban scan pair, 6-DOF coarse-to-fine: 2 x ~115k-point 64-ring "
-                               f"scans, 0.5 m voxels 320x320x20, {fdesc}, "
-                               "3 levels x 5^6 poses",
-                   "evals_per_step": evals_per_step, "n_b": int(n_b), "n_a": int(A.shape[1])},
-        "gpoint_transforms_per_s": gpts,
-        "roofline": roofline,
-        "plain_path": plain,
-        "cpu_baseline": cpu,
-        "result": {"pose": [float(v) for v in pose], "mi": best,
-                   "abs_err_vs_truth": [float(v) for v in err]},
-    }
-    print(json.dumps(out), flush=True)
+        res["cpu_baseline"] = {
+            "value": len(Ps) / tc, "unit": "MI pose evals/s", "cores": cores, "kind": "oracle",
+            "sample": f"all {len(Ps)} poses of level 0 of the same workload, FP64 dense oracle, "
+                      f"{tc:.1f} s"}
+    return res
 
 
-def _bench_batch(a):
-    """Batched (8^6 poses, one graph) and uneven-batch workloads."""
+# -------------------------------------------------------------------- batched
+
+def _run_batched(a, pair):
     import torch
 
     from paper_1709_06948_amd import mi, synth
 
-    torch.cuda.set_device(0)
-    if a.workload == "batched":
-        pair = synth.tiny_pair()
-        grid = mi.Grid(pair.origin, pair.dims, pair.voxel, features=mi.FEAT_COUNT, nb_count=32)
-        items = [mi.WorkItem(mi.Ref(grid, pair.A), pair.B, synth.grid8_poses(8))]
-        workload = ("tiny scan pair, 8^6 = 262,144 6-DOF poses in one batch (one captured HIP "
-                    "graph per step): ~20k / ~14k surface points, 1 m voxels 64x64x10, count 32 "
-                    "bins")
-    else:
-        work = synth.uneven_batch(n_pairs=a.pairs)
-        items = []
-        for pair, poses in work:
-            grid = mi.Grid(pair.origin, pair.dims, pair.voxel,
-                           features=mi.FEAT_COUNT | mi.FEAT_ZVAR, nb_count=32, nb_zvar=32)
-            items.append(mi.WorkItem(mi.Ref(grid, pair.A), pair.B, poses))
-        workload = (f"uneven batch: {a.pairs} surface-sampled pairs, points log-uniform in "
-                    "10k-300k, voxels 0.25/0.5/1 m (grids up to 640x640x40), count + z-variance "
-                    "32 bins, 4096 random 6-DOF poses per pair, one batch per step")
+    grid = mi.Grid(pair.origin, pair.dims, pair.voxel, features=mi.FEAT_COUNT, nb_count=32)
+    poses = synth.grid8_poses(8)
+    items = [mi.WorkItem(mi.Ref(grid, pair.A), pair.B, poses)]
     torch.cuda.synchronize()
     batch = mi.Batch(items)
-    K = sum(it.K for it in items)
-    point_poses = sum(it.K * it.xyz_b.shape[1] for it in items)
-    graph = None
-    if a.workload == "batched":
-        s = torch.cuda.Stream()
-        s.wait_stream(torch.cuda.current_stream())
-        with torch.cuda.stream(s):
-            batch.execute(stream=s)
-        torch.cuda.current_stream().wait_stream(s)
-        torch.cuda.synchronize()
-        graph = torch.cuda.CUDAGraph()
-        with torch.cuda.graph(graph):
-            batch.execute()
-    run = graph.replay if graph is not None else batch.execute
-    for _ in range(a.warmup):
-        run()
+    K = len(poses)
+    point_poses = K * pair.B.shape[1]
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        batch.execute(stream=s)
+    torch.cuda.current_stream().wait_stream(s)
     torch.cuda.synchronize()
-    # stage events cannot sit inside a graph: time the stages on an eager run
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        batch.execute()
+    for _ in range(a.warmup):
+        graph.replay()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(a.steps):
+        graph.replay()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    # stage events cannot sit inside a graph: the evaluator's duration comes from
+    # eager executions of the same batch right after the timed replays
     mi.profile_enable(True)
-    batch.execute()
+    for _ in range(2):
+        batch.execute()
     torch.cuda.synchronize()
     prof = mi.profile_read()
     mi.profile_enable(False)
-    t0 = time.perf_counter()
-    for _ in range(a.steps):
-        run()
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
     value = K * a.steps / dt
-    eval_ms_avg = prof["eval_ms"] / max(prof["eval_launches"], 1)
-    pp_per_launch = prof["point_poses"] / max(prof["eval_launches"], 1)
-    achieved = OPS_PER_POINT_POSE * pp_per_launch / (eval_ms_avg * 1e-3)
-    out = {
-        "metric": "MI pose evals/s", "value": value, "unit": "evals/s", "n_gpus": 1,
-        "steps": a.steps, "warmup": a.warmup, "ms_per_step": dt * 1e3 / a.steps,
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
-        "data": "synthetic",
-        "config": {"workload": workload, "evals_per_step": K, "pairs": len(items)},
-        "gpoint_transforms_per_s": point_poses * a.steps / dt / 1e9,
-        "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP64_OPS / 1e12,
-                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_OPS, "traffic": None,
-                     "kernel": "k_eval", "avg_launch_ms": eval_ms_avg,
-                     "eval_launches_per_step": prof["eval_launches"],
-                     "frames_ms_per_step": prof["frames_ms"], "eval_ms_per_step": prof["eval_ms"]},
-        "cpu_baseline": None,
-    }
-    print(json.dumps(out), flush=True)
+    res = {"value": value, "unit": "evals/s", "ms_per_step": dt * 1e3 / a.steps,
+           "steps": a.steps, "warmup": a.warmup,
+           "config": {"workload": "tiny scan pair, 8^6 = 262,144 6-DOF poses in one batch (one "
+                                  "captured HIP graph per step): ~20k / ~14k surface points, 1 m "
+                                  "voxels 64x64x10, count 32 bins", "evals_per_step": K},
+           "gpoint_transforms_per_s": point_poses * a.steps / dt / 1e9,
+           "roofline": _roofline(prof, "batched", timed_on="2 eager executions after the replays")}
+    res["cpu_baseline"] = None
+    if not a.no_cpu_baseline:
+        import oracle as O
+        og = O.Grid(pair.origin, pair.dims, pair.voxel, features=1, nb_count=32)
+        Ps = poses[::128]
+        cores = _cores()
+        tc0 = time.perf_counter()
+        O.eval_poses(og, pair.A, pair.B, Ps, nthreads=cores)
+        tc = time.perf_counter() - tc0
+        res["cpu_baseline"] = {
+            "value": len(Ps) / tc, "unit": "MI pose evals/s", "cores": cores, "kind": "oracle",
+            "sample": f"every 128th of the 262,144 poses ({len(Ps)}), FP64 dense oracle, {tc:.1f} s"}
+    return res
 
 
-# Initial simplex of the paper's experiments (m, m, m, rad, rad, rad).
+# ------------------------------------------------- accuracy and cost surfaces
+
 NM_STEP = [8.0, 8.0, 1.0, 0.1, 0.1, 0.8]
 # Success: final error under one voxel (1 m) in translation and 2 deg in rotation.
 SUCCESS_M, SUCCESS_DEG = 1.0, 2.0
@@ -501,24 +550,28 @@ def _bench_surface(a):
     print(json.dumps(out), flush=True)
 
 
-def _serving_pool(n_pool):
-    """Request pool: pairs drawn as the serving workload specifies (points
-    log-uniform in [20k, 250k], voxel 0.5 or 1 m, 160 x 160 x 10 m scenes),
-    each with a seeded prior near its true pose."""
+# -------------------------------------------------------------------- serving
+
+def _serving_request(spec):
+    """One request of the serving pool: a surface-sampled pair as the serving
+    workload specifies (points log-uniform in [20k, 250k], voxel 0.5 or 1 m,
+    160 x 160 x 10 m scenes) with a seeded prior near its true pose."""
     import math
 
     from paper_1709_06948_amd import synth
     d2r = math.pi / 180.0
+    pair = synth.make_request(spec)
+    rng = np.random.default_rng(spec["seed"] + 1)
+    init = pair.eta_gt + np.array([rng.normal(0, 0.5), rng.normal(0, 0.5), 0.0, 0.0, 0.0,
+                                   rng.normal(0, 2 * d2r)])
+    return dict(origin=pair.origin, dims=pair.dims, voxel=pair.voxel, A=pair.A, B=pair.B,
+                init=init, eta_gt=pair.eta_gt)
+
+
+def _serving_specs(n_pool):
+    from paper_1709_06948_amd import synth
     _, specs = synth.serving_requests(1.0, n_pool)
-    pool = []
-    for sp in specs:
-        pair = synth.make_request(sp)
-        rng = np.random.default_rng(sp["seed"] + 1)
-        init = pair.eta_gt + np.array([rng.normal(0, 0.5), rng.normal(0, 0.5), 0.0, 0.0, 0.0,
-                                       rng.normal(0, 2 * d2r)])
-        pool.append(dict(origin=pair.origin, dims=pair.dims, voxel=pair.voxel, A=pair.A,
-                         B=pair.B, init=init, eta_gt=pair.eta_gt))
-    return pool
+    return specs
 
 
 SERVE_HALF = (3.0, 3.0, 0.2, 2.0 * np.pi / 180, 2.0 * np.pi / 180, 10.0 * np.pi / 180)
@@ -536,15 +589,13 @@ def _fifo_latency(arrivals, service):
     return np.array(lat)
 
 
-def _bench_serving(a):
+def _run_serving(a, pool):
     import threading
 
     import torch
 
     from paper_1709_06948_amd import mi, synth
 
-    torch.cuda.set_device(0)
-    pool = _serving_pool(a.pool)
     K_req = SERVE_LEVELS * int(np.prod(SERVE_SAMPLES))
 
     def submit(srv, q):
@@ -552,8 +603,9 @@ def _bench_serving(a):
                           SERVE_SAMPLES, SERVE_LEVELS, SERVE_SHRINK, features=3, nb_count=32,
                           nb_zvar=32, feature_slot=0)
 
-    # one request at a time: batched per request, and the plain per-pose path on a sample
-    service, plain_rate = [], None
+    # one request at a time: batched per request (every pool pair), and the plain
+    # per-pose path on a sample of one level
+    service = []
     for q in pool:
         g = mi.Grid(q["origin"], q["dims"], q["voxel"], features=3, nb_count=32, nb_zvar=32)
         A = torch.from_numpy(q["A"]).cuda()
@@ -565,7 +617,7 @@ def _bench_serving(a):
                                 SERVE_SHRINK, feature_slot=0)
         torch.cuda.synchronize()
         service.append(time.perf_counter() - t0)
-    service[0] = service[1] if len(service) > 1 else service[0]   # first call warms up
+    service[0] = service[1] if len(service) > 1 else service[0]   # the first call warms up
     q = pool[0]
     g = mi.Grid(q["origin"], q["dims"], q["voxel"], features=3, nb_count=32, nb_zvar=32)
     ref = mi.Ref(g, q["A"])
@@ -580,6 +632,7 @@ def _bench_serving(a):
     plain_service = K_req / plain_rate * mean_pts / q["B"].shape[1]
 
     per_rate = []
+    prof_all = {"eval_ms": 0.0, "eval_launches": 0, "point_poses": 0, "frames_ms": 0.0}
     for rate in [float(r) for r in a.rates.split(",")]:
         rng = np.random.default_rng(int(rate))
         gaps = rng.exponential(1.0 / rate, a.requests)
@@ -602,14 +655,17 @@ def _bench_serving(a):
         mi.profile_enable(True)
         th.start()
         done, steps, lat, t_step = set(), 0, {}, 0.0
+        pending = list(range(a.requests))
         while len(done) < a.requests:
             ts = time.perf_counter()
             na, nq = srv.step()
             t_step += time.perf_counter() - ts
             steps += 1
             now = time.perf_counter() - t_start
-            for j in range(a.requests):
-                if j in done or ids[j] is None:
+            still = []
+            for j in pending:
+                if ids[j] is None:
+                    still.append(j)
                     continue
                 st = srv.poll(ids[j])
                 if st["state"] in (mi.REQ_DONE, mi.REQ_FAILED):
@@ -618,22 +674,33 @@ def _bench_serving(a):
                     done.add(j)
                     lat[j] = now - arrivals[j]
                     srv.release(ids[j])
+                else:
+                    still.append(j)
+            pending = still
             if na == 0 and nq == 0 and len(done) < a.requests:
                 time.sleep(0.0005)
         th.join()
         elapsed = time.perf_counter() - t_start
         prof = mi.profile_read()
         mi.profile_enable(False)
+        for k in prof_all:
+            prof_all[k] += prof[k]
         srv.close()
         L = np.array([lat[j] for j in range(a.requests)])
         svc = np.array([service[o] for o in order])
         one = _fifo_latency(arrivals, svc)
         plain_one = _fifo_latency(arrivals, np.full(a.requests, plain_service))
+        # the second half of the requests: the latency a request meets once the queue has
+        # reached the state this rate drives it to
+        half = slice(a.requests // 2, a.requests)
         per_rate.append({
             "rate_req_s": rate, "requests": a.requests, "steps": steps,
             "throughput_req_s": a.requests / elapsed,
             "evals_per_s": a.requests * K_req / elapsed,
             "p50_s": float(np.percentile(L, 50)), "p99_s": float(np.percentile(L, 99)),
+            "p50_s_second_half": float(np.percentile(L[half], 50)),
+            "p99_s_second_half": float(np.percentile(L[half], 99)),
+            "offered_req_s": float(a.requests / max(arrivals[-1], 1e-9)),
             "max_submit_late_s": float(max(late)),
             "time_in_steps_s": t_step, "elapsed_s": elapsed,
             "gpu_frames_ms": prof["frames_ms"], "gpu_eval_ms": prof["eval_ms"],
@@ -647,22 +714,116 @@ def _bench_serving(a):
         })
         print(json.dumps({"serving_rate": per_rate[-1]}), file=sys.stderr, flush=True)
     best = max(per_rate, key=lambda r: r["evals_per_s"])
-    out = {
-        "metric": "MI pose evals/s", "value": best["evals_per_s"], "unit": "evals/s",
-        "n_gpus": 1, "steps": a.requests, "warmup": 0,
-        "ms_per_step": 1e3 / best["throughput_req_s"], "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
-        "config": {"workload": "serving: Poisson arrivals of alignment requests (surface-sampled "
-                               "pairs, 20k-250k points, 0.5/1 m voxels, count + z-variance 32 "
-                               "bins, 3 levels x 4^6 poses), continuous batching, "
-                               f"{a.slots} slots", "pool": len(pool), "rates": a.rates},
-        "serving": per_rate,
-        "one_request_service_s": {"batched_mean": float(np.mean(service)),
-                                  "plain_estimate": plain_service,
-                                  "plain_evals_per_s": plain_rate},
-        "roofline": None, "cpu_baseline": None,
-    }
+    res = {"value": best["evals_per_s"], "unit": "evals/s", "steps": a.requests, "warmup": 0,
+           "ms_per_step": 1e3 / best["throughput_req_s"],
+           "config": {"workload": "serving: Poisson arrivals of alignment requests (surface-sampled "
+                                  "pairs, 20k-250k points, 0.5/1 m voxels, count + z-variance 32 "
+                                  "bins, 3 levels x 4^6 poses), continuous batching, "
+                                  f"{a.slots} slots", "pool": len(pool), "rates": a.rates,
+                      "requests_per_rate": a.requests},
+           "serving": per_rate,
+           "one_request_service_s": {"batched_mean": float(np.mean(service)),
+                                     "plain_estimate": plain_service,
+                                     "plain_evals_per_s": plain_rate},
+           "roofline": _roofline(prof_all, "serving", over="every evaluator launch of all rates")}
+    res["cpu_baseline"] = None
+    if not a.no_cpu_baseline:
+        import oracle as O
+        cores = _cores()
+        q = pool[0]
+        og = O.Grid(q["origin"], q["dims"], q["voxel"], features=3, nb_count=32, nb_zvar=32)
+        P = synth.level_poses(q["init"], SERVE_HALF, SERVE_SAMPLES)[::8]
+        tc0 = time.perf_counter()
+        O.eval_poses(og, q["A"], q["B"], P, nthreads=cores)
+        tc = time.perf_counter() - tc0
+        per_eval = tc / len(P) * mean_pts / q["B"].shape[1]
+        res["cpu_baseline"] = {
+            "value": len(P) / tc, "unit": "MI pose evals/s", "cores": cores, "kind": "oracle",
+            "request_latency_s_estimate": per_eval * K_req,
+            "capacity_req_s_estimate": 1.0 / (per_eval * K_req),
+            "sample": f"every 8th pose of level 0 of pool request 0 ({len(P)} evaluations, "
+                      f"{q['B'].shape[1]} points), FP64 dense oracle, {tc:.1f} s; one request "
+                      "at a time scaled to the pool's mean point count"}
+    return res
+
+
+
+# ------------------------------------------------------------------------ main
+
+def _sub(res, metric="MI pose evals/s"):
+    """A workload's result as a nested record of the benchmark line."""
+    out = {"metric": metric}
+    out.update(res)
+    return out
+
+
+def _bench_all(a):
+    """Every configured workload; the uneven batch is the headline."""
+    from paper_1709_06948_amd import synth
+
+    t_gen = time.perf_counter()
+    # generation runs in forked workers before this process touches the GPU
+    work = _parallel(_uneven_pair, list(range(a.pairs)))
+    pool = _parallel(_serving_request, _serving_specs(a.pool))
+    urban = synth.urban_pair()
+    tiny = synth.tiny_pair()
+    t_gen = time.perf_counter() - t_gen
+    import torch
+    torch.cuda.set_device(0)
+
+    head = _run_uneven(a, work)
+    del work
+    sub = {"c2f": _sub(_run_c2f(a, urban)), "batched": _sub(_run_batched(a, tiny))}
+    sa = argparse.Namespace(**vars(a))
+    sub["serving"] = _sub(_run_serving(sa, pool))
+    out = _line("MI pose evals/s", head["value"], "evals/s", head["steps"], head["warmup"],
+                head["ms_per_step"], head["config"],
+                gpoint_transforms_per_s=head["gpoint_transforms_per_s"],
+                roofline=head["roofline"], cpu_baseline=head["cpu_baseline"],
+                workloads=sub, generation_s=t_gen)
     print(json.dumps(out), flush=True)
+
+
+def _bench_one(a):
+    """One workload alone, on its own line."""
+    from paper_1709_06948_amd import synth
+    if a.workload == "uneven":
+        work = _parallel(_uneven_pair, list(range(a.pairs)))
+    elif a.workload == "serving":
+        pool = _parallel(_serving_request, _serving_specs(a.pool))
+    import torch
+    torch.cuda.set_device(0)
+    if a.workload == "uneven":
+        res = _run_uneven(a, work)
+    elif a.workload == "c2f":
+        res = _run_c2f(a, synth.urban_pair())
+    elif a.workload == "batched":
+        res = _run_batched(a, synth.tiny_pair())
+    else:
+        res = _run_serving(a, pool)
+    extra = {k: v for k, v in res.items()
+             if k not in ("value", "unit", "steps", "warmup", "ms_per_step", "config")}
+    print(json.dumps(_line("MI pose evals/s", res["value"], "evals/s", res["steps"],
+                           res["warmup"], res["ms_per_step"], res["config"], **extra)), flush=True)
+
+
+def main():
+    a = _args()
+    if a.gpus != 1:
+        print(json.dumps({"error": "this benchmark runs on one GPU only; pose sets are not "
+                                   "sharded over several GPUs",
+                          "n_gpus": a.gpus}), flush=True)
+        sys.exit(2)
+    if a.calibrate_copy:
+        _calibrate_copy()
+        return
+    if a.workload == "all":
+        return _bench_all(a)
+    if a.workload == "accuracy":
+        return _bench_accuracy(a)
+    if a.workload == "surface":
+        return _bench_surface(a)
+    return _bench_one(a)
 
 
 if __name__ == "__main__":

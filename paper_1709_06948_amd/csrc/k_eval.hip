@@ -40,6 +40,7 @@ namespace mi {
 static constexpr uint32_t kEmpty = 0xffffffffu;
 static constexpr uint32_t kNever = 0xfffffffeu;  // never a key, never empty
 static constexpr int kMaxProbe = 32;
+static constexpr uint32_t kNoVoxel = 0xffffffffu;  // bucket entry of a point outside the grid
 
 struct EvalCfgDev {
   int32_t hist_copies, hist_words;
@@ -93,7 +94,7 @@ struct DirectVoxel {
 };
 
 template <bool ZVAR, bool NEAR>
-__device__ __forceinline__ DirectVoxel direct_voxel(const float *xyz, int64_t n, int64_t i,
+__device__ __forceinline__ DirectVoxel direct_voxel(float xf, float yf, float zf,
                                                     const double (&R)[9], double s, double cx,
                                                     double cy, double cz, int nx, int ny, int nz,
                                                     double voxel) {
@@ -101,7 +102,7 @@ __device__ __forceinline__ DirectVoxel direct_voxel(const float *xyz, int64_t n,
   r.in = false;
   r.near = false;
   r.q = 0u;
-  const float xf = ldg(xyz + i), yf = ldg(xyz + n + i), zf = ldg(xyz + 2 * n + i);
+  r.ix = r.iy = r.iz = -1;
   if (!isfinite(xf) || !isfinite(yf) || !isfinite(zf)) return r;
   const double x = xf, y = yf, z = zf;
   const double wx = (R[0] * x + R[1] * y) + R[2] * z;
@@ -205,6 +206,7 @@ __global__ void __launch_bounds__(1024) k_eval(const PairDev *__restrict__ pairs
     const uint32_t kind0 = P.kind[0], kind1 = P.kind[1];
     const int nbc = P.nbc, nbz = P.nbz;
     const bool count_default = P.count_default != 0;
+    const int zvar_zero = P.zvar_zero_edges;
     const uint8_t *binA0 = P.binA[0], *binA1 = P.binA[1];
     const int BY = P.stripe_h, NS = P.n_stripes, Q = P.pieces, RM = BY + 2;
     const int kxb = P.kx_bits, kyb = P.ky_bits;
@@ -234,16 +236,39 @@ __global__ void __launch_bounds__(1024) k_eval(const PairDev *__restrict__ pairs
       const double fs = Fr.s;
       const float *xyz = Fr.xyz;
       const int64_t nb = Fr.n;
+      // stripe of a voxel row, iy / BY, by a multiply-high where that is exact:
+      // with m = ceil(2^32 / BY), m * BY - 2^32 < BY, so iy * m / 2^32 has the
+      // quotient's integer part while iy * BY < 2^32 (any row below 2^26)
+      const uint32_t by_mag = (uint32_t)(((1ull << 32) + (uint64_t)BY - 1ull) / (uint64_t)BY);
+      const bool by_mul = BY > 1 && ny <= (1 << 26);  // (for BY = 1, m = 2^32 needs 33 bits)
+      auto stripe_of = [&](int iy) -> uint32_t {
+        return by_mul ? __umulhi((uint32_t)iy, by_mag) : (uint32_t)iy / (uint32_t)BY;
+      };
       for (int i = tid; i < NS; i += T) scur[i] = 0u;
       __syncthreads();
-      for (int64_t i = tid; i < nb; i += T) {
-        const DirectVoxel dv = direct_voxel<ZVAR, NEAR>(xyz, nb, i, R, fs, cx, cy, cz, nx, ny, nz,
-                                                         P.voxel);
-        if (!dv.in) continue;
-        atomicAdd(&scur[dv.iy / BY], 1u);
-        if (NEAR && dv.near && dv.ix >= alo0 && dv.ix <= ahi0 && dv.iy >= alo1 &&
-            dv.iy <= ahi1 && dv.iz >= alo2 && dv.iz <= ahi2)
-          ++nnear;
+      // Count pass: only the y row of the transform decides the stripe.  Four
+      // points per lane are loaded before any is used, so a wave waits on
+      // memory once per four points.
+      for (int64_t i0 = tid; i0 < nb; i0 += 4 * (int64_t)T) {
+        float fx[4], fy[4], fz[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const int64_t i = i0 + (int64_t)j * T;
+          const int64_t ii = i < nb ? i : 0;
+          fx[j] = ldg(xyz + ii);
+          fy[j] = ldg(xyz + nb + ii);
+          fz[j] = ldg(xyz + 2 * nb + ii);
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const int64_t i = i0 + (int64_t)j * T;
+          if (i < nb && isfinite(fx[j]) && isfinite(fy[j]) && isfinite(fz[j])) {
+            const double x = fx[j], y = fy[j], z = fz[j];
+            const double uy = ((R[3] * x + R[4] * y) + R[5] * z) * fs + cy;
+            const int iy = (int)floor(uy);
+            if ((uint32_t)iy < (uint32_t)ny) atomicAdd(&scur[stripe_of(iy)], 1u);
+          }
+        }
       }
       __syncthreads();
       if (wid == 0) {  // exclusive scan of the stripe counts
@@ -265,15 +290,46 @@ __global__ void __launch_bounds__(1024) k_eval(const PairDev *__restrict__ pairs
         if (lane == 0) soff[NS] = run;
       }
       __syncthreads();
-      for (int64_t i = tid; i < nb; i += T) {
-        const DirectVoxel dv = direct_voxel<ZVAR, false>(xyz, nb, i, R, fs, cx, cy, cz, nx, ny,
-                                                          nz, P.voxel);
-        if (!dv.in) continue;
-        const int st = dv.iy / BY;
-        const uint32_t pos = atomicAdd(&scur[st], 1u);
-        const uint32_t key = ((uint32_t)dv.iz << (kxb + kyb)) |
-                             ((uint32_t)(dv.iy - st * BY) << kxb) | (uint32_t)dv.ix;
-        mine[pos] = make_uint2(key, dv.q);
+      // Scatter pass: the whole voxel.  Every point counted above gets an entry
+      // in its stripe's bucket; one outside the grid in x or z is marked by
+      // q = kNoVoxel and skipped by the bricks.
+      for (int64_t i0 = tid; i0 < nb; i0 += 4 * (int64_t)T) {
+        float fx[4], fy[4], fz[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const int64_t i = i0 + (int64_t)j * T;
+          const int64_t ii = i < nb ? i : 0;
+          fx[j] = ldg(xyz + ii);
+          fy[j] = ldg(xyz + nb + ii);
+          fz[j] = ldg(xyz + 2 * nb + ii);
+        }
+        uint32_t pos[4], key[4], qv[4];
+        bool put[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const int64_t i = i0 + (int64_t)j * T;
+          const DirectVoxel dv = direct_voxel<ZVAR, NEAR>(fx[j], fy[j], fz[j], R, fs, cx, cy, cz,
+                                                           nx, ny, nz, P.voxel);
+          put[j] = i < nb && (uint32_t)dv.iy < (uint32_t)ny;
+          pos[j] = 0u;
+          key[j] = 0u;
+          qv[j] = kNoVoxel;
+          if (put[j]) {
+            const uint32_t st = stripe_of(dv.iy);
+            pos[j] = atomicAdd(&scur[st], 1u);
+            if (dv.in) {
+              key[j] = ((uint32_t)dv.iz << (kxb + kyb)) | ((uint32_t)(dv.iy - (int)st * BY) << kxb) |
+                       (uint32_t)dv.ix;
+              qv[j] = dv.q;
+              if (NEAR && dv.near && dv.ix >= alo0 && dv.ix <= ahi0 && dv.iy >= alo1 &&
+                  dv.iy <= ahi1 && dv.iz >= alo2 && dv.iz <= ahi2)
+                ++nnear;
+            }
+          }
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+          if (put[j]) mine[pos[j]] = make_uint2(key[j], qv[j]);
       }
       __syncthreads();
     }
@@ -531,7 +587,7 @@ __global__ void __launch_bounds__(1024) k_eval(const PairDev *__restrict__ pairs
                   const bool val = k + i * W < nch && idx < bend;
                   const int ix = (int)(key[i] & kxm);
                   const int iy = SY0 + (int)((key[i] >> kxb) & kym);
-                  inb[i] = val && (uint32_t)(ix - X0) < (uint32_t)(X1 - X0) &&
+                  inb[i] = val && q[i] != kNoVoxel && (uint32_t)(ix - X0) < (uint32_t)(X1 - X0) &&
                            (uint32_t)(iy - Y0) < (uint32_t)(Y1 - Y0);
                 }
                 unsigned long long add1[4], add2[4];
@@ -571,52 +627,72 @@ __global__ void __launch_bounds__(1024) k_eval(const PairDev *__restrict__ pairs
               if (tid == 0) { ovf[p ^ 1] = 0u; occn[p ^ 1] = 0u; }
               int blo0 = nx, blo1 = ny, blo2 = nz, bhi0 = -1, bhi1 = -1, bhi2 = -1;
               unsigned long long bnin = 0;
-              for (int i = tid; i < nocc; i += T) {
-                const uint32_t h = occ[i];
-                const uint32_t key = hkey[h];
-                const int ix = (int)(key & kxm);
-                const int iy = SY0 + (int)((key >> kxb) & kym);
-                const int iz = (int)(key >> (kxb + kyb));
-                uint32_t n;
-                unsigned long long s1 = 0, s2 = 0;
-                if (ZVAR) {
-                  const unsigned long long a = hv1[h];
-                  n = (uint32_t)(a >> 44);
-                  s1 = a & ((1ull << 44) - 1);
-                  s2 = hv2[h];
-                  hv1[h] = 0ull;
-                  hv2[h] = 0ull;
-                } else {
-                  n = hcnt[h];
-                  hcnt[h] = 0u;
+              // Two slots per thread per round: both slots' LDS reads, then both
+              // voxels' A-bin gathers, are in flight together.
+              for (int i = tid; i < nocc; i += 2 * T) {
+                bool live[2], inO[2];
+                uint32_t n[2];
+                unsigned long long s1[2], s2[2];
+                int64_t lin[2];
+#pragma unroll
+                for (int j = 0; j < 2; ++j) {
+                  const int ii = i + j * T;
+                  live[j] = ii < nocc;
+                  inO[j] = false;
+                  n[j] = 0u;
+                  s1[j] = s2[j] = 0ull;
+                  lin[j] = 0;
+                  if (!live[j]) continue;
+                  const uint32_t h = occ[ii];
+                  const uint32_t key = hkey[h];
+                  const int ix = (int)(key & kxm);
+                  const int iy = SY0 + (int)((key >> kxb) & kym);
+                  const int iz = (int)(key >> (kxb + kyb));
+                  if (ZVAR) {
+                    const unsigned long long a = hv1[h];
+                    n[j] = (uint32_t)(a >> 44);
+                    s1[j] = a & ((1ull << 44) - 1);
+                    s2[j] = hv2[h];
+                    hv1[h] = 0ull;
+                    hv2[h] = 0ull;
+                  } else {
+                    n[j] = hcnt[h];
+                    hcnt[h] = 0u;
+                  }
+                  hkey[h] = kEmpty;
+                  bnin += n[j];
+                  blo0 = min(blo0, ix); blo1 = min(blo1, iy); blo2 = min(blo2, iz);
+                  bhi0 = max(bhi0, ix); bhi1 = max(bhi1, iy); bhi2 = max(bhi2, iz);
+                  inO[j] = !overflow && ix >= alo0 && ix <= ahi0 && iy >= alo1 && iy <= ahi1 &&
+                           iz >= alo2 && iz <= ahi2;
+                  lin[j] = ((int64_t)iz * ny + iy) * nx + ix;
                 }
-                hkey[h] = kEmpty;
-                bnin += n;
-                blo0 = min(blo0, ix); blo1 = min(blo1, iy); blo2 = min(blo2, iz);
-                bhi0 = max(bhi0, ix); bhi1 = max(bhi1, iy); bhi2 = max(bhi2, iz);
-                if (!overflow && ix >= alo0 && ix <= ahi0 && iy >= alo1 && iy <= ahi1 &&
-                    iz >= alo2 && iz <= ahi2) {
-                  const int64_t lin = ((int64_t)iz * ny + iy) * nx + ix;
+                int a0[2], a1[2];
+#pragma unroll
+                for (int j = 0; j < 2; ++j) {
+                  a0[j] = inO[j] ? (int)ldg(binA0 + lin[j]) : 0;
+                  a1[j] = inO[j] && nf > 1 ? (int)ldg(binA1 + lin[j]) : 0;
+                }
+#pragma unroll
+                for (int j = 0; j < 2; ++j) {
+                  if (!inO[j]) continue;
+                  const uint32_t nn = n[j];
                   // count bins: O(1) with the default edges 1, 2, ..., nb - 1; the
                   // joint feature numbers its (count, z-variance) bin pairs
                   auto count_bin = [&]() -> int {
-                    return count_default ? (int)min(n, (uint32_t)(nbc - 1))
-                                         : bin_count_dev(n, nbc, cedge);
+                    return count_default ? (int)min(nn, (uint32_t)(nbc - 1))
+                                         : bin_count_dev(nn, nbc, cedge);
                   };
                   auto bin_of = [&](uint32_t kind) -> int {
                     if (kind == MI_FEAT_COUNT || !ZVAR) return count_bin();
-                    const int bz = bin_zvar_nodiv(n, s1, s2, nbz, zedged, zedge);
+                    // one point has zero variance: 1 + the number of zero edges
+                    const int bz = nn == 1u ? 1 + zvar_zero
+                                            : bin_zvar_nodiv(nn, s1[j], s2[j], nbz, zedged, zedge);
                     if (kind == MI_FEAT_ZVAR) return bz;
                     return joint_value(count_bin(), bz, nbz);
                   };
-                  {
-                    const int a = ldg(binA0 + lin);
-                    atomicAdd(&myhist[a * nb0 + bin_of(kind0)], 1u);
-                  }
-                  if (nf > 1) {
-                    const int a = ldg(binA1 + lin);
-                    atomicAdd(&myhist[hoff1 + a * nb1 + bin_of(kind1)], 1u);
-                  }
+                  atomicAdd(&myhist[a0[j] * nb0 + bin_of(kind0)], 1u);
+                  if (nf > 1) atomicAdd(&myhist[hoff1 + a1[j] * nb1 + bin_of(kind1)], 1u);
                 }
               }
               __syncthreads();

@@ -1238,6 +1238,9 @@ mi_status create_plan(const mi_work_item *w, int64_t n, uint32_t flags, void *ws
     P.count_default = 1;
     for (int j = 0; j + 1 < gi.nbc; ++j)
       if (gi.count_edges[j] != (uint32_t)(j + 1)) P.count_default = 0;
+    P.zvar_zero_edges = 0;
+    for (int j = 0; j + 2 < gi.nbz; ++j)
+      if (gi.zvar_edges[j] == 0) ++P.zvar_zero_edges;
     P.nonfinite = PL.nonfinite + 2 * i;
     P.n_b = w[i].n_b;
     P.mi_out = w[i].mi_out;

@@ -92,7 +92,7 @@ struct PairDev {
   int32_t kx_bits, ky_bits;  // hash key: iz << (kx+ky) | (iy - stripe y0) << kx | ix
   int32_t plan_stripes;      // stripes whose candidate rows are planned per round
   int32_t count_default;     // count edges are 1, 2, ..., nb - 1 (bin = min(n, nb - 1))
-  int32_t pad1;
+  int32_t zvar_zero_edges;   // z-variance edges equal to 0 (a zero variance has bin 1 + this)
   const unsigned long long *nonfinite; // device counter
   int64_t n_b;
   double *mi_out;

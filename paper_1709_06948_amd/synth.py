@@ -450,25 +450,29 @@ def surface_pair(rng: np.random.Generator, n_points: int, voxel: float, half_ext
     return Pair(as_soa32(A), as_soa32(B), eta, origin, dims, voxel)
 
 
+def uneven_pair(j, seed=None, n_range=(10_000, 300_000), voxels=(0.25, 0.5, 1.0),
+                poses_per_pair=4096):
+    """Pair j of the uneven batch: (Pair, poses[P, 6]).  Each pair has its own
+    seed, so pairs can be generated independently (in parallel)."""
+    d2r = math.pi / 180.0
+    rng = np.random.default_rng(seed_for(4, j) if seed is None else seed + j)
+    n = int(round(math.exp(rng.uniform(math.log(n_range[0]), math.log(n_range[1])))))
+    voxel = float(rng.choice(voxels))
+    pair = surface_pair(rng, n, voxel)
+    prior = pair.eta_gt + np.array([rng.normal(0, 0.5), rng.normal(0, 0.5), 0.0, 0.0, 0.0,
+                                    rng.normal(0, 2 * d2r)])
+    span = np.array([3.0, 3.0, 0.2, 2 * d2r, 2 * d2r, 10 * d2r])
+    poses = prior + rng.uniform(-1, 1, (poses_per_pair, 6)) * span
+    return pair, poses
+
+
 def uneven_batch(n_pairs=64, seed=None, n_range=(10_000, 300_000), voxels=(0.25, 0.5, 1.0),
                  poses_per_pair=4096):
     """Uneven batch: per-pair point counts log-uniform in n_range, voxel size
     drawn from voxels, and poses_per_pair candidates uniform within +-3 m (x,y),
     +-0.2 m (z), +-10 deg yaw, +-2 deg roll/pitch of a seeded prior near the
     true pose.  Returns a list of (Pair, poses[P, 6])."""
-    out = []
-    d2r = math.pi / 180.0
-    for j in range(n_pairs):
-        rng = np.random.default_rng(seed_for(4, j) if seed is None else seed + j)
-        n = int(round(math.exp(rng.uniform(math.log(n_range[0]), math.log(n_range[1])))))
-        voxel = float(rng.choice(voxels))
-        pair = surface_pair(rng, n, voxel)
-        prior = pair.eta_gt + np.array([rng.normal(0, 0.5), rng.normal(0, 0.5), 0.0, 0.0, 0.0,
-                                        rng.normal(0, 2 * d2r)])
-        span = np.array([3.0, 3.0, 0.2, 2 * d2r, 2 * d2r, 10 * d2r])
-        poses = prior + rng.uniform(-1, 1, (poses_per_pair, 6)) * span
-        out.append((pair, poses))
-    return out
+    return [uneven_pair(j, seed, n_range, voxels, poses_per_pair) for j in range(n_pairs)]
 
 
 def serving_requests(rate_hz: float, n_requests: int, seed=None, n_range=(20_000, 250_000),
