@@ -212,7 +212,7 @@ def _run_uneven(a, work):
                       "pairs": len(items), "point_poses_per_step": point_poses},
            "gpoint_transforms_per_s": point_poses * a.steps / dt / 1e9,
            "roofline": _roofline(prof, "uneven",
-                                 cells_or_frames_ms_per_step=prof["frames_ms"] / a.steps)}
+                                 frames_ms_per_step=prof["frames_ms"] / a.steps)}
     del batch
     res["cpu_baseline"] = None
     if not a.no_cpu_baseline and a.cpu_per_pair > 0:
@@ -771,11 +771,18 @@ def _bench_all(a):
     import torch
     torch.cuda.set_device(0)
 
-    head = _run_uneven(a, work)
+    def done(name, res):
+        print(json.dumps({"workload_done": name, "value": res["value"],
+                          "frac": (res.get("roofline") or {}).get("frac")}), file=sys.stderr,
+              flush=True)
+        return res
+
+    print(json.dumps({"generated_s": round(t_gen, 1)}), file=sys.stderr, flush=True)
+    head = done("uneven", _run_uneven(a, work))
     del work
-    sub = {"c2f": _sub(_run_c2f(a, urban)), "batched": _sub(_run_batched(a, tiny))}
-    sa = argparse.Namespace(**vars(a))
-    sub["serving"] = _sub(_run_serving(sa, pool))
+    sub = {"c2f": _sub(done("c2f", _run_c2f(a, urban))),
+           "batched": _sub(done("batched", _run_batched(a, tiny)))}
+    sub["serving"] = _sub(done("serving", _run_serving(a, pool)))
     out = _line("MI pose evals/s", head["value"], "evals/s", head["steps"], head["warmup"],
                 head["ms_per_step"], head["config"],
                 gpoint_transforms_per_s=head["gpoint_transforms_per_s"],
