@@ -227,6 +227,24 @@ mi_status mi_eval_poses(const mi_ref *r, const float *xyz_b, int64_t n_b, const 
                         uint32_t *hist_out, mi_pose_stats *stats_out, void *ws, size_t ws_bytes,
                         void *stream);
 
+/* mi_eval_poses without a workspace, for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc).  Same arguments (less ws / ws_bytes) and results as
+ * mi_eval_poses.  Its work memory is a static device array of
+ * MI_STATIC_SCRATCH_BYTES per GPU, allocated with the library's code object
+ * and held until the process ends; the call makes no device or pinned-host
+ * allocation (pose tables are copied from pageable host memory).  Pose sets
+ * whose tables, rotated frames or per-pose buckets cannot fit it fail with
+ * MI_E_UNSUPPORTED; the per-pose form runs fewer workgroups when the buckets
+ * of all of them would not fit.  Every call on a GPU uses that GPU's one
+ * array: calls that overlap on one GPU (other streams, other host threads)
+ * race and must be serialized by the caller. */
+#define MI_STATIC_SCRATCH_BYTES ((int64_t)256 << 20)
+mi_status mi_eval_poses_static(const mi_ref *r, const float *xyz_b, int64_t n_b,
+                               const double *poses, int64_t n_poses, uint32_t flags,
+                               double *mi_out, int64_t *argmax_out, uint32_t *hist_out,
+                               mi_pose_stats *stats_out, void *stream);
+
 /* The paper-shaped path: for each pose in turn, one launch sequence of
  * transform + voxel mapping + extent, scatter into a dense per-pose voxel grid
  * in device memory, dense sweep of the overlap box into the joint histogram,

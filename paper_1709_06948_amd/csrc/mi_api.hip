@@ -1079,14 +1079,36 @@ size_t single_plan_bytes(int64_t K, int32_t F, int64_t ncols, int64_t n_b) {
   return batch_bytes(B, &w, 1, 0);
 }
 
+// no_alloc: the workspace is fixed (the static scratch), so the per-pose
+// buckets get as many workgroup slots as it holds, and the tables are copied
+// from host memory directly instead of through pinned staging (which may
+// allocate).
 mi_status create_plan(const mi_work_item *w, int64_t n, uint32_t flags, void *ws, size_t ws_bytes,
-                      size_t budget, void *stream, bool bind_per_execution, mi_plan **out) {
+                      size_t budget, void *stream, bool bind_per_execution, mi_plan **out,
+                      bool no_alloc = false) {
   if (!out) return fail(MI_E_INVALID, "NULL output handle");
   *out = nullptr;
   BatchTables B;
   mi_status st = prepare_batch(w, n, flags, B);  // argument errors before workspace errors
   if (st != MI_OK) return st;
   if (!ws || ((uintptr_t)ws & 255)) return fail(MI_E_WORKSPACE, "workspace NULL or not 256-aligned");
+  if (no_alloc && B.scratch_slots > 0) {
+    // the buckets take what the tables leave (half of it when frames need room too)
+    const int64_t want = B.scratch_slots;
+    B.scratch_slots = 0;
+    Carver c0(nullptr, 0);
+    plan_fixed(B, n, c0, nullptr);
+    const size_t fixed = c0.used() + 4096;
+    size_t room = ws_bytes > fixed ? ws_bytes - fixed : 0;
+    if (B.F_built > 0) room /= 2;
+    const size_t per_slot = (size_t)B.scratch_stride * sizeof(uint2);
+    const int64_t fit = (int64_t)(room / per_slot) / kXcds * kXcds;
+    if (fit < kXcds)
+      return fail(MI_E_UNSUPPORTED,
+                  "per-pose buckets of %lld points for %d workgroups need %zu bytes; %zu are left",
+                  (long long)B.scratch_stride, kXcds, per_slot * kXcds, room);
+    B.scratch_slots = std::min(want, fit);
+  }
   Carver c(ws, ws_bytes);
   PlanLayout PL;
   plan_fixed(B, n, c, &PL);
@@ -1255,6 +1277,19 @@ mi_status create_plan(const mi_work_item *w, int64_t n, uint32_t flags, void *ws
   const size_t b_items = sizeof(PoseDev) * items.size(), b_pairs = sizeof(PairDev) * pairs.size(),
                b_frames = sizeof(FrameDev) * frames.size();
   hipError_t e = hipSuccess;
+  if (no_alloc) {
+    // pageable host source: each copy has taken its data when it returns
+    const hipStream_t hs = (hipStream_t)stream;
+    if (b_items)
+      HIP_TRY(hipMemcpyAsync(PL.items, items.data(), b_items, hipMemcpyHostToDevice, hs), "pose table");
+    if (b_pairs)
+      HIP_TRY(hipMemcpyAsync(PL.pairs, pairs.data(), b_pairs, hipMemcpyHostToDevice, hs), "pair table");
+    if (b_frames)
+      HIP_TRY(hipMemcpyAsync(PL.frames, frames.data(), b_frames, hipMemcpyHostToDevice, hs),
+              "frame table");
+    *out = p.release();
+    return MI_OK;
+  }
   Staging *sg = staging_acquire(b_items + b_pairs + b_frames + 64, &e);
   if (!sg) return dev_fail(e, "pinned staging");
   char *h = (char *)sg->p;
@@ -1567,6 +1602,54 @@ extern "C" mi_status mi_eval_poses(const mi_ref *r, const float *xyz_b, int64_t 
   return guarded("mi_eval_poses", [&]() -> mi_status {
   mi_plan *p = nullptr;
   mi_status st = mi_plan_create(r, n_b, poses, K, flags, ws, ws_bytes, 0, stream, &p);
+  if (st != MI_OK) return st;
+  st = mi_plan_execute(p, xyz_b, mi_out, argmax_out, hist_out, stats_out, stream);
+  mi_plan_destroy(p);
+  return st;
+  });
+}
+
+// ------------------------------------------------------------ static scratch
+
+// Device memory of mi_eval_poses_static: one array per GPU, held until the
+// process ends.  In host code the array's name only stands for the symbol;
+// its device address (per device) comes from hipGetSymbolAddress.
+static __device__ __align__(256) unsigned char static_scratch[MI_STATIC_SCRATCH_BYTES];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_static_mu;
+void *g_static_ptr[kMaxDevices] = {};
+}  // namespace
+
+extern "C" mi_status mi_eval_poses_static(const mi_ref *r, const float *xyz_b, int64_t n_b,
+                                          const double *poses, int64_t K, uint32_t flags,
+                                          double *mi_out, int64_t *argmax_out, uint32_t *hist_out,
+                                          mi_pose_stats *stats_out, void *stream) {
+  return guarded("mi_eval_poses_static", [&]() -> mi_status {
+  if (!r) return fail(MI_E_INVALID, "mi_eval_poses_static: NULL ref");
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev), "current device");
+  if (dev < 0 || dev >= kMaxDevices) return fail(MI_E_UNSUPPORTED, "device index %d", dev);
+  void *base = nullptr;
+  {
+    std::lock_guard<std::mutex> lk(g_static_mu);
+    if (!g_static_ptr[dev]) {  // once per device, with that device current
+      void *q = nullptr;
+      HIP_TRY(hipGetSymbolAddress(&q, HIP_SYMBOL(static_scratch)), "static scratch address");
+      g_static_ptr[dev] = q;
+    }
+    base = g_static_ptr[dev];
+  }
+  mi_work_item w;
+  memset(&w, 0, sizeof w);
+  w.ref = r; w.n_b = n_b; w.poses = poses; w.K = K;
+  mi_plan *p = nullptr;
+  mi_status st = create_plan(&w, 1, flags, base, (size_t)MI_STATIC_SCRATCH_BYTES, 0, stream, true,
+                             &p, true);
+  if (st == MI_E_WORKSPACE)
+    return fail(MI_E_UNSUPPORTED, "mi_eval_poses_static: the %lld-byte static scratch is too small: %s",
+                (long long)MI_STATIC_SCRATCH_BYTES, t_err.c_str());
   if (st != MI_OK) return st;
   st = mi_plan_execute(p, xyz_b, mi_out, argmax_out, hist_out, stats_out, stream);
   mi_plan_destroy(p);

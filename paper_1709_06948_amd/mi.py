@@ -120,6 +120,7 @@ def _load():
         "mi_ref_summary": ([vp, vp, C.POINTER(C.c_int32), C.POINTER(C.c_int64)], st),
         "mi_eval_poses_workspace": ([vp, i64, dp, i64, u32, sz], sz),
         "mi_eval_poses": ([vp, vp, i64, dp, i64, u32, vp, vp, vp, vp, vp, sz, vp], st),
+        "mi_eval_poses_static": ([vp, vp, i64, dp, i64, u32, vp, vp, vp, vp, vp], st),
         "mi_eval_poses_plain_workspace": ([vp, i64, i64], sz),
         "mi_eval_poses_plain": ([vp, vp, i64, dp, i64, u32, vp, vp, vp, vp, vp, sz, vp], st),
         "mi_plan_create": ([vp, i64, dp, i64, u32, vp, sz, sz, vp, C.POINTER(vp)], st),
@@ -418,6 +419,24 @@ def eval_poses(ref: Ref, xyz_b, poses, flags=0, want_hist=False, want_stats=Fals
            "mi_eval_poses")
     out = _unpack(ref.grid, K, mi, am, hist, stats)
     out["_keep"] = (xb, ws)
+    return out
+
+
+@_stream_ordered
+def eval_poses_static(ref: Ref, xyz_b, poses, flags=0, want_hist=False, want_stats=False,
+                      want_argmax=True, stream=None):
+    """mi_eval_poses_static: mi_eval_poses on the library's static device
+    scratch (no workspace; the call allocates no device memory)."""
+    xb = _dev_points(xyz_b)
+    P = _poses(poses)
+    K = P.shape[0]
+    pp = P.ctypes.data_as(C.POINTER(C.c_double))
+    mi, am, hist, stats = _outputs(ref.grid, K, want_hist, want_stats, want_argmax)
+    _check(_lib.mi_eval_poses_static(ref._h, _dptr(xb), xb.shape[1], pp, K, flags, _dptr(mi),
+                                     _dptr(am), _dptr(hist), _dptr(stats), _stream(stream)),
+           "mi_eval_poses_static")
+    out = _unpack(ref.grid, K, mi, am, hist, stats)
+    out["_keep"] = (xb,)
     return out
 
 
