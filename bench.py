@@ -16,7 +16,7 @@ roofline and CPU-oracle baseline:
   c2f      a realistic pair: two 64-ring spinning-scanner scans (~115k points
            each) of a 160 x 160 m urban scene, 0.5 m voxels over 320 x 320 x 20,
            both features at 32 bins; 3 coarse-to-fine levels of 5^6 poses, and
-           a finer search (7,7,5,5,5,9 nodes, 4 levels, shrink 3) for accuracy;
+           a finer search (7,7,5,5,5,9 nodes, 6 levels, shrink 2) for accuracy;
   batched  the tiny pair (~20k / ~14k points, 1 m voxels, 64 x 64 x 10, count at
            32 bins) with 8^6 = 262,144 poses in one batch, replayed as one
            captured HIP graph;
@@ -239,7 +239,7 @@ def _run_uneven(a, work):
 # A finer search than the configured one (nodes per axis, levels, shrink), with
 # the same level-0 half-ranges: it recovers the urban pair's true pose.
 FINE_SAMPLES = (7, 7, 5, 5, 5, 9)
-FINE_LEVELS, FINE_SHRINK = 4, 3.0
+FINE_LEVELS, FINE_SHRINK = 6, 2.0
 
 
 def _run_c2f(a, pair):
