@@ -29,7 +29,10 @@ roofline and CPU-oracle baseline:
 Each workload alone: --workload NAME (its own line).  accuracy and surface
 run the paper's accuracy protocol and cost surfaces on synthetic stand-ins.
 --calibrate-copy runs a plain 1 GiB device copy, the reference kernel that
-scales the HBM byte counters of a profile.
+scales the HBM byte counters of a profile.  --calibrate KIND|all runs the
+roofline microbenchmarks (LDS atomics and compare-and-swap, HBM stream read,
+FP64 issue); their committed results (profiles/roofline_calibration.md) give
+each roofline a measured peak beside the published one.
 
 Rooflines: the evaluator is bound by FP64/integer ALU work (no dense
 contraction, so no MFMA); achieved = 27 algorithmic FP64 operations per
@@ -89,6 +92,9 @@ def _args():
     ap.add_argument("--pool", type=int, default=24)
     ap.add_argument("--slots", type=int, default=32)
     ap.add_argument("--calibrate-copy", action="store_true")
+    ap.add_argument("--calibrate", choices=("lds_u32", "lds_u64", "lds_cas", "hbm_read", "fp64",
+                                            "all"),
+                    help="roofline microbenchmarks: measured peaks of the units the evaluator uses")
     return ap.parse_args()
 
 
@@ -133,6 +139,11 @@ def _roofline(prof, workload, **extra):
            "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_OPS,
            "traffic": _measured_traffic(workload), "kernel": "k_eval", "avg_launch_ms": ms,
            "point_poses_per_launch": pp, "eval_launches": prof["eval_launches"]}
+    peaks = _measured_peaks()
+    if peaks.get("fp64_lane_ops_per_s"):
+        # the same work against the FP64 issue rate measured on this GPU
+        out["measured_peak"] = peaks["fp64_lane_ops_per_s"] / 1e12
+        out["frac_of_measured_peak"] = achieved / peaks["fp64_lane_ops_per_s"]
     out.update(extra)
     return out
 
@@ -154,6 +165,60 @@ def _line(metric, value, unit, steps, warmup, ms_per_step, config, **extra):
            "config": config}
     out.update(extra)
     return out
+
+
+CALIB_KINDS = {"lds_u32": (0, 2000, "LDS 32-bit atomic add lane-ops/s"),
+               "lds_u64": (1, 2000, "LDS 64-bit atomic add lane-ops/s"),
+               "lds_cas": (2, 2000, "LDS compare-and-swap lane-ops/s"),
+               "hbm_read": (3, 1, "HBM stream read bytes/s"),
+               "fp64": (4, 20000, "FP64 VALU mul/add lane-ops/s (no contraction)")}
+CALIB_FILE = os.path.join(ROOT, "profiles", "roofline_calibration.md")
+
+
+def _calibrate(a):
+    """Each microbenchmark launched 5 times after a warm-up, timed with HIP
+    events on the launch stream; the best rate is reported."""
+    import torch
+
+    from paper_1709_06948_amd import mi
+
+    torch.cuda.set_device(0)
+    kinds = list(CALIB_KINDS) if a.calibrate == "all" else [a.calibrate]
+    out = {}
+    for name in kinds:
+        kind, size, what = CALIB_KINDS[name]
+        nbytes = (4 << 30) if name == "hbm_read" else (1 << 20)
+        scratch = torch.ones(nbytes // 4, dtype=torch.int32, device="cuda")
+        s = torch.cuda.current_stream()
+        mi.calibrate_launch(kind, size, scratch, stream=s)
+        best = 0.0
+        for _ in range(5):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(s)
+            ops = mi.calibrate_launch(kind, size, scratch, stream=s)
+            e1.record(s)
+            e1.synchronize()
+            best = max(best, ops / (e0.elapsed_time(e1) * 1e-3))
+        out[name] = {"rate": best, "unit": what}
+        del scratch
+    print(json.dumps({"calibration": out}), flush=True)
+
+
+def _measured_peaks():
+    """Peaks measured by --calibrate all (the committed profile), or {}."""
+    vals = {}
+    try:
+        text = open(CALIB_FILE).read()
+    except OSError:
+        return vals
+    for line in text.splitlines():
+        if line.startswith("- ") and ":" in line:
+            k, v = line[2:].split(":", 1)
+            try:
+                vals[k.strip()] = float(v.strip().strip("`"))
+            except ValueError:
+                pass
+    return vals
 
 
 def _calibrate_copy():
@@ -824,6 +889,8 @@ def main():
     if a.calibrate_copy:
         _calibrate_copy()
         return
+    if a.calibrate:
+        return _calibrate(a)
     if a.workload == "all":
         return _bench_all(a)
     if a.workload == "accuracy":

@@ -467,6 +467,19 @@ mi_status mi_server_release(mi_server *s, int64_t id); /* forget a finished requ
 mi_status mi_server_info(mi_server *s, size_t *heap_bytes, size_t *heap_free);
 void mi_server_destroy(mi_server *s);
 
+/* ------------------------------------------------------------ calibration */
+
+/* Roofline microbenchmarks (measurement support, not part of the method):
+ * launches one kernel of a known operation count on `stream` and returns that
+ * count in *ops; the caller times the launch.  kind: 0 = LDS 32-bit atomic
+ * add, 1 = LDS 64-bit atomic add, 2 = LDS compare-and-swap (lane operations,
+ * conflict-free, iters = size rounds of 8 per lane), 3 = HBM stream read of
+ * the scratch buffer (bytes; needs >= 16 KiB), 4 = FP64 VALU multiply and add
+ * without contraction (lane operations, size rounds of 16 per lane).
+ * scratch: device memory the kernel may write (>= 8 bytes per workgroup). */
+mi_status mi_calibrate_launch(int32_t kind, int64_t size, void *scratch, int64_t scratch_bytes,
+                              void *stream, double *ops);
+
 #ifdef __cplusplus
 }
 #endif

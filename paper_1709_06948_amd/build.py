@@ -18,7 +18,8 @@ ROOT = os.path.dirname(HERE)
 INCLUDE = os.path.join(ROOT, "include")
 BUILD_DIR = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libmi355.so")
-SOURCES = ["mi_api.hip", "k_ref.hip", "k_frames.hip", "k_eval.hip", "k_plain.hip", "k_util.hip"]
+SOURCES = ["mi_api.hip", "k_ref.hip", "k_frames.hip", "k_eval.hip", "k_plain.hip", "k_util.hip",
+           "k_calib.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-ffp-contract=off",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
@@ -37,7 +38,7 @@ def _compile(src: str) -> str:
 def build(verbose: bool = False) -> str:
     """Compile every HIP source and link libmi355.so (always rebuilds)."""
     os.makedirs(BUILD_DIR, exist_ok=True)
-    with ThreadPoolExecutor(max_workers=min(len(SOURCES), 6)) as ex:
+    with ThreadPoolExecutor(max_workers=min(len(SOURCES), 7)) as ex:
         objs = list(ex.map(_compile, SOURCES))
     tmp = LIB + ".tmp"
     cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp, *objs]

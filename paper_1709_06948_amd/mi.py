@@ -121,6 +121,7 @@ def _load():
         "mi_eval_poses_workspace": ([vp, i64, dp, i64, u32, sz], sz),
         "mi_eval_poses": ([vp, vp, i64, dp, i64, u32, vp, vp, vp, vp, vp, sz, vp], st),
         "mi_eval_poses_static": ([vp, vp, i64, dp, i64, u32, vp, vp, vp, vp, vp], st),
+        "mi_calibrate_launch": ([st, i64, vp, i64, vp, dp], st),
         "mi_eval_poses_plain_workspace": ([vp, i64, i64], sz),
         "mi_eval_poses_plain": ([vp, vp, i64, dp, i64, u32, vp, vp, vp, vp, vp, sz, vp], st),
         "mi_plan_create": ([vp, i64, dp, i64, u32, vp, sz, sz, vp, C.POINTER(vp)], st),
@@ -420,6 +421,16 @@ def eval_poses(ref: Ref, xyz_b, poses, flags=0, want_hist=False, want_stats=Fals
     out = _unpack(ref.grid, K, mi, am, hist, stats)
     out["_keep"] = (xb, ws)
     return out
+
+
+def calibrate_launch(kind: int, size: int, scratch: torch.Tensor, stream=None) -> float:
+    """mi_calibrate_launch: launches one roofline microbenchmark kernel on the
+    stream and returns its operation count (the caller times it)."""
+    ops = C.c_double(0.0)
+    _check(_lib.mi_calibrate_launch(int(kind), int(size), _dptr(scratch), scratch.numel() *
+                                    scratch.element_size(), _stream(stream), C.byref(ops)),
+           "mi_calibrate_launch")
+    return ops.value
 
 
 @_stream_ordered
