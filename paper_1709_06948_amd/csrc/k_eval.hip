@@ -208,6 +208,8 @@ __global__ void __launch_bounds__(1024) k_eval(const PairDev *__restrict__ pairs
     const bool count_default = P.count_default != 0;
     const int zvar_zero = P.zvar_zero_edges;
     const uint8_t *binA0 = P.binA[0], *binA1 = P.binA[1];
+    const uint32_t nvox = (uint32_t)nx * (uint32_t)ny * (uint32_t)nz;  // below 2^31
+    const brsrc rbin0 = buf_rsrc(binA0, nvox), rbin1 = buf_rsrc(binA1, nf > 1 ? nvox : 0u);
     const int BY = P.stripe_h, NS = P.n_stripes, Q = P.pieces, RM = BY + 2;
     const int kxb = P.kx_bits, kyb = P.ky_bits;
     const uint32_t kxm = (1u << kxb) - 1u, kym = (1u << kyb) - 1u;
@@ -229,13 +231,20 @@ __global__ void __launch_bounds__(1024) k_eval(const PairDev *__restrict__ pairs
     uint32_t *soff = (uint32_t *)plan;   // [NS + 1]
     uint32_t *scur = soff + NS + 1;      // [NS]
     uint2 *mine = DIRECT ? scratch + (int64_t)blockIdx.x * scratch_stride : nullptr;
+    // this workgroup's buckets: (key, q) pairs, 8 bytes each (the stride is
+    // below 2^28 entries in this form)
+    const brsrc rmine = buf_rsrc(mine, DIRECT ? 8u * (uint32_t)scratch_stride : 0u);
     if (DIRECT) {
       double R[9];
 #pragma unroll
       for (int a = 0; a < 9; ++a) R[a] = Fr.R[a];
       const double fs = Fr.s;
-      const float *xyz = Fr.xyz;
-      const int64_t nb = Fr.n;
+      // scan B (fewer than 2^28 points in this form) through one buffer
+      // resource: the coordinate arrays at scalar offsets 0, 4n and 8n
+      const uint32_t nb32 = (uint32_t)Fr.n;
+      const brsrc rxyz = buf_rsrc(Fr.xyz, 12u * nb32);
+      const uint32_t oy = 4u * nb32, oz = 8u * nb32;
+
       // stripe of a voxel row, iy / BY, by a multiply-high where that is exact:
       // with m = ceil(2^32 / BY), m * BY - 2^32 < BY, so iy * m / 2^32 has the
       // quotient's integer part while iy * BY < 2^32 (any row below 2^26)
@@ -249,20 +258,19 @@ __global__ void __launch_bounds__(1024) k_eval(const PairDev *__restrict__ pairs
       // Count pass: only the y row of the transform decides the stripe.  Four
       // points per lane are loaded before any is used, so a wave waits on
       // memory once per four points.
-      for (int64_t i0 = tid; i0 < nb; i0 += 4 * (int64_t)T) {
+      for (uint32_t i0 = (uint32_t)tid; i0 < nb32; i0 += 4u * (uint32_t)T) {
         float fx[4], fy[4], fz[4];
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
-          const int64_t i = i0 + (int64_t)j * T;
-          const int64_t ii = i < nb ? i : 0;
-          fx[j] = ldg(xyz + ii);
-          fy[j] = ldg(xyz + nb + ii);
-          fz[j] = ldg(xyz + 2 * nb + ii);
+          const uint32_t i = i0 + (uint32_t)j * (uint32_t)T;  // past the end: reads 0
+          fx[j] = buf_f32(rxyz, 4u * i, 0u);
+          fy[j] = buf_f32(rxyz, 4u * i, oy);
+          fz[j] = buf_f32(rxyz, 4u * i, oz);
         }
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
-          const int64_t i = i0 + (int64_t)j * T;
-          if (i < nb && isfinite(fx[j]) && isfinite(fy[j]) && isfinite(fz[j])) {
+          const uint32_t i = i0 + (uint32_t)j * (uint32_t)T;
+          if (i < nb32 && isfinite(fx[j]) && isfinite(fy[j]) && isfinite(fz[j])) {
             const double x = fx[j], y = fy[j], z = fz[j];
             const double uy = ((R[3] * x + R[4] * y) + R[5] * z) * fs + cy;
             const int iy = (int)floor(uy);
@@ -293,24 +301,23 @@ __global__ void __launch_bounds__(1024) k_eval(const PairDev *__restrict__ pairs
       // Scatter pass: the whole voxel.  Every point counted above gets an entry
       // in its stripe's bucket; one outside the grid in x or z is marked by
       // q = kNoVoxel and skipped by the bricks.
-      for (int64_t i0 = tid; i0 < nb; i0 += 4 * (int64_t)T) {
+      for (uint32_t i0 = (uint32_t)tid; i0 < nb32; i0 += 4u * (uint32_t)T) {
         float fx[4], fy[4], fz[4];
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
-          const int64_t i = i0 + (int64_t)j * T;
-          const int64_t ii = i < nb ? i : 0;
-          fx[j] = ldg(xyz + ii);
-          fy[j] = ldg(xyz + nb + ii);
-          fz[j] = ldg(xyz + 2 * nb + ii);
+          const uint32_t i = i0 + (uint32_t)j * (uint32_t)T;  // past the end: reads 0
+          fx[j] = buf_f32(rxyz, 4u * i, 0u);
+          fy[j] = buf_f32(rxyz, 4u * i, oy);
+          fz[j] = buf_f32(rxyz, 4u * i, oz);
         }
         uint32_t pos[4], key[4], qv[4];
         bool put[4];
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
-          const int64_t i = i0 + (int64_t)j * T;
+          const uint32_t i = i0 + (uint32_t)j * (uint32_t)T;
           const DirectVoxel dv = direct_voxel<ZVAR, NEAR>(fx[j], fy[j], fz[j], R, fs, cx, cy, cz,
                                                            nx, ny, nz, P.voxel);
-          put[j] = i < nb && (uint32_t)dv.iy < (uint32_t)ny;
+          put[j] = i < nb32 && (uint32_t)dv.iy < (uint32_t)ny;
           pos[j] = 0u;
           key[j] = 0u;
           qv[j] = kNoVoxel;
@@ -329,7 +336,7 @@ __global__ void __launch_bounds__(1024) k_eval(const PairDev *__restrict__ pairs
         }
 #pragma unroll
         for (int j = 0; j < 4; ++j)
-          if (put[j]) mine[pos[j]] = make_uint2(key[j], qv[j]);
+          if (put[j]) buf_store_u32x2((u32x2){key[j], qv[j]}, rmine, 8u * pos[j]);
       }
       __syncthreads();
     }
@@ -576,10 +583,9 @@ __global__ void __launch_bounds__(1024) k_eval(const PairDev *__restrict__ pairs
                 for (int i = 0; i < 4; ++i) {
                   const uint32_t idx = bst + (uint32_t)(k + i * W) * 64u + (uint32_t)lane;
                   const bool val = k + i * W < nch && idx < bend;
-                  const unsigned long long e =
-                      ldg((const unsigned long long *)(mine + (val ? idx : bst)));
-                  key[i] = (uint32_t)e;
-                  q[i] = (uint32_t)(e >> 32);
+                  const u32x2 e = buf_u32x2(rmine, 8u * (val ? idx : bst));
+                  key[i] = e.x;
+                  q[i] = e.y;
                 }
   #pragma unroll
                 for (int i = 0; i < 4; ++i) {
@@ -633,7 +639,7 @@ __global__ void __launch_bounds__(1024) k_eval(const PairDev *__restrict__ pairs
                 bool live[2], inO[2];
                 uint32_t n[2];
                 unsigned long long s1[2], s2[2];
-                int64_t lin[2];
+                uint32_t lin[2];  // a grid has fewer than 2^31 voxels
 #pragma unroll
                 for (int j = 0; j < 2; ++j) {
                   const int ii = i + j * T;
@@ -641,7 +647,7 @@ __global__ void __launch_bounds__(1024) k_eval(const PairDev *__restrict__ pairs
                   inO[j] = false;
                   n[j] = 0u;
                   s1[j] = s2[j] = 0ull;
-                  lin[j] = 0;
+                  lin[j] = 0u;
                   if (!live[j]) continue;
                   const uint32_t h = occ[ii];
                   const uint32_t key = hkey[h];
@@ -665,13 +671,13 @@ __global__ void __launch_bounds__(1024) k_eval(const PairDev *__restrict__ pairs
                   bhi0 = max(bhi0, ix); bhi1 = max(bhi1, iy); bhi2 = max(bhi2, iz);
                   inO[j] = !overflow && ix >= alo0 && ix <= ahi0 && iy >= alo1 && iy <= ahi1 &&
                            iz >= alo2 && iz <= ahi2;
-                  lin[j] = ((int64_t)iz * ny + iy) * nx + ix;
+                  lin[j] = ((uint32_t)iz * (uint32_t)ny + (uint32_t)iy) * (uint32_t)nx + (uint32_t)ix;
                 }
                 int a0[2], a1[2];
 #pragma unroll
                 for (int j = 0; j < 2; ++j) {
-                  a0[j] = inO[j] ? (int)ldg(binA0 + lin[j]) : 0;
-                  a1[j] = inO[j] && nf > 1 ? (int)ldg(binA1 + lin[j]) : 0;
+                  a0[j] = inO[j] ? (int)buf_u8(rbin0, lin[j]) : 0;
+                  a1[j] = inO[j] && nf > 1 ? (int)buf_u8(rbin1, lin[j]) : 0;
                 }
 #pragma unroll
                 for (int j = 0; j < 2; ++j) {

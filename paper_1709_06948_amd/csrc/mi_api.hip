@@ -934,9 +934,15 @@ mi_status prepare_batch(const mi_work_item *w, int64_t n, uint32_t flags, BatchT
     if (!choose_stripes(gi, tu, zvar, B.SS[(size_t)i], &why))
       return fail(MI_E_UNSUPPORTED, "work item %lld: evaluator: %s", (long long)i, why);
     const PoseTables &T = B.T[(size_t)i];
-    // a rotation shared by fewer than two poses on average is not worth a frame
+    // a rotation shared by fewer than two poses on average is not worth a frame;
+    // the per-pose form addresses scan B with 32-bit offsets (below 2^28 points)
+    const bool small = it.n_b < ((int64_t)1 << 28);
+    if ((flags & MI_EVAL_PER_POSE) && !small)
+      return fail(MI_E_UNSUPPORTED, "work item %lld: the per-pose form takes below 2^28 points",
+                  (long long)i);
     const bool direct = (flags & MI_EVAL_PER_POSE) ||
-                        (!(flags & MI_EVAL_SHARED_FRAMES) && it.K > 0 && 2 * (int64_t)T.F > it.K);
+                        (!(flags & MI_EVAL_SHARED_FRAMES) && small && it.K > 0 &&
+                         2 * (int64_t)T.F > it.K);
     B.direct[(size_t)i] = direct;
     if (direct) {
       // A per-pose brick rescans its stripe's whole bucket, so overflow retries

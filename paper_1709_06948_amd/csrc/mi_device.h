@@ -17,6 +17,27 @@ __device__ __forceinline__ T ldg(const T *p) {
   return *(const __attribute__((address_space(1))) T *)p;
 }
 
+// Raw buffer access: a 32-bit byte offset from a uniform base, checked by the
+// hardware against the buffer's size (a read past it returns 0, a write past
+// it is dropped).  Descriptor word 3 of a plain 32-bit raw buffer on gfx9.
+typedef __amdgpu_buffer_rsrc_t brsrc;
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ brsrc buf_rsrc(const void *p, uint32_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p), (short)0, (int)bytes, 0x00020000);
+}
+__device__ __forceinline__ float buf_f32(brsrc r, uint32_t off, uint32_t soff) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, soff, 0));
+}
+__device__ __forceinline__ uint32_t buf_u8(brsrc r, uint32_t off) {
+  return (uint32_t)__builtin_amdgcn_raw_buffer_load_b8(r, off, 0, 0);
+}
+__device__ __forceinline__ u32x2 buf_u32x2(brsrc r, uint32_t off) {
+  return __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0);
+}
+__device__ __forceinline__ void buf_store_u32x2(u32x2 v, brsrc r, uint32_t off) {
+  __builtin_amdgcn_raw_buffer_store_b64(v, r, off, 0, 0);
+}
+
 // Point-count feature (Sec. III-A, number of points in the voxel):
 // bin = #{j : n >= e[j]} over nb-1 non-decreasing edges (binary search).
 __device__ __forceinline__ int bin_count_dev(uint32_t n, int nb, const uint32_t *e) {
