@@ -91,6 +91,9 @@ def _args():
     ap.add_argument("--requests", type=int, default=2000)
     ap.add_argument("--pool", type=int, default=24)
     ap.add_argument("--slots", type=int, default=32)
+    ap.add_argument("--serial", action="store_true",
+                    help="generate the synthetic pairs in this process (no worker pool), as "
+                         "under a profiler")
     ap.add_argument("--calibrate-copy", action="store_true")
     ap.add_argument("--calibrate", choices=("lds_u32", "lds_u64", "lds_cas", "hbm_read", "fp64",
                                             "all"),
@@ -148,12 +151,22 @@ def _roofline(prof, workload, **extra):
     return out
 
 
+SERIAL = False
+
+
 def _parallel(fn, args):
-    """fn over args in forked worker processes (before any GPU work), in order."""
+    """fn over args in forked worker processes (before any GPU work), in order;
+    in this process, printing progress, with --serial."""
     import multiprocessing as mp
     n = max(1, min(16, _cores(), len(args)))
-    if n == 1:
-        return [fn(x) for x in args]
+    if n == 1 or SERIAL:
+        out = []
+        for i, x in enumerate(args):
+            out.append(fn(x))
+            if SERIAL and (i + 1) % 8 == 0:
+                print(json.dumps({"generated": i + 1, "of": len(args)}), file=sys.stderr,
+                      flush=True)
+        return out
     with mp.get_context("fork").Pool(n) as pool:
         return pool.map(fn, args, chunksize=1)
 
@@ -880,7 +893,9 @@ def _bench_one(a):
 
 
 def main():
+    global SERIAL
     a = _args()
+    SERIAL = a.serial
     if a.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU only; pose sets are not "
                                    "sharded over several GPUs",
