@@ -19,7 +19,7 @@ INCLUDE = os.path.join(ROOT, "include")
 BUILD_DIR = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libmi355.so")
 SOURCES = ["mi_api.hip", "k_ref.hip", "k_frames.hip", "k_eval.hip", "k_plain.hip", "k_util.hip",
-           "k_calib.hip"]
+           "k_calib.hip", "k_tiles.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-ffp-contract=off",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

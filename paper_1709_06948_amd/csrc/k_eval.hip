@@ -93,7 +93,8 @@ struct DirectVoxel {
   bool near;   // within kNearFace of a face (when asked for)
 };
 
-template <bool ZVAR, bool NEAR>
+// (FINITE: the point is known to be finite, as every tile entry is)
+template <bool ZVAR, bool NEAR, bool FINITE = false>
 __device__ __forceinline__ DirectVoxel direct_voxel(float xf, float yf, float zf,
                                                     const double (&R)[9], double s, double cx,
                                                     double cy, double cz, int nx, int ny, int nz,
@@ -103,7 +104,7 @@ __device__ __forceinline__ DirectVoxel direct_voxel(float xf, float yf, float zf
   r.near = false;
   r.q = 0u;
   r.ix = r.iy = r.iz = -1;
-  if (!isfinite(xf) || !isfinite(yf) || !isfinite(zf)) return r;
+  if (!FINITE && (!isfinite(xf) || !isfinite(yf) || !isfinite(zf))) return r;
   const double x = xf, y = yf, z = zf;
   const double wx = (R[0] * x + R[1] * y) + R[2] * z;
   const double wy = (R[3] * x + R[4] * y) + R[5] * z;
@@ -131,17 +132,36 @@ __device__ __forceinline__ DirectVoxel direct_voxel(float xf, float yf, float zf
   return r;
 }
 
-// DIRECT = false: candidates come from the pose's rotated frame (points
-// bucketed by column, shared by every pose with that rotation).
-// DIRECT = true: the workgroup buckets its pose's points itself, by stripe,
-// into its own slot of `scratch` (count, scan, scatter of (key, q) pairs),
-// for pose sets whose rotations are (nearly) all distinct.
-template <bool NEAR, bool ZVAR, bool DIRECT>
+// Bit mixer (the MurmurHash3 finalizer) for splitting an overflowed tile's
+// voxels into parts independently of their hash slots.
+__device__ __forceinline__ uint32_t mix32(uint32_t k) {
+  k ^= k >> 16;
+  k *= 0x85ebca6bu;
+  k ^= k >> 13;
+  k *= 0xc2b2ae35u;
+  k ^= k >> 16;
+  return k;
+}
+
+// MODE 0: candidates come from the pose's rotated frame (points bucketed by
+// column, shared by every pose with that rotation).
+// MODE 1: the workgroup buckets its pose's points itself, by stripe, into its
+// own slot of `scratch` (count, scan, scatter of (key, q) pairs), for pose
+// sets whose rotations are (nearly) all distinct.
+// MODE 2: for such pose sets, scan B comes bucketed into tiles of its own
+// (x, y) frame, each followed by its halo (the neighbours' points within
+// 0.88 voxel of it).  The workgroup takes the tiles one at a time, each as
+// one brick keyed by whole-grid voxels, and keeps a voxel only in the tile
+// that holds the voxel's centre mapped back into B's frame: a point of the
+// voxel lies within half a voxel diagonal (0.866 voxel) of that centre, so
+// the tile and its halo hold every point of every voxel it keeps.
+template <bool NEAR, bool ZVAR, int MODE>
 __global__ void __launch_bounds__(1024) k_eval(const PairDev *__restrict__ pairs,
                                                const FrameDev *__restrict__ frames,
                                                const PoseDev *__restrict__ items, EvalCfgDev cfg,
                                                uint2 *__restrict__ scratch,
                                                int64_t scratch_stride) {
+  constexpr bool DIRECT = MODE == 1, TILED = MODE == 2;
   extern __shared__ __align__(16) unsigned char smem[];
   const int T = blockDim.x, tid = threadIdx.x, lane = tid & 63, W = T >> 6;
   const int wid = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -341,7 +361,247 @@ __global__ void __launch_bounds__(1024) k_eval(const PairDev *__restrict__ pairs
       __syncthreads();
     }
 
-    for (int s0 = 0; s0 < NS; s0 += G) {
+    // Four candidates per lane, branch-free up to the rare collisions:
+    // find or claim each in-brick candidate's slot, then add its sums.
+    // (p: the brick's parity, whose overflow flag and occupied count it uses;
+    // max_probe: slots a probe sequence may visit before the brick overflows)
+    auto insert4 = [&](bool (&inb)[4], const uint32_t (&key)[4],
+                       const unsigned long long (&add1)[4],
+                       const unsigned long long (&add2)[4], const int p, const int max_probe) {
+      uint32_t h[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) h[i] = __umulhi(key[i] * 2654435761u, (uint32_t)cap);
+      bool coll[4], fresh[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        // one compare-and-swap finds or claims the home slot (only lanes
+        // holding a run issue it)
+        uint32_t old = kEmpty;
+        if (inb[i]) old = atomicCAS(&hkey[h[i]], kEmpty, key[i]);
+        fresh[i] = inb[i] && old == kEmpty;
+        coll[i] = inb[i] && old != kEmpty && old != key[i];
+      }
+      if (coll[0] || coll[1] || coll[2] || coll[3]) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          if (!coll[i]) continue;
+          uint32_t hh = h[i];
+          bool ok = false;
+          for (int pr = 1; pr < max_probe; ++pr) {
+            hh = hh + 1u == (uint32_t)cap ? 0u : hh + 1u;
+            uint32_t k1 = __atomic_load_n(&hkey[hh], __ATOMIC_RELAXED);
+            if (k1 == kEmpty) {
+              k1 = atomicCAS(&hkey[hh], kEmpty, key[i]);
+              if (k1 == kEmpty) fresh[i] = true;
+            }
+            if (k1 == kEmpty || k1 == key[i]) { ok = true; break; }
+          }
+          if (ok) h[i] = hh;
+          else { ovf[p] = 1u; inb[i] = false; }
+        }
+      }
+      // newly claimed slots go on the brick's occupied list (one LDS atomic per wave)
+      {
+        unsigned long long m[4];
+        uint32_t tot = 0;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          m[i] = __ballot(fresh[i]);
+          tot += (uint32_t)__popcll(m[i]);
+        }
+        if (tot) {
+          uint32_t base = 0;
+          if (lane == 0) base = atomicAdd(&occn[p], tot);
+          base = __builtin_amdgcn_readfirstlane(base);  // every lane is active here
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            if (fresh[i]) {
+              const uint32_t r = __builtin_amdgcn_mbcnt_hi(
+                  (uint32_t)(m[i] >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m[i], 0u));
+              occ[base + r] = (uint16_t)h[i];
+            }
+            base += (uint32_t)__popcll(m[i]);
+          }
+        }
+      }
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        if (inb[i]) {
+          if (ZVAR) {
+            atomicAdd(&hv1[h[i]], add1[i]);
+            atomicAdd(&hv2[h[i]], add2[i]);
+          } else {
+            atomicAdd(&hcnt[h[i]], (uint32_t)add1[i]);
+          }
+        }
+      }
+    };
+    // One voxel of B in O: a count in each feature's joint histogram at
+    // (A's bin, B's bin) from the voxel's sums n, S1, S2.
+    auto hist_add = [&](const uint32_t nn, const unsigned long long s1,
+                        const unsigned long long s2, const int a0, const int a1) {
+      // count bins: O(1) with the default edges 1, 2, ..., nb - 1; the joint
+      // feature numbers its (count, z-variance) bin pairs
+      auto count_bin = [&]() -> int {
+        return count_default ? (int)min(nn, (uint32_t)(nbc - 1)) : bin_count_dev(nn, nbc, cedge);
+      };
+      auto bin_of = [&](uint32_t kind) -> int {
+        if (kind == MI_FEAT_COUNT || !ZVAR) return count_bin();
+        // one point has zero variance: 1 + the number of zero edges
+        const int bz = nn == 1u ? 1 + zvar_zero : bin_zvar_nodiv(nn, s1, s2, nbz, zedged, zedge);
+        if (kind == MI_FEAT_ZVAR) return bz;
+        return joint_value(count_bin(), bz, nbz);
+      };
+      atomicAdd(&myhist[a0 * nb0 + bin_of(kind0)], 1u);
+      if (nf > 1) atomicAdd(&myhist[hoff1 + a1 * nb1 + bin_of(kind1)], 1u);
+    };
+
+    if (TILED) {
+      double R[9];
+#pragma unroll
+      for (int a = 0; a < 9; ++a) R[a] = Fr.R[a];
+      const double fs = Fr.s, vox = P.voxel;
+      const int tnx = P.tile_nx, tny = P.tile_ny, ntiles = tnx * tny;
+      const double tx0 = P.tile_x0, ty0 = P.tile_y0, tilx = P.tile_ilx, tily = P.tile_ily;
+      const int qxb = P.key_xbits, qyb = P.key_ybits;
+      const uint32_t qxm = (1u << qxb) - 1u, qym = (1u << qyb) - 1u;
+      // the tiles' points through one buffer resource (below 2^28 entries):
+      // x, y and z arrays at scalar offsets 0, 4 * stride and 8 * stride
+      const uint32_t ts = (uint32_t)P.tile_stride;
+      const brsrc rt = buf_rsrc(P.tile_xyz, 12u * ts);
+      const uint32_t toy = 4u * ts, toz = 8u * ts;
+      for (int t = 0; t < ntiles; ++t) {
+        const uint32_t tst = P.tile_off[t], ten = P.tile_off[t + 1], town = P.tile_own[t];
+        if (ten == tst) continue;
+        const int ti = t % tnx, tj = t / tnx;
+        // A tile that overflows the hash is redone in parts: part (lvl, idx)
+        // takes the voxels whose mixed key has idx in its top lvl bits, and
+        // splits into (lvl + 1, 2 idx) and (lvl + 1, 2 idx + 1); parts are taken
+        // depth first.  From lvl 2 on, probing is unlimited, so a part only
+        // overflows if its voxels exceed the slots.
+        int lvl = 0;
+        uint32_t part = 0;
+        for (;;) {
+          const int p = parity;
+          const int max_probe =
+              ((int64_t)(ten - tst) <= cfg.load_max || lvl >= 2) ? cap : kMaxProbe;
+          unsigned long long bnear = 0;
+          // 256 consecutive entries per wave step, four per lane, 64 apart
+          for (uint32_t b = tst + (uint32_t)wid * 256u; b < ten; b += 256u * (uint32_t)W) {
+            float fx[4], fy[4], fz[4];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+              const uint32_t idx = b + (uint32_t)j * 64u + (uint32_t)lane;
+              const uint32_t e = idx < ten ? idx : tst;
+              fx[j] = buf_f32(rt, 4u * e, 0u);
+              fy[j] = buf_f32(rt, 4u * e, toy);
+              fz[j] = buf_f32(rt, 4u * e, toz);
+            }
+            bool inb[4];
+            uint32_t key[4];
+            unsigned long long add1[4], add2[4];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+              const uint32_t idx = b + (uint32_t)j * 64u + (uint32_t)lane;
+              const DirectVoxel dv = direct_voxel<ZVAR, NEAR, true>(fx[j], fy[j], fz[j], R, fs, cx,
+                                                                     cy, cz, nx, ny, nz, vox);
+              key[j] = ((uint32_t)dv.iz << (qxb + qyb)) | ((uint32_t)dv.iy << qxb) |
+                       (uint32_t)dv.ix;
+              inb[j] = idx < ten && dv.in &&
+                       (lvl == 0 || (mix32(key[j]) >> (32 - lvl)) == part);
+              add1[j] = ZVAR ? ((1ull << 44) | (unsigned long long)dv.q) : 1ull;
+              add2[j] = ZVAR ? (unsigned long long)dv.q * dv.q : 0ull;
+              // a point is tallied once: in its own tile, in its voxel's part
+              if (NEAR && inb[j] && idx < town && dv.near && dv.ix >= alo0 && dv.ix <= ahi0 &&
+                  dv.iy >= alo1 && dv.iy <= ahi1 && dv.iz >= alo2 && dv.iz <= ahi2)
+                ++bnear;
+            }
+            insert4(inb, key, add1, add2, p, max_probe);
+          }
+          __syncthreads();
+          const bool overflow = ovf[p] != 0u;
+          const int nocc = (int)occn[p];
+          if (tid == 0) { ovf[p ^ 1] = 0u; occn[p ^ 1] = 0u; }
+          int blo0 = nx, blo1 = ny, blo2 = nz, bhi0 = -1, bhi1 = -1, bhi2 = -1;
+          unsigned long long bnin = 0;
+          for (int i = tid; i < nocc; i += 2 * T) {
+            bool inO[2];
+            uint32_t n[2], lin[2];
+            unsigned long long s1[2], s2[2];
+#pragma unroll
+            for (int j = 0; j < 2; ++j) {
+              const int ii = i + j * T;
+              inO[j] = false;
+              n[j] = 0u;
+              s1[j] = s2[j] = 0ull;
+              lin[j] = 0u;
+              if (ii >= nocc) continue;
+              const uint32_t h = occ[ii];
+              const uint32_t key = hkey[h];
+              const int ix = (int)(key & qxm), iy = (int)((key >> qxb) & qym);
+              const int iz = (int)(key >> (qxb + qyb));
+              if (ZVAR) {
+                const unsigned long long a = hv1[h];
+                n[j] = (uint32_t)(a >> 44);
+                s1[j] = a & ((1ull << 44) - 1);
+                s2[j] = hv2[h];
+                hv1[h] = 0ull;
+                hv2[h] = 0ull;
+              } else {
+                n[j] = hcnt[h];
+                hcnt[h] = 0u;
+              }
+              hkey[h] = kEmpty;
+              // the voxel's owner: the tile holding its centre mapped back into
+              // B's frame, R^T ((centre - c) voxel)
+              const double dx = ((double)ix + 0.5 - cx) * vox;
+              const double dy = ((double)iy + 0.5 - cy) * vox;
+              const double dz = ((double)iz + 0.5 - cz) * vox;
+              const double bx = (R[0] * dx + R[3] * dy) + R[6] * dz;
+              const double by = (R[1] * dx + R[4] * dy) + R[7] * dz;
+              const int oi = min(max((int)floor((bx - tx0) * tilx), 0), tnx - 1);
+              const int oj = min(max((int)floor((by - ty0) * tily), 0), tny - 1);
+              if (overflow || oi != ti || oj != tj) continue;
+              bnin += n[j];
+              blo0 = min(blo0, ix); blo1 = min(blo1, iy); blo2 = min(blo2, iz);
+              bhi0 = max(bhi0, ix); bhi1 = max(bhi1, iy); bhi2 = max(bhi2, iz);
+              inO[j] = ix >= alo0 && ix <= ahi0 && iy >= alo1 && iy <= ahi1 && iz >= alo2 &&
+                       iz <= ahi2;
+              lin[j] = ((uint32_t)iz * (uint32_t)ny + (uint32_t)iy) * (uint32_t)nx + (uint32_t)ix;
+            }
+            int a0[2], a1[2];
+#pragma unroll
+            for (int j = 0; j < 2; ++j) {
+              a0[j] = inO[j] ? (int)buf_u8(rbin0, lin[j]) : 0;
+              a1[j] = inO[j] && nf > 1 ? (int)buf_u8(rbin1, lin[j]) : 0;
+            }
+#pragma unroll
+            for (int j = 0; j < 2; ++j)
+              if (inO[j]) hist_add(n[j], s1[j], s2[j], a0[j], a1[j]);
+          }
+          __syncthreads();
+          parity ^= 1;
+          if (overflow) {
+            ++lvl;
+            part <<= 1;
+            continue;
+          }
+          nin += bnin;
+          nnear += bnear;
+          lo0 = min(lo0, blo0); lo1 = min(lo1, blo1); lo2 = min(lo2, blo2);
+          hi0 = max(hi0, bhi0); hi1 = max(hi1, bhi1); hi2 = max(hi2, bhi2);
+          // next part, depth first
+          ++part;
+          while (lvl > 0 && (part & 1u) == 0u) {
+            part >>= 1;
+            --lvl;
+          }
+          if (lvl == 0) break;
+        }
+      }
+    }
+
+    for (int s0 = 0; !TILED && s0 < NS; s0 += G) {
       const int gn = min(G, NS - s0);
       // ---- plan: offsets of every candidate row at every piece cut
       for (int e = tid; !DIRECT && e < gn * PE; e += T) {
@@ -448,79 +708,6 @@ __global__ void __launch_bounds__(1024) k_eval(const PairDev *__restrict__ pairs
                 *n_valid = rem;
                 return rem > 0 ? st + off0 : st;
               };
-              // Four candidates per lane, branch-free up to the rare collisions:
-              // find or claim each in-brick candidate's slot, then add its sums.
-              auto insert4 = [&](bool (&inb)[4], const uint32_t (&key)[4],
-                                 const unsigned long long (&add1)[4],
-                                 const unsigned long long (&add2)[4]) {
-                uint32_t h[4];
-  #pragma unroll
-                for (int i = 0; i < 4; ++i) h[i] = __umulhi(key[i] * 2654435761u, (uint32_t)cap);
-                bool coll[4], fresh[4];
-  #pragma unroll
-                for (int i = 0; i < 4; ++i) {
-                  // one compare-and-swap finds or claims the home slot (only lanes
-                  // holding a run issue it)
-                  uint32_t old = kEmpty;
-                  if (inb[i]) old = atomicCAS(&hkey[h[i]], kEmpty, key[i]);
-                  fresh[i] = inb[i] && old == kEmpty;
-                  coll[i] = inb[i] && old != kEmpty && old != key[i];
-                }
-                if (coll[0] || coll[1] || coll[2] || coll[3]) {
-  #pragma unroll
-                  for (int i = 0; i < 4; ++i) {
-                    if (!coll[i]) continue;
-                    uint32_t hh = h[i];
-                    bool ok = false;
-                    for (int pr = 1; pr < max_probe; ++pr) {
-                      hh = hh + 1u == (uint32_t)cap ? 0u : hh + 1u;
-                      uint32_t k1 = __atomic_load_n(&hkey[hh], __ATOMIC_RELAXED);
-                      if (k1 == kEmpty) {
-                        k1 = atomicCAS(&hkey[hh], kEmpty, key[i]);
-                        if (k1 == kEmpty) fresh[i] = true;
-                      }
-                      if (k1 == kEmpty || k1 == key[i]) { ok = true; break; }
-                    }
-                    if (ok) h[i] = hh;
-                    else { ovf[p] = 1u; inb[i] = false; }
-                  }
-                }
-                // newly claimed slots go on the brick's occupied list (one LDS atomic per wave)
-                {
-                  unsigned long long m[4];
-                  uint32_t tot = 0;
-  #pragma unroll
-                  for (int i = 0; i < 4; ++i) {
-                    m[i] = __ballot(fresh[i]);
-                    tot += (uint32_t)__popcll(m[i]);
-                  }
-                  if (tot) {
-                    uint32_t base = 0;
-                    if (lane == 0) base = atomicAdd(&occn[p], tot);
-                    base = __builtin_amdgcn_readfirstlane(base);  // every lane is active here
-  #pragma unroll
-                    for (int i = 0; i < 4; ++i) {
-                      if (fresh[i]) {
-                        const uint32_t r = __builtin_amdgcn_mbcnt_hi(
-                            (uint32_t)(m[i] >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m[i], 0u));
-                        occ[base + r] = (uint16_t)h[i];
-                      }
-                      base += (uint32_t)__popcll(m[i]);
-                    }
-                  }
-                }
-  #pragma unroll
-                for (int i = 0; i < 4; ++i) {
-                  if (inb[i]) {
-                    if (ZVAR) {
-                      atomicAdd(&hv1[h[i]], add1[i]);
-                      atomicAdd(&hv2[h[i]], add2[i]);
-                    } else {
-                      atomicAdd(&hcnt[h[i]], (uint32_t)add1[i]);
-                    }
-                  }
-                }
-              };
               // Frame candidates: u = fl(v + c), voxel floor(u), in-brick test.
               auto step4 = [&](const bool (&val)[4], const double (&vx)[4], const double (&vy)[4],
                                const double (&vz)[4]) {
@@ -570,7 +757,7 @@ __global__ void __launch_bounds__(1024) k_eval(const PairDev *__restrict__ pairs
                 }
   #pragma unroll
                 for (int i = 1; i < 4; ++i) inb[i] = inb[i] && !same[i];
-                insert4(inb, key, add1, add2);
+                insert4(inb, key, add1, add2, p, max_probe);
               };
               // Four chunks per wave step: the twelve loads are issued together, then
               // the four candidates of each lane go through step4 together.  Lanes
@@ -602,7 +789,7 @@ __global__ void __launch_bounds__(1024) k_eval(const PairDev *__restrict__ pairs
                   add1[i] = ZVAR ? ((1ull << 44) | (unsigned long long)q[i]) : 1ull;
                   add2[i] = ZVAR ? (unsigned long long)q[i] * q[i] : 0ull;
                 }
-                insert4(inb, key, add1, add2);
+                insert4(inb, key, add1, add2, p, max_probe);
               }
               for (int k = wid; !DIRECT && k < nch; k += W) {
                 int nv;
@@ -680,26 +867,8 @@ __global__ void __launch_bounds__(1024) k_eval(const PairDev *__restrict__ pairs
                   a1[j] = inO[j] && nf > 1 ? (int)buf_u8(rbin1, lin[j]) : 0;
                 }
 #pragma unroll
-                for (int j = 0; j < 2; ++j) {
-                  if (!inO[j]) continue;
-                  const uint32_t nn = n[j];
-                  // count bins: O(1) with the default edges 1, 2, ..., nb - 1; the
-                  // joint feature numbers its (count, z-variance) bin pairs
-                  auto count_bin = [&]() -> int {
-                    return count_default ? (int)min(nn, (uint32_t)(nbc - 1))
-                                         : bin_count_dev(nn, nbc, cedge);
-                  };
-                  auto bin_of = [&](uint32_t kind) -> int {
-                    if (kind == MI_FEAT_COUNT || !ZVAR) return count_bin();
-                    // one point has zero variance: 1 + the number of zero edges
-                    const int bz = nn == 1u ? 1 + zvar_zero
-                                            : bin_zvar_nodiv(nn, s1[j], s2[j], nbz, zedged, zedge);
-                    if (kind == MI_FEAT_ZVAR) return bz;
-                    return joint_value(count_bin(), bz, nbz);
-                  };
-                  atomicAdd(&myhist[a0[j] * nb0 + bin_of(kind0)], 1u);
-                  if (nf > 1) atomicAdd(&myhist[hoff1 + a1[j] * nb1 + bin_of(kind1)], 1u);
-                }
+                for (int j = 0; j < 2; ++j)
+                  if (inO[j]) hist_add(n[j], s1[j], s2[j], a0[j], a1[j]);
               }
               __syncthreads();
               parity ^= 1;
@@ -852,7 +1021,7 @@ size_t eval_lds_bytes(const EvalLaunch &c) {
       .total;
 }
 
-template <bool NEAR, bool ZVAR, bool DIRECT>
+template <bool NEAR, bool ZVAR, int MODE>
 static hipError_t launch_one(const PairDev *pairs_dev, const FrameDev *frames_dev,
                              const PoseDev *items_dev, int64_t n_items, const int64_t *xcd_start,
                              const EvalLaunch &c, uint2 *scratch, int64_t scratch_stride,
@@ -879,14 +1048,14 @@ static hipError_t launch_one(const PairDev *pairs_dev, const FrameDev *frames_de
     longest = std::max(longest, d.xcd_start[x + 1] - d.xcd_start[x]);
   }
   if (d.xcd_start[0] != 0 || d.xcd_start[kXcds] != n_items) return hipErrorInvalidValue;
-  hipError_t e = hipFuncSetAttribute((const void *)k_eval<NEAR, ZVAR, DIRECT>,
+  hipError_t e = hipFuncSetAttribute((const void *)k_eval<NEAR, ZVAR, MODE>,
                                      hipFuncAttributeMaxDynamicSharedMemorySize, L.total);
   if (e != hipSuccess) return e;
   int64_t wpx = std::max<int64_t>(1, longest);  // workgroups per XCD
   if (max_wgs > 0) wpx = std::max<int64_t>(1, std::min<int64_t>(wpx, max_wgs / kXcds));
   const int64_t grid = wpx * kXcds;
   if (grid > 0x7fffffff) return hipErrorInvalidValue;
-  k_eval<NEAR, ZVAR, DIRECT><<<(unsigned)grid, c.waves * 64, (size_t)L.total, s>>>(
+  k_eval<NEAR, ZVAR, MODE><<<(unsigned)grid, c.waves * 64, (size_t)L.total, s>>>(
       pairs_dev, frames_dev, items_dev, d, scratch, scratch_stride);
   return hipGetLastError();
 }
@@ -894,7 +1063,7 @@ static hipError_t launch_one(const PairDev *pairs_dev, const FrameDev *frames_de
 // Workgroups of a persistent grid for this launch shape: the compute units
 // times the resident workgroups per unit (at most per_cu), a multiple of the
 // XCD count.
-hipError_t eval_resident_wgs(const EvalLaunch &c, int per_cu, int64_t *out) {
+hipError_t eval_resident_wgs(const EvalLaunch &c, int per_cu, int64_t *out, int mode) {
   const Layout L = eval_layout(c.waves, c.hist_copies, c.hist_words, c.plan_bytes,
                                c.cap, c.zvar);
   hipError_t e;
@@ -902,8 +1071,12 @@ hipError_t eval_resident_wgs(const EvalLaunch &c, int per_cu, int64_t *out) {
   if ((e = hipGetDevice(&dev)) != hipSuccess) return e;
   if ((e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess)
     return e;
-  const void *fn = (const void *)k_eval<false, false, true>;
-  if (c.zvar) fn = (const void *)k_eval<false, true, true>;
+  const void *fn = mode == 0   ? (c.zvar ? (const void *)k_eval<false, true, 0>
+                                          : (const void *)k_eval<false, false, 0>)
+                   : mode == 2 ? (c.zvar ? (const void *)k_eval<false, true, 2>
+                                          : (const void *)k_eval<false, false, 2>)
+                               : (c.zvar ? (const void *)k_eval<false, true, 1>
+                                          : (const void *)k_eval<false, false, 1>);
   if ((e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, L.total)) !=
       hipSuccess)
     return e;
@@ -925,13 +1098,13 @@ hipError_t launch_eval(const PairDev *pairs_dev, const FrameDev *frames_dev,
     if (e != hipSuccess) return e;
   }
   if (c.near_face)
-    return c.zvar ? launch_one<true, true, false>(pairs_dev, frames_dev, items_dev, n_items,
+    return c.zvar ? launch_one<true, true, 0>(pairs_dev, frames_dev, items_dev, n_items,
                                                   xcd_start, c, nullptr, 0, max_wgs, s)
-                  : launch_one<true, false, false>(pairs_dev, frames_dev, items_dev, n_items,
+                  : launch_one<true, false, 0>(pairs_dev, frames_dev, items_dev, n_items,
                                                    xcd_start, c, nullptr, 0, max_wgs, s);
-  return c.zvar ? launch_one<false, true, false>(pairs_dev, frames_dev, items_dev, n_items,
+  return c.zvar ? launch_one<false, true, 0>(pairs_dev, frames_dev, items_dev, n_items,
                                                  xcd_start, c, nullptr, 0, max_wgs, s)
-                : launch_one<false, false, false>(pairs_dev, frames_dev, items_dev, n_items,
+                : launch_one<false, false, 0>(pairs_dev, frames_dev, items_dev, n_items,
                                                   xcd_start, c, nullptr, 0, max_wgs, s);
 }
 
@@ -941,14 +1114,29 @@ hipError_t launch_eval_direct(const PairDev *pairs_dev, const FrameDev *frames_d
                               int64_t slots, hipStream_t s) {
   if (n_items <= 0) return hipSuccess;
   if (c.near_face)
-    return c.zvar ? launch_one<true, true, true>(pairs_dev, frames_dev, items_dev, n_items,
+    return c.zvar ? launch_one<true, true, 1>(pairs_dev, frames_dev, items_dev, n_items,
                                                  xcd_start, c, scratch, scratch_stride, slots, s)
-                  : launch_one<true, false, true>(pairs_dev, frames_dev, items_dev, n_items,
+                  : launch_one<true, false, 1>(pairs_dev, frames_dev, items_dev, n_items,
                                                   xcd_start, c, scratch, scratch_stride, slots, s);
-  return c.zvar ? launch_one<false, true, true>(pairs_dev, frames_dev, items_dev, n_items,
+  return c.zvar ? launch_one<false, true, 1>(pairs_dev, frames_dev, items_dev, n_items,
                                                 xcd_start, c, scratch, scratch_stride, slots, s)
-                : launch_one<false, false, true>(pairs_dev, frames_dev, items_dev, n_items,
+                : launch_one<false, false, 1>(pairs_dev, frames_dev, items_dev, n_items,
                                                  xcd_start, c, scratch, scratch_stride, slots, s);
+}
+
+hipError_t launch_eval_tiles(const PairDev *pairs_dev, const FrameDev *frames_dev,
+                             const PoseDev *items_dev, int64_t n_items, const int64_t *xcd_start,
+                             const EvalLaunch &c, int64_t slots, hipStream_t s) {
+  if (n_items <= 0) return hipSuccess;
+  if (c.near_face)
+    return c.zvar ? launch_one<true, true, 2>(pairs_dev, frames_dev, items_dev, n_items,
+                                              xcd_start, c, nullptr, 0, slots, s)
+                  : launch_one<true, false, 2>(pairs_dev, frames_dev, items_dev, n_items,
+                                               xcd_start, c, nullptr, 0, slots, s);
+  return c.zvar ? launch_one<false, true, 2>(pairs_dev, frames_dev, items_dev, n_items,
+                                             xcd_start, c, nullptr, 0, slots, s)
+                : launch_one<false, false, 2>(pairs_dev, frames_dev, items_dev, n_items,
+                                              xcd_start, c, nullptr, 0, slots, s);
 }
 
 }  // namespace mi

@@ -7,6 +7,7 @@
 
 #include <algorithm>
 #include <array>
+#include <atomic>
 #include <chrono>
 #include <deque>
 #include <map>
@@ -19,6 +20,7 @@
 #include <new>
 #include <mutex>
 #include <string>
+#include <thread>
 #include <unordered_map>
 #include <vector>
 
@@ -172,6 +174,9 @@ namespace {
 constexpr int32_t kAutoHashBytes = 66 * 1024;
 constexpr int32_t kFitHashBytes = 60 * 1024;
 constexpr int64_t kTwoWorkgroupLds = 80 * 1024;
+// The tiled per-pose form under the auto tuning: one workgroup of this many
+// waves per compute unit, its voxel hash taking the LDS the rest leaves.
+constexpr int32_t kTileWaves = 16;
 struct Tuning {
   int32_t waves = 8;
   int32_t hash_bytes = 0;  // 0: auto
@@ -763,6 +768,102 @@ bool choose_stripes(const GridInfo &gi, const Tuning &tu, bool zvar, StripeShape
   return true;
 }
 
+// ------------------------------------------------------------- scan B tiles
+
+// Halo width of the tiled per-pose form, in voxels: above half a voxel
+// diagonal (0.866), with room for the rounding of the two transforms.
+constexpr double kTileHalo = 0.88;
+
+// Most tiles of a scan of n_b points (fixes the tile tables' size before the
+// scan is read).
+int64_t tiles_max(int64_t n_b) { return std::max<int64_t>(1, n_b / 128); }
+
+struct TileGeom {
+  double x0 = 0.0, y0 = 0.0, ilx = 1.0, ily = 1.0, hx = 0.0, hy = 0.0;
+  int32_t nx = 1, ny = 1;
+};
+
+// Tiles of scan B's own (x, y) frame: the box of its finite points (outliers
+// aside) cut into nx x ny equal tiles, as many as keep the distinct voxels of
+// a tile and its halo near half of the hash slots (counted on voxels of B's
+// own frame; a posed scan fills somewhat more, and a tile that overflows is
+// redone in parts).  Tiles are at least three halo widths wide, so the halo of
+// a tile only takes points of its 8 neighbours.
+TileGeom choose_tiles(const float *xyz, int64_t n, double voxel, int32_t cap) {
+  TileGeom g;
+  const float *X = xyz, *Y = xyz + n, *Z = xyz + 2 * n;
+  std::vector<uint64_t> keys;
+  std::vector<float> xs, ys;
+  keys.reserve((size_t)n);
+  xs.reserve((size_t)n);
+  ys.reserve((size_t)n);
+  auto cell = [&](float v) -> uint64_t {
+    const double c = std::floor((double)v / voxel) + (double)(1 << 20);
+    return (uint64_t)std::min(std::max(c, 0.0), (double)((1 << 21) - 1));
+  };
+  for (int64_t i = 0; i < n; ++i) {
+    if (!std::isfinite(X[i]) || !std::isfinite(Y[i]) || !std::isfinite(Z[i])) continue;
+    xs.push_back(X[i]);
+    ys.push_back(Y[i]);
+    keys.push_back(cell(X[i]) | (cell(Y[i]) << 21) | (cell(Z[i]) << 42));
+  }
+  if (keys.empty()) return g;
+  // the box of the central 99.8 % of the points (the rest clamp to the edge tiles)
+  const size_t m = xs.size(), lo = m / 1000, hi = m - 1 - m / 1000;
+  std::nth_element(xs.begin(), xs.begin() + lo, xs.end());
+  const double x0 = xs[lo];
+  std::nth_element(xs.begin(), xs.begin() + hi, xs.end());
+  const double x1 = xs[hi];
+  std::nth_element(ys.begin(), ys.begin() + lo, ys.end());
+  const double y0 = ys[lo];
+  std::nth_element(ys.begin(), ys.begin() + hi, ys.end());
+  const double y1 = ys[hi];
+  std::sort(keys.begin(), keys.end());
+  keys.erase(std::unique(keys.begin(), keys.end()), keys.end());
+  const double h = kTileHalo * voxel;
+  const double W = std::max(x1 - x0, voxel), H = std::max(y1 - y0, voxel);
+  const double target = std::max(64.0, cap / 2.0);
+  const int64_t tmax = tiles_max(n);
+  const int nxmax = std::max(1, (int)std::min(W / (3.0 * h), 65536.0));
+  const int nymax = std::max(1, (int)std::min(H / (3.0 * h), 65536.0));
+  std::vector<int32_t> cnt;
+  double nt = std::ceil((double)keys.size() / target);
+  for (int it = 0;; ++it) {
+    int nx = std::max(1, (int)std::min(std::llround(std::sqrt(nt * W / H)), (long long)nxmax));
+    int ny = std::max(1, std::min((int)std::ceil(nt / nx), nymax));
+    while ((int64_t)nx * ny > tmax) {
+      if (nx >= ny && nx > 1) --nx;
+      else --ny;
+    }
+    g.nx = nx; g.ny = ny; g.x0 = x0; g.y0 = y0;
+    g.ilx = (double)nx / W;
+    g.ily = (double)ny / H;
+    g.hx = nx > 1 ? h * g.ilx : 0.0;
+    g.hy = ny > 1 ? h * g.ily : 0.0;
+    // distinct voxels per tile with its halo, at the voxels' centres
+    cnt.assign((size_t)nx * ny, 0);
+    int32_t worst = 0;
+    for (uint64_t k : keys) {
+      const double cx = ((double)(k & 0x1fffff) - (double)(1 << 20) + 0.5) * voxel;
+      const double cy = ((double)((k >> 21) & 0x1fffff) - (double)(1 << 20) + 0.5) * voxel;
+      const double fx = (cx - g.x0) * g.ilx, fy = (cy - g.y0) * g.ily;
+      const int i = std::min(std::max((int)std::floor(fx), 0), nx - 1);
+      const int j = std::min(std::max((int)std::floor(fy), 0), ny - 1);
+      const double rx = fx - i, ry = fy - j;
+      const int di = (i > 0 && rx < g.hx) ? -1 : (i + 1 < nx && rx > 1.0 - g.hx) ? 1 : 0;
+      const int dj = (j > 0 && ry < g.hy) ? -1 : (j + 1 < ny && ry > 1.0 - g.hy) ? 1 : 0;
+      worst = std::max(worst, ++cnt[(size_t)(j * nx + i)]);
+      if (di) worst = std::max(worst, ++cnt[(size_t)(j * nx + i + di)]);
+      if (dj) worst = std::max(worst, ++cnt[(size_t)((j + dj) * nx + i)]);
+      if (di && dj) worst = std::max(worst, ++cnt[(size_t)((j + dj) * nx + i + di)]);
+    }
+    if (worst <= target || it >= 12 || (int64_t)nx * ny >= tmax || (nx >= nxmax && ny >= nymax))
+      break;
+    nt *= 1.3;
+  }
+  return g;
+}
+
 }  // namespace
 
 // One scan pair of a plan as the host keeps it.
@@ -787,8 +888,14 @@ struct mi_plan {
   std::vector<uint32_t *> chunk_cur; // contiguous column cursors of each chunk's frames
   std::vector<std::array<int64_t, kXcds + 1>> chunk_xcd;  // runs per XCD within each chunk
   std::array<int64_t, kXcds + 1> direct_xcd;              // and within the per-pose items
-  int64_t n_frame_items;             // items [n_frame_items, n_items) are per-pose
-  int64_t direct_point_poses;
+  int64_t n_frame_items;             // items [n_frame_items, n_items) are per-pose:
+  int64_t n_stripe_items;            // first those bucketed by stripe, then the tiled ones
+  int64_t direct_point_poses, tile_point_poses;
+  std::array<int64_t, kXcds + 1> tile_xcd;  // runs per XCD within the tiled items
+  int32_t n_tiled;                   // tiled pairs
+  int32_t *tiled_dev;                // their pair indices
+  uint32_t *tile_cnt;                // every tiled pair's tile counts
+  int64_t tile_cnt_words, tile_max_n;
   uint2 *scratch;                    // per-pose buckets: slots x stride
   int64_t scratch_stride, scratch_slots;
   PoseDev *items_dev;
@@ -796,6 +903,8 @@ struct mi_plan {
   FrameDev *frames_dev;
   unsigned long long *nonfinite;     // [pairs][2]
   EvalLaunch launch;
+  EvalLaunch tile_launch;            // the tiled per-pose form's
+  int64_t tile_slots;
   mi_tuning tuning;                  // the tuning the plan was created under
 };
 
@@ -853,11 +962,16 @@ FrameBytes frame_bytes(int64_t n_b, int64_t ncols) {
 struct BatchTables {
   std::vector<PoseTables> T;
   std::vector<StripeShape> SS;
-  std::vector<char> direct;          // per pair: per-pose bucketing instead of frames
+  std::vector<char> direct;          // per pair: 0 frames, 1 per-pose stripe buckets, 2 tiles
+  std::vector<int64_t> n_b;          // per pair: points of scan B
   std::vector<int32_t> frame_start;  // per pair: first entry in the frame table
   EvalLaunch L;
+  EvalLaunch Lt;                     // launch of the tiled per-pose form
+  int64_t tile_slots = 0;            // its workgroups
   int64_t n_items = 0;
   int64_t n_frame_items = 0;         // items of frame-mode pairs (they come first)
+  int64_t n_stripe_items = 0;        // then items of stripe-bucketed pairs, then tiled ones
+  int32_t n_tiled = 0;               // tiled pairs
   int32_t F = 0;                     // frame table entries
   int32_t F_built = 0;               // entries of frame-mode pairs (built; they come first)
   int64_t scratch_stride = 0;        // largest n_b of a per-pose pair
@@ -865,7 +979,9 @@ struct BatchTables {
   mi_tuning tuning = {};             // in force, the auto hash resolved to its size
 };
 
-mi_status prepare_batch(const mi_work_item *w, int64_t n, uint32_t flags, BatchTables &B) {
+// tiles: per-pose pairs may be tiled (scan B is read when the plan is made).
+mi_status prepare_batch(const mi_work_item *w, int64_t n, uint32_t flags, BatchTables &B,
+                        bool tiles = false) {
   if (n < 0 || (n > 0 && !w)) return fail(MI_E_INVALID, "bad work item list");
   if (n >= ((int64_t)1 << 20)) return fail(MI_E_UNSUPPORTED, "more than 2^20 work items");
   if (flags & ~(uint32_t)(MI_EVAL_NEAR_FACE | MI_EVAL_PER_POSE | MI_EVAL_SHARED_FRAMES))
@@ -886,8 +1002,10 @@ mi_status prepare_batch(const mi_work_item *w, int64_t n, uint32_t flags, BatchT
   B.T.assign((size_t)n, PoseTables());
   B.SS.assign((size_t)n, StripeShape());
   B.direct.assign((size_t)n, 0);
+  B.n_b.assign((size_t)n, 0);
   B.frame_start.assign((size_t)n, 0);
   Tuning tu = tuning_now();
+  const bool auto_tuned = tu.hash_bytes == 0;
   if (tu.hash_bytes == 0) {
     tu.hash_bytes = kAutoHashBytes;
     // the default hash only where the launch keeps two workgroups per CU
@@ -943,8 +1061,13 @@ mi_status prepare_batch(const mi_work_item *w, int64_t n, uint32_t flags, BatchT
     const bool direct = (flags & MI_EVAL_PER_POSE) ||
                         (!(flags & MI_EVAL_SHARED_FRAMES) && small && it.K > 0 &&
                          2 * (int64_t)T.F > it.K);
-    B.direct[(size_t)i] = direct;
-    if (direct) {
+    B.n_b[(size_t)i] = it.n_b;
+    // tiled: the tile entries (at most 4 per point) are addressed with 32-bit
+    // offsets, and the whole-grid voxel key fits 31 bits
+    const bool tiled = direct && tiles && it.n_b > 0 && it.n_b < ((int64_t)1 << 26) &&
+                       bits_for(gi.dims[0]) + bits_for(gi.dims[1]) + bits_for(gi.dims[2]) <= 31;
+    B.direct[(size_t)i] = tiled ? 2 : direct ? 1 : 0;
+    if (direct && !tiled) {
       // A per-pose brick rescans its stripe's whole bucket, so overflow retries
       // are costly: stripes are sized for about a third of the slots, taking
       // about 0.6 occupied voxels per point spread evenly over the rows.
@@ -956,9 +1079,12 @@ mi_status prepare_batch(const mi_work_item *w, int64_t n, uint32_t flags, BatchT
         return fail(MI_E_UNSUPPORTED, "work item %lld: evaluator: %s", (long long)i, why);
     }
     const StripeShape &S = B.SS[(size_t)i];
-    if (direct) {
+    if (tiled) {
+      ++B.n_tiled;
+    } else if (direct) {
       plan_bytes_max = std::max(plan_bytes_max, (2 * S.n_stripes + 1) * 4);
       B.scratch_stride = std::max(B.scratch_stride, std::max<int64_t>(it.n_b, 1));
+      B.n_stripe_items += it.K;
     } else {
       plan_bytes_max = std::max(plan_bytes_max, S.plan_stripes * S.plan_entries * 8);
       B.n_frame_items += it.K;
@@ -989,12 +1115,40 @@ mi_status prepare_batch(const mi_work_item *w, int64_t n, uint32_t flags, BatchT
   if ((int64_t)eval_lds_bytes(L) > max_lds_per_block())
     return fail(MI_E_UNSUPPORTED, "tuning needs %zu LDS bytes per workgroup, device has %d",
                 eval_lds_bytes(L), max_lds_per_block());
-  if (B.n_frame_items < B.n_items) {
+  if (B.n_stripe_items > 0) {
     hipError_t e = eval_resident_wgs(L, L.wgs_per_cu > 0 ? L.wgs_per_cu : 2, &B.scratch_slots);
     if (e != hipSuccess) return dev_fail(e, "occupancy of the per-pose evaluator");
     // no more slots than the launch can use (a multiple of the XCD count)
-    const int64_t nd = B.n_items - B.n_frame_items;
+    const int64_t nd = B.n_stripe_items;
     B.scratch_slots = std::min<int64_t>(B.scratch_slots, ((nd + kXcds - 1) / kXcds) * kXcds);
+  }
+  // The tiled form: under the auto tuning, one workgroup of kTileWaves waves
+  // per CU with the largest hash the LDS holds (a tile's set-up and its two
+  // barriers are then spread over more points); a set tuning is used as given.
+  EvalLaunch &Lt = B.Lt;
+  Lt = L;
+  Lt.plan_bytes = 8;
+  if (auto_tuned) {
+    Lt.waves = kTileWaves;
+    Lt.wgs_per_cu = 1;
+    Lt.hist_copies = 1;
+    const int slot = eval_hash_slot_bytes(zvar);
+    Lt.cap = 64;
+    const int64_t rest = (int64_t)eval_lds_bytes(Lt) - 64 * slot;
+    Lt.cap = (int32_t)std::max<int64_t>(
+        64, std::min<int64_t>(65536, ((int64_t)max_lds_per_block() - rest - 256) / slot) &
+                ~(int64_t)63);
+    while (Lt.cap > 64 && (int64_t)eval_lds_bytes(Lt) > max_lds_per_block()) Lt.cap -= 64;
+  }
+  const int64_t n_tile_items = B.n_items - B.n_frame_items - B.n_stripe_items;
+  if (n_tile_items > 0) {
+    if ((int64_t)eval_lds_bytes(Lt) > max_lds_per_block())
+      return fail(MI_E_UNSUPPORTED, "tiled launch needs %zu LDS bytes per workgroup, device has %d",
+                  eval_lds_bytes(Lt), max_lds_per_block());
+    hipError_t e = eval_resident_wgs(Lt, Lt.wgs_per_cu > 0 ? Lt.wgs_per_cu : 2, &B.tile_slots, 2);
+    if (e != hipSuccess) return dev_fail(e, "occupancy of the tiled evaluator");
+    B.tile_slots =
+        std::min<int64_t>(B.tile_slots, ((n_tile_items + kXcds - 1) / kXcds) * kXcds);
   }
   return MI_OK;
 }
@@ -1038,6 +1192,11 @@ struct PlanLayout {
   FrameDev *frames;
   unsigned long long *nonfinite;
   uint2 *scratch;
+  int32_t *tiled;                  // [n_tiled] pair indices
+  uint32_t *tile_cnt;              // [tile_cnt_words]
+  int64_t tile_cnt_words;
+  std::vector<float *> tile_xyz;   // per pair (tiled pairs only)
+  std::vector<uint32_t *> tile_off, tile_own, tile_cnt_of;
   char *store;
 };
 
@@ -1047,10 +1206,39 @@ void plan_fixed(const BatchTables &B, int64_t n_pairs, Carver &c, PlanLayout *L)
   FrameDev *frames = c.take<FrameDev>((size_t)std::max(B.F, 1));
   unsigned long long *nf = c.take<unsigned long long>((size_t)std::max<int64_t>(2 * n_pairs, 2));
   uint2 *scratch = c.take<uint2>((size_t)(B.scratch_slots * B.scratch_stride));
+  // tiled pairs: up to 4 entries per point (its tile and up to 3 halos), and
+  // the tile tables at their largest
+  int32_t *tiled = c.take<int32_t>((size_t)std::max(B.n_tiled, 1));
+  int64_t words = 0;
+  for (size_t i = 0; i < B.direct.size(); ++i)
+    if (B.direct[i] == 2) words += 2 * tiles_max(B.n_b[i]);
+  uint32_t *tcnt = c.take<uint32_t>((size_t)std::max<int64_t>(words, 1));
+  if (L) {
+    L->tile_xyz.assign(B.direct.size(), nullptr);
+    L->tile_off.assign(B.direct.size(), nullptr);
+    L->tile_own.assign(B.direct.size(), nullptr);
+    L->tile_cnt_of.assign(B.direct.size(), nullptr);
+  }
+  int64_t w0 = 0;
+  for (size_t i = 0; i < B.direct.size(); ++i) {
+    if (B.direct[i] != 2) continue;
+    const int64_t tm = tiles_max(B.n_b[i]);
+    float *xyz = c.take<float>((size_t)(12 * B.n_b[i]));
+    uint32_t *off = c.take<uint32_t>((size_t)(tm + 1));
+    uint32_t *own = c.take<uint32_t>((size_t)tm);
+    if (L) {
+      L->tile_xyz[i] = xyz;
+      L->tile_off[i] = off;
+      L->tile_own[i] = own;
+      L->tile_cnt_of[i] = tcnt + w0;
+    }
+    w0 += 2 * tm;
+  }
   char *store = c.take<char>(0);
   if (L) {
     L->items = items; L->pairs = pairs; L->frames = frames; L->nonfinite = nf;
     L->scratch = scratch; L->store = store;
+    L->tiled = tiled; L->tile_cnt = tcnt; L->tile_cnt_words = words;
   }
 }
 
@@ -1089,13 +1277,18 @@ size_t single_plan_bytes(int64_t K, int32_t F, int64_t ncols, int64_t n_b) {
 // buckets get as many workgroup slots as it holds, and the tables are copied
 // from host memory directly instead of through pinned staging (which may
 // allocate).
+//
+// tiles: per-pose pairs use the tiled form (batch plans, whose scans are fixed
+// here: each tiled scan is copied to the host once to choose its tiles, so
+// this call waits for the stream).
 mi_status create_plan(const mi_work_item *w, int64_t n, uint32_t flags, void *ws, size_t ws_bytes,
                       size_t budget, void *stream, bool bind_per_execution, mi_plan **out,
-                      bool no_alloc = false) {
+                      bool no_alloc = false, bool tiles = false) {
   if (!out) return fail(MI_E_INVALID, "NULL output handle");
   *out = nullptr;
   BatchTables B;
-  mi_status st = prepare_batch(w, n, flags, B);  // argument errors before workspace errors
+  // argument errors before workspace errors
+  mi_status st = prepare_batch(w, n, flags, B, tiles && !bind_per_execution && !no_alloc);
   if (st != MI_OK) return st;
   if (!ws || ((uintptr_t)ws & 255)) return fail(MI_E_WORKSPACE, "workspace NULL or not 256-aligned");
   if (no_alloc && B.scratch_slots > 0) {
@@ -1134,12 +1327,21 @@ mi_status create_plan(const mi_work_item *w, int64_t n, uint32_t flags, void *ws
   p->n_items = B.n_items;
   p->F = B.F;
   p->launch = B.L;
+  p->tile_launch = B.Lt;
+  p->tile_slots = B.tile_slots;
   p->tuning = B.tuning;
   p->items_dev = PL.items;
   p->pairs_dev = PL.pairs;
   p->frames_dev = PL.frames;
   p->nonfinite = PL.nonfinite;
   p->n_frame_items = B.n_frame_items;
+  p->n_stripe_items = B.n_stripe_items;
+  p->tile_point_poses = 0;
+  p->n_tiled = B.n_tiled;
+  p->tiled_dev = PL.tiled;
+  p->tile_cnt = PL.tile_cnt;
+  p->tile_cnt_words = PL.tile_cnt_words;
+  p->tile_max_n = 0;
   p->scratch = PL.scratch;
   p->scratch_stride = B.scratch_stride;
   p->scratch_slots = B.scratch_slots;
@@ -1156,15 +1358,16 @@ mi_status create_plan(const mi_work_item *w, int64_t n, uint32_t flags, void *ws
   } else {
     items.resize((size_t)B.n_items);
     size_t k = 0;
-    for (int pass = 0; pass < 2; ++pass)
+    for (int pass = 0; pass < 3; ++pass)
       for (int64_t i = 0; i < n; ++i) {
-        if ((bool)B.direct[(size_t)i] != (pass == 1)) continue;
+        if (B.direct[(size_t)i] != pass) continue;
         for (const PoseDev &it : B.T[(size_t)i].items) {
           PoseDev d = it;
           d.pair = (int32_t)i;
           d.frame = it.frame + B.frame_start[(size_t)i];
           items[k++] = d;
           if (pass == 1) p->direct_point_poses += w[i].n_b;
+          if (pass == 2) p->tile_point_poses += w[i].n_b;
         }
       }
   }
@@ -1238,7 +1441,37 @@ mi_status create_plan(const mi_work_item *w, int64_t n, uint32_t flags, void *ws
   p->chunk_xcd.resize(n_chunks);
   for (size_t ch = 0; ch < n_chunks; ++ch)
     group_by_xcd(items, p->chunk_item[ch], p->chunk_item[ch + 1], p->chunk_xcd[ch]);
-  group_by_xcd(items, B.n_frame_items, B.n_items, p->direct_xcd);
+  group_by_xcd(items, B.n_frame_items, B.n_frame_items + B.n_stripe_items, p->direct_xcd);
+  group_by_xcd(items, B.n_frame_items + B.n_stripe_items, B.n_items, p->tile_xcd);
+  // tiled pairs: each scan is read back once to choose its tiles
+  std::vector<TileGeom> geom((size_t)n);
+  std::vector<int32_t> tiled;
+  for (int64_t i = 0; i < n; ++i)
+    if (B.direct[(size_t)i] == 2) tiled.push_back((int32_t)i);
+  if (!tiled.empty()) {
+    std::vector<std::vector<float>> hb(tiled.size());
+    for (size_t k = 0; k < tiled.size(); ++k) {
+      const int64_t nb = w[tiled[k]].n_b;
+      hb[k].resize((size_t)(3 * nb));
+      HIP_TRY(hipMemcpyAsync(hb[k].data(), w[tiled[k]].xyz_b, sizeof(float) * 3 * (size_t)nb,
+                             hipMemcpyDeviceToHost, (hipStream_t)stream),
+              "scan B to host");
+      p->tile_max_n = std::max(p->tile_max_n, nb);
+    }
+    HIP_TRY(hipStreamSynchronize((hipStream_t)stream), "scan B to host");
+    std::atomic<size_t> next(0);
+    auto work = [&]() {
+      for (size_t k; (k = next.fetch_add(1)) < tiled.size();) {
+        const int32_t i = tiled[k];
+        geom[(size_t)i] = choose_tiles(hb[k].data(), w[i].n_b, w[i].ref->g->gi.voxel, B.Lt.cap);
+      }
+    };
+    const size_t nthr = std::min<size_t>(tiled.size(), 8);
+    std::vector<std::thread> pool;
+    for (size_t t = 1; t < nthr; ++t) pool.emplace_back(work);
+    work();
+    for (std::thread &t : pool) t.join();
+  }
   std::vector<PairDev> pairs((size_t)n);
   for (int64_t i = 0; i < n; ++i) {
     const GridInfo &gi = w[i].ref->g->gi;
@@ -1271,6 +1504,21 @@ mi_status create_plan(const mi_work_item *w, int64_t n, uint32_t flags, void *ws
       if (gi.zvar_edges[j] == 0) ++P.zvar_zero_edges;
     P.nonfinite = PL.nonfinite + 2 * i;
     P.n_b = w[i].n_b;
+    P.xyz_b = w[i].xyz_b;
+    if (B.direct[(size_t)i] == 2) {
+      const TileGeom &g = geom[(size_t)i];
+      P.tile_xyz = PL.tile_xyz[(size_t)i];
+      P.tile_stride = 4 * w[i].n_b;
+      P.tile_off = PL.tile_off[(size_t)i];
+      P.tile_own = PL.tile_own[(size_t)i];
+      P.tile_cnt = PL.tile_cnt_of[(size_t)i];
+      P.tile_x0 = g.x0; P.tile_y0 = g.y0;
+      P.tile_ilx = g.ilx; P.tile_ily = g.ily;
+      P.tile_hx = g.hx; P.tile_hy = g.hy;
+      P.tile_nx = g.nx; P.tile_ny = g.ny;
+      P.key_xbits = bits_for(gi.dims[0]);
+      P.key_ybits = bits_for(gi.dims[1]);
+    }
     P.mi_out = w[i].mi_out;
     P.K = w[i].K;
     P.hist_out = w[i].hist_out;
@@ -1281,7 +1529,8 @@ mi_status create_plan(const mi_work_item *w, int64_t n, uint32_t flags, void *ws
     memcpy(P.zvar_edges, gi.zvar_edges, sizeof P.zvar_edges);
   }
   const size_t b_items = sizeof(PoseDev) * items.size(), b_pairs = sizeof(PairDev) * pairs.size(),
-               b_frames = sizeof(FrameDev) * frames.size();
+               b_frames = sizeof(FrameDev) * frames.size(),
+               b_tiled = sizeof(int32_t) * tiled.size();
   hipError_t e = hipSuccess;
   if (no_alloc) {
     // pageable host source: each copy has taken its data when it returns
@@ -1296,15 +1545,17 @@ mi_status create_plan(const mi_work_item *w, int64_t n, uint32_t flags, void *ws
     *out = p.release();
     return MI_OK;
   }
-  Staging *sg = staging_acquire(b_items + b_pairs + b_frames + 64, &e);
+  Staging *sg = staging_acquire(b_items + b_pairs + b_frames + b_tiled + 64, &e);
   if (!sg) return dev_fail(e, "pinned staging");
   char *h = (char *)sg->p;
   if (b_items) memcpy(h, items.data(), b_items);
   if (b_pairs) memcpy(h + b_items, pairs.data(), b_pairs);
   if (b_frames) memcpy(h + b_items + b_pairs, frames.data(), b_frames);
-  const Upload ups[3] = {{PL.items, 0, b_items}, {PL.pairs, b_items, b_pairs},
-                         {PL.frames, b_items + b_pairs, b_frames}};
-  e = staging_upload(sg, ups, 3, (hipStream_t)stream);
+  if (b_tiled) memcpy(h + b_items + b_pairs + b_frames, tiled.data(), b_tiled);
+  const Upload ups[4] = {{PL.items, 0, b_items}, {PL.pairs, b_items, b_pairs},
+                         {PL.frames, b_items + b_pairs, b_frames},
+                         {PL.tiled, b_items + b_pairs + b_frames, b_tiled}};
+  e = staging_upload(sg, ups, 4, (hipStream_t)stream);
   if (e != hipSuccess) return dev_fail(e, "pose table upload");
   *out = p.release();
   return MI_OK;
@@ -1316,6 +1567,14 @@ mi_status run_plan(mi_plan *p, hipStream_t s) {
   for (size_t i = 0; i < p->pairs.size(); ++i)
     HIP_TRY(launch_count_nonfinite(p->pairs[i].xyz, p->pairs[i].n_b, p->nonfinite + 2 * i, s),
             "count non-finite");
+  if (p->n_tiled > 0) {
+    hipEvent_t a = nullptr;
+    const bool timed = prof_begin(s, &a);
+    HIP_TRY(launch_tiles(p->pairs_dev, p->tiled_dev, p->n_tiled, p->tile_max_n, p->tile_cnt,
+                         p->tile_cnt_words, s),
+            "scan B tiles");
+    if (timed) prof_end(s, a, kStageFrames, 0, 0);
+  }
   const size_t n_chunks = p->chunk_frame.size() - 1;
   for (size_t ch = 0; ch < n_chunks; ++ch) {
     const int32_t f0 = p->chunk_frame[ch], nfr = p->chunk_frame[ch + 1] - f0;
@@ -1337,7 +1596,7 @@ mi_status run_plan(mi_plan *p, hipStream_t s) {
       if (timed) prof_end(s, a, kStageEval, i1 - i0, p->chunk_point_poses[ch]);
     }
   }
-  const int64_t nd = p->n_items - p->n_frame_items;
+  const int64_t nd = p->n_stripe_items;
   if (nd > 0) {
     hipEvent_t a = nullptr;
     const bool timed = prof_begin(s, &a);
@@ -1346,6 +1605,16 @@ mi_status run_plan(mi_plan *p, hipStream_t s) {
                                p->scratch_slots, s),
             "eval (per-pose buckets)");
     if (timed) prof_end(s, a, kStageEval, nd, p->direct_point_poses);
+  }
+  const int64_t nt = p->n_items - p->n_frame_items - p->n_stripe_items;
+  if (nt > 0) {
+    hipEvent_t a = nullptr;
+    const bool timed = prof_begin(s, &a);
+    HIP_TRY(launch_eval_tiles(p->pairs_dev, p->frames_dev,
+                              p->items_dev + p->n_frame_items + p->n_stripe_items, nt,
+                              p->tile_xcd.data(), p->tile_launch, p->tile_slots, s),
+            "eval (tiles)");
+    if (timed) prof_end(s, a, kStageEval, nt, p->tile_point_poses);
   }
   for (const PairHost &ph : p->pairs)
     if (ph.argmax_out && ph.K > 0)
@@ -1356,12 +1625,23 @@ mi_status run_plan(mi_plan *p, hipStream_t s) {
 
 }  // namespace
 
+namespace {
+
+// tiles: as for create_plan (batch plans tile their per-pose pairs; plans that
+// bind scan B per execution bucket them by stripe)
+size_t workspace_bytes(const mi_work_item *items, int64_t n_items, uint32_t flags, size_t budget,
+                       bool tiles) {
+  BatchTables B;
+  if (prepare_batch(items, n_items, flags, B, tiles) != MI_OK) return 0;
+  return batch_bytes(B, items, n_items, budget);
+}
+
+}  // namespace
+
 extern "C" size_t mi_batch_workspace(const mi_work_item *items, int64_t n_items, uint32_t flags,
                                      size_t budget) {
   return guarded_size([&]() -> size_t {
-  BatchTables B;
-  if (prepare_batch(items, n_items, flags, B) != MI_OK) return 0;
-  return batch_bytes(B, items, n_items, budget);
+  return workspace_bytes(items, n_items, flags, budget, true);
   });
 }
 
@@ -1375,7 +1655,7 @@ extern "C" mi_status mi_batch_create(const mi_work_item *items, int64_t n_items,
     if (items[i].n_b > 0 && !items[i].xyz_b)
       return fail(MI_E_INVALID, "work item %lld: xyz_b is NULL", (long long)i);
   }
-  return create_plan(items, n_items, flags, ws, ws_bytes, budget, stream, false, out);
+  return create_plan(items, n_items, flags, ws, ws_bytes, budget, stream, false, out, false, true);
   });
 }
 
@@ -1444,7 +1724,7 @@ extern "C" size_t mi_autotune_workspace(const mi_work_item *items, int64_t n_ite
   Sample S;
   make_sample(items, n_items, max_poses, S);
   BatchTables B;
-  if (prepare_batch(S.items.data(), n_items, flags, B) != MI_OK) return 0;
+  if (prepare_batch(S.items.data(), n_items, flags, B, true) != MI_OK) return 0;
   return sample_out_bytes(S) + batch_bytes(B, S.items.data(), n_items, 0) + 512;
   });
 }
@@ -1477,7 +1757,8 @@ extern "C" mi_status mi_autotune(const mi_work_item *items, int64_t n_items, uin
     *ms = -1.0;
     if (mi_tuning_set(&t) != MI_OK) return MI_OK;
     mi_plan *p = nullptr;
-    mi_status st = create_plan(S.items.data(), n_items, flags, bws, bws_bytes, 0, stream, false, &p);
+    mi_status st = create_plan(S.items.data(), n_items, flags, bws, bws_bytes, 0, stream, false, &p,
+                               false, true);
     // a tuning the workload cannot use, or whose plan (per-pose scratch grows
     // with the resident workgroups) does not fit the workspace, is skipped
     if (st == MI_E_UNSUPPORTED || st == MI_E_WORKSPACE) return MI_OK;
@@ -1553,7 +1834,7 @@ extern "C" size_t mi_eval_poses_workspace(const mi_ref *r, int64_t n_b, const do
   mi_work_item w;
   memset(&w, 0, sizeof w);
   w.ref = r; w.n_b = n_b; w.poses = poses; w.K = K;
-  return mi_batch_workspace(&w, 1, flags, budget);
+  return workspace_bytes(&w, 1, flags, budget, false);
   });
 }
 
@@ -2473,8 +2754,11 @@ extern "C" size_t mi_align_nm_workspace(const mi_ref *r, int64_t n_b, int32_t n_
   mi_work_item w;
   memset(&w, 0, sizeof w);
   w.ref = r; w.n_b = n_b; w.poses = P.data(); w.K = K;
-  const size_t b = mi_batch_workspace(&w, 1, MI_EVAL_PER_POSE, 0);
-  if (b == 0) return 0;
+  // the simplex rounds use the stripe-bucketed per-pose form (no read-back of
+  // scan B per round)
+  BatchTables B;
+  if (prepare_batch(&w, 1, MI_EVAL_PER_POSE, B) != MI_OK) return 0;
+  const size_t b = batch_bytes(B, &w, 1, 0);
   return b + al256((size_t)r->g->gi.nf * (size_t)K * sizeof(double)) + 512;
   });
 }

@@ -95,6 +95,20 @@ struct PairDev {
   int32_t zvar_zero_edges;   // z-variance edges equal to 0 (a zero variance has bin 1 + this)
   const unsigned long long *nonfinite; // device counter
   int64_t n_b;
+  // Tiled per-pose form: scan B bucketed into tiles of its own (x, y) frame.
+  // Tile (i, j), t = j * tile_nx + i, holds the points with
+  // i = floor((x - tile_x0) * tile_ilx) (clamped to [0, tile_nx)), likewise j,
+  // then its halo: the points of the neighbouring tiles that lie within
+  // tile_hx (tile units) of it.  tile_nx = 0: the pair is not tiled.
+  const float *xyz_b;        // scan B, [3][n_b]
+  float *tile_xyz;           // [3][tile_stride]: per tile its own points, then its halo
+  int64_t tile_stride;
+  uint32_t *tile_off;        // [tiles + 1]: tile t is [off[t], off[t + 1])
+  uint32_t *tile_own;        // [tiles]: end of tile t's own points
+  uint32_t *tile_cnt;        // [2 * tiles]: own and halo counts, then cursors
+  double tile_x0, tile_y0, tile_ilx, tile_ily, tile_hx, tile_hy;
+  int32_t tile_nx, tile_ny;
+  int32_t key_xbits, key_ybits;  // whole-grid voxel key: iz << (x + y bits) | iy << x bits | ix
   double *mi_out;
   int64_t K;                 // feature stride of mi_out
   uint32_t *hist_out;
@@ -136,8 +150,19 @@ hipError_t launch_eval_direct(const PairDev *pairs_dev, const FrameDev *frames_d
                               const PoseDev *items_dev, int64_t n_items, const int64_t *xcd_start,
                               const EvalLaunch &cfg, uint2 *scratch, int64_t scratch_stride,
                               int64_t slots, hipStream_t s);
-// Workgroups of a persistent grid of this shape (at most per_cu per compute unit).
-hipError_t eval_resident_wgs(const EvalLaunch &cfg, int per_cu, int64_t *out);
+// Tiled per-pose form (pose sets with (nearly) all rotations distinct, scan B
+// fixed when the plan is made): a grid of `slots` workgroups over the items.
+hipError_t launch_eval_tiles(const PairDev *pairs_dev, const FrameDev *frames_dev,
+                             const PoseDev *items_dev, int64_t n_items, const int64_t *xcd_start,
+                             const EvalLaunch &cfg, int64_t slots, hipStream_t s);
+// Bucketing of the tiled pairs' scans (pairs_dev[tiled_dev[k]], k < n_tiled):
+// clears `cnt_words` words of counts at `cnt` (every tiled pair's tile_cnt lies
+// there), counts, scans, scatters.  max_n: the most points of a tiled scan.
+hipError_t launch_tiles(const PairDev *pairs_dev, const int32_t *tiled_dev, int32_t n_tiled,
+                        int64_t max_n, uint32_t *cnt, int64_t cnt_words, hipStream_t s);
+// Workgroups of a persistent grid of this shape (at most per_cu per compute
+// unit) for the evaluator form `mode` (0 frames, 1 stripe buckets, 2 tiles).
+hipError_t eval_resident_wgs(const EvalLaunch &cfg, int per_cu, int64_t *out, int mode = 1);
 size_t eval_lds_bytes(const EvalLaunch &cfg);
 int32_t eval_hash_slot_bytes(bool zvar);
 

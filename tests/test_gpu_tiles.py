@@ -1,0 +1,142 @@
+"""GPU parity of the tiled per-pose form (batches whose pose sets have
+distinct rotations): scan B bucketed into tiles of its own (x, y) frame with a
+halo, each voxel kept by the tile that holds its centre mapped back into B's
+frame.  Histograms, overlap boxes and counts must equal the oracle's bit for
+bit (Eqs. 1-5, the overlap step of Alg. 1), and equal the shared-frame and
+stripe-bucketed forms' results.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from paper_1709_06948_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+MI_TOL = 1e-6
+D2R = math.pi / 180.0
+
+
+@pytest.fixture(scope="module")
+def M():
+    from paper_1709_06948_amd import mi
+    return mi
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _check(M, og, grid, A, B, poses, res, label):
+    omi, oh, ost = O.eval_poses(og, A, B, poses, want_hist=True, want_stats=True)
+    K = len(poses)
+    gmi = res["mi"].cpu().numpy()
+    for f in range(grid.nf):
+        gh = res["hist"][f].cpu().numpy().astype(np.int64).reshape(K, -1)
+        bad = np.flatnonzero(np.any(gh != oh[f].reshape(K, -1).astype(np.int64), axis=1))
+        assert bad.size == 0, f"{label} feature {f}: histograms differ at poses {bad[:10]}"
+        assert np.max(np.abs(gmi[f] - omi[f])) <= MI_TOL, label
+    st = M.stats_to_numpy(res["stats_raw"], K)
+    assert np.array_equal(st["lo"], ost[:, 0:3]) and np.array_equal(st["hi"], ost[:, 3:6]), label
+    for i, name in enumerate(("n_overlap", "n_in_grid", "n_out_of_grid", "n_nonfinite",
+                              "n_near_face")):
+        assert np.array_equal(st[name], ost[:, 6 + i]), (label, name)
+
+
+def _same(a, b, nf, label):
+    assert torch.equal(a["mi"], b["mi"]), label
+    for f in range(nf):
+        assert torch.equal(a["hist"][f], b["hist"][f]), (label, f)
+    assert torch.equal(a["stats_raw"], b["stats_raw"]), label
+
+
+def _hard_pair(seed, n, voxel):
+    """A surface-sampled pair whose scan B also holds non-finite points,
+    points far outside the grid, and points a few 1e-6 m from voxel faces
+    (for the near-face tally)."""
+    rng = np.random.default_rng(seed)
+    pair = synth.surface_pair(rng, n, voxel, half_extent=40.0)
+    B = pair.B.copy()
+    k = n // 50
+    idx = rng.choice(n, 3 * k, replace=False)
+    B[0, idx[:k]] = np.nan
+    B[2, idx[k:2 * k]] = np.inf
+    B[:2, idx[2 * k:]] += np.float32(500.0)
+    # near faces: snap a few coordinates onto the voxel lattice of B's frame
+    snap = rng.choice(n, k, replace=False)
+    B[0, snap] = (np.round(B[0, snap] / voxel) * voxel + 3e-6).astype(np.float32)
+    poses = pair.eta_gt + rng.uniform(-1, 1, (96, 6)) * np.array(
+        [2.0, 2.0, 0.2, 2 * D2R, 2 * D2R, 8 * D2R])
+    return pair, B, poses
+
+
+@pytest.mark.parametrize("features,voxel", [(3, 0.5), (1, 1.0), (3, 0.25)])
+def test_tiles_match_oracle_and_other_forms(M, features, voxel):
+    pair, B, poses = _hard_pair(100 + int(4 * voxel), 24_000, voxel)
+    kw = dict(origin=pair.origin, dims=pair.dims, voxel=voxel, features=features, nb_count=32,
+              nb_zvar=32)
+    grid = M.Grid(**kw)
+    ref = M.Ref(grid, pair.A)
+    _say("tiled: features", features, "voxel", voxel, "n_b", B.shape[1], "poses", len(poses))
+    flags = M.EVAL_NEAR_FACE | M.EVAL_PER_POSE
+    it = M.WorkItem(ref, B, poses, want_hist=True, want_stats=True)
+    M.Batch([it], flags=flags).execute()
+    torch.cuda.synchronize()
+    tiled = it.results()
+    _check(M, O.Grid(**kw), grid, pair.A, B, poses, tiled, "tiled")
+    stripes = M.eval_poses(ref, B, poses, flags=flags, want_hist=True, want_stats=True)
+    frames = M.eval_poses(ref, B, poses, flags=M.EVAL_NEAR_FACE | M.EVAL_SHARED_FRAMES,
+                          want_hist=True, want_stats=True)
+    torch.cuda.synchronize()
+    _same(tiled, stripes, grid.nf, "tiled vs stripe buckets")
+    _same(tiled, frames, grid.nf, "tiled vs shared frames")
+
+
+def test_tiles_overflow_parts(M):
+    """A voxel hash of 128 slots: the tiles hold more voxels than that, so
+    they overflow and are redone in parts (split by a mix of the voxel key)."""
+    pair, B, poses = _hard_pair(7, 20_000, 0.5)
+    kw = dict(origin=pair.origin, dims=pair.dims, voxel=0.5, features=3, nb_count=16,
+              nb_zvar=16)
+    grid = M.Grid(**kw)
+    ref = M.Ref(grid, pair.A)
+    orig = M.tuning_get()
+    try:
+        M.tuning_set(**dict(orig, hash_bytes=128 * 22))
+        it = M.WorkItem(ref, B, poses[:48], want_hist=True, want_stats=True)
+        M.Batch([it], flags=M.EVAL_NEAR_FACE | M.EVAL_PER_POSE).execute()
+        torch.cuda.synchronize()
+        res = it.results()
+    finally:
+        M.tuning_set(**orig)
+    _say("small hash: grid", pair.dims, "n_b", B.shape[1])
+    _check(M, O.Grid(**kw), grid, pair.A, B, poses[:48], res, "tiled, 128-slot hash")
+
+
+def test_tiles_degenerate_scans(M):
+    """One point; every point at one spot (a zero-extent box, one tile); all
+    points non-finite but one; poses that move the scan off the grid."""
+    pair = synth.tiny_pair()
+    kw = dict(origin=pair.origin, dims=pair.dims, voxel=pair.voxel, features=3, nb_count=8,
+              nb_zvar=8)
+    grid = M.Grid(**kw)
+    og = O.Grid(**kw)
+    ref = M.Ref(grid, pair.A)
+    rng = np.random.default_rng(3)
+    poses = rng.uniform(-1, 1, (24, 6)) * np.array([4.0, 4.0, 0.5, 0.05, 0.05, 0.3])
+    poses[-2:, 0] = 1e3  # off the grid
+    one = pair.B[:, :1].copy()
+    spot = np.repeat(pair.B[:, 5:6], 300, axis=1)
+    nan = pair.B[:, :50].copy()
+    nan[1, 1:] = np.nan
+    items = [M.WorkItem(ref, b, poses, want_hist=True, want_stats=True) for b in (one, spot, nan)]
+    M.Batch(items, flags=M.EVAL_NEAR_FACE | M.EVAL_PER_POSE).execute()
+    torch.cuda.synchronize()
+    for j, (it, b) in enumerate(zip(items, (one, spot, nan))):
+        _say("degenerate scan", j, "points", b.shape[1])
+        _check(M, og, grid, pair.A, b, poses, it.results(), f"degenerate {j}")
