@@ -44,21 +44,47 @@ __device__ __forceinline__ TileHits tiles_of(const PairDev &P, float xf, float y
   return r;
 }
 
-// counts: tile_cnt[t] own points of tile t, tile_cnt[tiles + t] its halo
-__global__ void __launch_bounds__(256) k_tile_count(const PairDev *__restrict__ pairs,
-                                                    const int32_t *__restrict__ tiled) {
+// Tiles counted in LDS per workgroup (more fall back to global atomics only).
+constexpr int kTileLds = 4096;
+// Points per thread per round of the count and scatter passes.
+constexpr int kTilePpt = 4;
+
+// counts: tile_cnt[t] own points of tile t, tile_cnt[tiles + t] its halo.  A
+// workgroup counts a round of kTilePpt * blockDim points in LDS, then adds its
+// nonzero counts to the pair's (one global atomic per tile and round).
+__global__ void __launch_bounds__(1024) k_tile_count(const PairDev *__restrict__ pairs,
+                                                     const int32_t *__restrict__ tiled) {
+  __shared__ uint32_t lown[kTileLds], lhalo[kTileLds];
   const PairDev &P = pairs[tiled[blockIdx.y]];
   const int64_t n = P.n_b;
-  const int nt = P.tile_nx * P.tile_ny;
+  const int nt = P.tile_nx * P.tile_ny, T = blockDim.x, tid = threadIdx.x;
   uint32_t *own = P.tile_cnt, *halo = P.tile_cnt + nt;
   const float *x = P.xyz_b, *y = x + n, *z = y + n;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-       i += (int64_t)gridDim.x * blockDim.x) {
-    const float xf = x[i], yf = y[i], zf = z[i];
-    if (!isfinite(xf) || !isfinite(yf) || !isfinite(zf)) continue;
-    const TileHits h = tiles_of(P, xf, yf);
-    atomicAdd(&own[h.own], 1u);
-    for (int k = 0; k < h.n; ++k) atomicAdd(&halo[h.halo[k]], 1u);
+  const bool lds = nt <= kTileLds;
+  const int64_t round = (int64_t)kTilePpt * T;
+  for (int64_t base = (int64_t)blockIdx.x * round; base < n; base += (int64_t)gridDim.x * round) {
+    if (lds) {
+      for (int t = tid; t < nt; t += T) { lown[t] = 0u; lhalo[t] = 0u; }
+      __syncthreads();
+    }
+#pragma unroll
+    for (int k = 0; k < kTilePpt; ++k) {
+      const int64_t i = base + (int64_t)k * T + tid;
+      if (i >= n) continue;
+      const float xf = x[i], yf = y[i], zf = z[i];
+      if (!isfinite(xf) || !isfinite(yf) || !isfinite(zf)) continue;
+      const TileHits h = tiles_of(P, xf, yf);
+      atomicAdd(lds ? &lown[h.own] : &own[h.own], 1u);
+      for (int m = 0; m < h.n; ++m) atomicAdd(lds ? &lhalo[h.halo[m]] : &halo[h.halo[m]], 1u);
+    }
+    if (lds) {
+      __syncthreads();
+      for (int t = tid; t < nt; t += T) {
+        if (lown[t]) atomicAdd(&own[t], lown[t]);
+        if (lhalo[t]) atomicAdd(&halo[t], lhalo[t]);
+      }
+      __syncthreads();
+    }
   }
 }
 
@@ -97,29 +123,70 @@ __global__ void __launch_bounds__(1024) k_tile_scan(const PairDev *__restrict__ 
   if (tid == T - 1) P.tile_off[nt] = run;
 }
 
-__global__ void __launch_bounds__(256) k_tile_scatter(const PairDev *__restrict__ pairs,
-                                                      const int32_t *__restrict__ tiled) {
+// Scatter: a workgroup ranks its round's points per tile in LDS, reserves
+// each tile's run of places with one global atomic on the tile's cursor, and
+// writes every point to its run.
+__global__ void __launch_bounds__(1024) k_tile_scatter(const PairDev *__restrict__ pairs,
+                                                       const int32_t *__restrict__ tiled) {
+  __shared__ uint32_t lown[kTileLds], lhalo[kTileLds];
   const PairDev &P = pairs[tiled[blockIdx.y]];
   const int64_t n = P.n_b, ts = P.tile_stride;
-  const int nt = P.tile_nx * P.tile_ny;
+  const int nt = P.tile_nx * P.tile_ny, T = blockDim.x, tid = threadIdx.x;
   uint32_t *own = P.tile_cnt, *halo = P.tile_cnt + nt;
   const float *x = P.xyz_b, *y = x + n, *z = y + n;
   float *tx = P.tile_xyz, *ty = tx + ts, *tz = ty + ts;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-       i += (int64_t)gridDim.x * blockDim.x) {
-    const float xf = x[i], yf = y[i], zf = z[i];
-    if (!isfinite(xf) || !isfinite(yf) || !isfinite(zf)) continue;
-    const TileHits h = tiles_of(P, xf, yf);
-    uint32_t pos = atomicAdd(&own[h.own], 1u);
-    tx[pos] = xf;
-    ty[pos] = yf;
-    tz[pos] = zf;
-    for (int k = 0; k < h.n; ++k) {
-      pos = atomicAdd(&halo[h.halo[k]], 1u);
-      tx[pos] = xf;
-      ty[pos] = yf;
-      tz[pos] = zf;
+  const bool lds = nt <= kTileLds;
+  const int64_t round = (int64_t)kTilePpt * T;
+  for (int64_t base = (int64_t)blockIdx.x * round; base < n; base += (int64_t)gridDim.x * round) {
+    if (lds) {
+      for (int t = tid; t < nt; t += T) { lown[t] = 0u; lhalo[t] = 0u; }
+      __syncthreads();
     }
+    float px[kTilePpt], py[kTilePpt], pz[kTilePpt];
+    bool ok[kTilePpt];
+    TileHits h[kTilePpt];
+    uint32_t r_own[kTilePpt], r_halo[kTilePpt][3];
+#pragma unroll
+    for (int k = 0; k < kTilePpt; ++k) {
+      const int64_t i = base + (int64_t)k * T + tid;
+      ok[k] = false;
+      h[k].n = 0;
+      if (i >= n) continue;
+      px[k] = x[i];
+      py[k] = y[i];
+      pz[k] = z[i];
+      if (!isfinite(px[k]) || !isfinite(py[k]) || !isfinite(pz[k])) continue;
+      ok[k] = true;
+      h[k] = tiles_of(P, px[k], py[k]);
+      // LDS: the point's rank within this round; global: its place
+      r_own[k] = atomicAdd(lds ? &lown[h[k].own] : &own[h[k].own], 1u);
+      for (int m = 0; m < h[k].n; ++m)
+        r_halo[k][m] = atomicAdd(lds ? &lhalo[h[k].halo[m]] : &halo[h[k].halo[m]], 1u);
+    }
+    if (lds) {
+      __syncthreads();
+      // each tile's run of places for this round
+      for (int t = tid; t < nt; t += T) {
+        if (lown[t]) lown[t] = atomicAdd(&own[t], lown[t]);
+        if (lhalo[t]) lhalo[t] = atomicAdd(&halo[t], lhalo[t]);
+      }
+      __syncthreads();
+    }
+#pragma unroll
+    for (int k = 0; k < kTilePpt; ++k) {
+      if (!ok[k]) continue;
+      uint32_t pos = r_own[k] + (lds ? lown[h[k].own] : 0u);
+      tx[pos] = px[k];
+      ty[pos] = py[k];
+      tz[pos] = pz[k];
+      for (int m = 0; m < h[k].n; ++m) {
+        pos = r_halo[k][m] + (lds ? lhalo[h[k].halo[m]] : 0u);
+        tx[pos] = px[k];
+        ty[pos] = py[k];
+        tz[pos] = pz[k];
+      }
+    }
+    if (lds) __syncthreads();
   }
 }
 
@@ -128,18 +195,19 @@ hipError_t launch_tiles(const PairDev *pairs_dev, const int32_t *tiled_dev, int3
   if (n_tiled <= 0) return hipSuccess;
   hipError_t e = launch_fill_u32(cnt, 0u, cnt_words, s);
   if (e != hipSuccess) return e;
-  const unsigned gx = (unsigned)std::min<int64_t>(std::max<int64_t>((max_n + 255) / 256, 1), 4096);
+  const int64_t round = (int64_t)kTilePpt * 1024;
+  const unsigned gx = (unsigned)std::min<int64_t>(std::max<int64_t>((max_n + round - 1) / round, 1), 1024);
   // pairs along grid y, at most 65535 per launch
   for (int32_t k0 = 0; k0 < n_tiled; k0 += 65535) {
     const unsigned ny = (unsigned)std::min<int32_t>(65535, n_tiled - k0);
-    k_tile_count<<<dim3(gx, ny), 256, 0, s>>>(pairs_dev, tiled_dev + k0);
+    k_tile_count<<<dim3(gx, ny), 1024, 0, s>>>(pairs_dev, tiled_dev + k0);
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
   k_tile_scan<<<(unsigned)n_tiled, 1024, 0, s>>>(pairs_dev, tiled_dev);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   for (int32_t k0 = 0; k0 < n_tiled; k0 += 65535) {
     const unsigned ny = (unsigned)std::min<int32_t>(65535, n_tiled - k0);
-    k_tile_scatter<<<dim3(gx, ny), 256, 0, s>>>(pairs_dev, tiled_dev + k0);
+    k_tile_scatter<<<dim3(gx, ny), 1024, 0, s>>>(pairs_dev, tiled_dev + k0);
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
   return hipSuccess;
