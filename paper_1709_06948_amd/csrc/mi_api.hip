@@ -781,53 +781,100 @@ int64_t tiles_max(int64_t n_b) { return std::max<int64_t>(1, n_b / 128); }
 struct TileGeom {
   double x0 = 0.0, y0 = 0.0, ilx = 1.0, ily = 1.0, hx = 0.0, hy = 0.0;
   int32_t nx = 1, ny = 1;
+  double coherence = 0.0;  // share of consecutive finite points in one voxel of B's own frame
+  bool known = false;
 };
 
 // Tiles of scan B's own (x, y) frame: the box of its finite points (outliers
 // aside) cut into nx x ny equal tiles, as many as keep the distinct voxels of
 // a tile and its halo near half of the hash slots (counted on voxels of B's
-// own frame; a posed scan fills somewhat more, and a tile that overflows is
-// redone in parts).  Tiles are at least three halo widths wide, so the halo of
-// a tile only takes points of its 8 neighbours.
+// own frame, per cell of a grid of at most 256 x 256 cells over the box; a
+// posed scan fills somewhat more, and a tile that overflows is redone in
+// parts).  Tiles are at least three halo widths wide, so the halo of a tile
+// only takes points of its 8 neighbours.  Also measures how often
+// consecutive points share a voxel (scanner order: often; surface samples in
+// random order: almost never), which decides between tiles and shared frames.
 TileGeom choose_tiles(const float *xyz, int64_t n, double voxel, int32_t cap) {
   TileGeom g;
+  g.known = true;
   const float *X = xyz, *Y = xyz + n, *Z = xyz + 2 * n;
-  std::vector<uint64_t> keys;
-  std::vector<float> xs, ys;
-  keys.reserve((size_t)n);
+  std::vector<float> xs, ys, zs;
   xs.reserve((size_t)n);
   ys.reserve((size_t)n);
-  auto cell = [&](float v) -> uint64_t {
-    const double c = std::floor((double)v / voxel) + (double)(1 << 20);
-    return (uint64_t)std::min(std::max(c, 0.0), (double)((1 << 21) - 1));
-  };
+  zs.reserve((size_t)n);
+  int64_t same = 0, links = 0;
+  double px = 0.0, py = 0.0, pz = 0.0;
+  bool prev = false;
   for (int64_t i = 0; i < n; ++i) {
-    if (!std::isfinite(X[i]) || !std::isfinite(Y[i]) || !std::isfinite(Z[i])) continue;
+    if (!std::isfinite(X[i]) || !std::isfinite(Y[i]) || !std::isfinite(Z[i])) {
+      prev = false;
+      continue;
+    }
+    const double cx = std::floor(X[i] / voxel), cy = std::floor(Y[i] / voxel),
+                 cz = std::floor(Z[i] / voxel);
+    if (prev) {
+      ++links;
+      same += cx == px && cy == py && cz == pz;
+    }
+    px = cx; py = cy; pz = cz;
+    prev = true;
     xs.push_back(X[i]);
     ys.push_back(Y[i]);
-    keys.push_back(cell(X[i]) | (cell(Y[i]) << 21) | (cell(Z[i]) << 42));
+    zs.push_back(Z[i]);
   }
-  if (keys.empty()) return g;
+  g.coherence = links ? (double)same / (double)links : 0.0;
+  if (xs.empty()) return g;
   // the box of the central 99.8 % of the points (the rest clamp to the edge tiles)
   const size_t m = xs.size(), lo = m / 1000, hi = m - 1 - m / 1000;
-  std::nth_element(xs.begin(), xs.begin() + lo, xs.end());
-  const double x0 = xs[lo];
-  std::nth_element(xs.begin(), xs.begin() + hi, xs.end());
-  const double x1 = xs[hi];
-  std::nth_element(ys.begin(), ys.begin() + lo, ys.end());
-  const double y0 = ys[lo];
-  std::nth_element(ys.begin(), ys.begin() + hi, ys.end());
-  const double y1 = ys[hi];
-  std::sort(keys.begin(), keys.end());
-  keys.erase(std::unique(keys.begin(), keys.end()), keys.end());
+  auto quantiles = [&](std::vector<float> v, double *a, double *b) {
+    std::nth_element(v.begin(), v.begin() + lo, v.end());
+    *a = v[lo];
+    std::nth_element(v.begin(), v.begin() + hi, v.end());
+    *b = v[hi];
+  };
+  double x0, x1, y0, y1, z0, z1;
+  quantiles(xs, &x0, &x1);
+  quantiles(ys, &y0, &y1);
+  quantiles(zs, &z0, &z1);
   const double h = kTileHalo * voxel;
   const double W = std::max(x1 - x0, voxel), H = std::max(y1 - y0, voxel);
+  // distinct voxels of B's own frame (a bitmap over the box, at most 2^27
+  // bits; coarser voxels for a larger box), counted per cell
+  double bv = voxel;
+  int64_t bx = 0, by = 0, bz = 0;
+  for (;;) {
+    bx = (int64_t)std::ceil(W / bv) + 1;
+    by = (int64_t)std::ceil(H / bv) + 1;
+    bz = (int64_t)std::ceil(std::max(z1 - z0, voxel) / bv) + 1;
+    if (bx * by * bz <= ((int64_t)1 << 27)) break;
+    bv *= 2.0;
+  }
+  std::vector<uint64_t> bits((size_t)((bx * by * bz + 63) / 64), 0ull);
+  const double cs = std::max(bv, std::sqrt(W * H / 65536.0));
+  const int mx = (int)std::min<int64_t>(256, std::max<int64_t>(1, (int64_t)std::ceil(W / cs)));
+  const int my = (int)std::min<int64_t>(256, std::max<int64_t>(1, (int64_t)std::ceil(H / cs)));
+  std::vector<int32_t> cell((size_t)mx * my, 0);
+  int64_t distinct = 0;
+  auto clampi = [](double v, int64_t hi_) -> int64_t {
+    return std::min<int64_t>(std::max<int64_t>((int64_t)std::floor(v), 0), hi_ - 1);
+  };
+  for (size_t i = 0; i < m; ++i) {
+    const int64_t ix = clampi((xs[i] - x0) / bv, bx), iy = clampi((ys[i] - y0) / bv, by),
+                  iz = clampi((zs[i] - z0) / bv, bz);
+    const int64_t b = (iz * by + iy) * bx + ix;
+    uint64_t &wd = bits[(size_t)(b >> 6)];
+    const uint64_t bit = 1ull << (b & 63);
+    if (wd & bit) continue;
+    wd |= bit;
+    ++distinct;
+    ++cell[(size_t)(clampi((ys[i] - y0) / cs, my) * mx + clampi((xs[i] - x0) / cs, mx))];
+  }
   const double target = std::max(64.0, cap / 2.0);
   const int64_t tmax = tiles_max(n);
   const int nxmax = std::max(1, (int)std::min(W / (3.0 * h), 65536.0));
   const int nymax = std::max(1, (int)std::min(H / (3.0 * h), 65536.0));
-  std::vector<int32_t> cnt;
-  double nt = std::ceil((double)keys.size() / target);
+  std::vector<int64_t> cnt;
+  double nt = std::ceil((double)distinct / target);
   for (int it = 0;; ++it) {
     int nx = std::max(1, (int)std::min(std::llround(std::sqrt(nt * W / H)), (long long)nxmax));
     int ny = std::max(1, std::min((int)std::ceil(nt / nx), nymax));
@@ -840,23 +887,24 @@ TileGeom choose_tiles(const float *xyz, int64_t n, double voxel, int32_t cap) {
     g.ily = (double)ny / H;
     g.hx = nx > 1 ? h * g.ilx : 0.0;
     g.hy = ny > 1 ? h * g.ily : 0.0;
-    // distinct voxels per tile with its halo, at the voxels' centres
+    // distinct voxels per tile with its halo, each cell's at the cell's centre
     cnt.assign((size_t)nx * ny, 0);
-    int32_t worst = 0;
-    for (uint64_t k : keys) {
-      const double cx = ((double)(k & 0x1fffff) - (double)(1 << 20) + 0.5) * voxel;
-      const double cy = ((double)((k >> 21) & 0x1fffff) - (double)(1 << 20) + 0.5) * voxel;
-      const double fx = (cx - g.x0) * g.ilx, fy = (cy - g.y0) * g.ily;
-      const int i = std::min(std::max((int)std::floor(fx), 0), nx - 1);
-      const int j = std::min(std::max((int)std::floor(fy), 0), ny - 1);
-      const double rx = fx - i, ry = fy - j;
-      const int di = (i > 0 && rx < g.hx) ? -1 : (i + 1 < nx && rx > 1.0 - g.hx) ? 1 : 0;
-      const int dj = (j > 0 && ry < g.hy) ? -1 : (j + 1 < ny && ry > 1.0 - g.hy) ? 1 : 0;
-      worst = std::max(worst, ++cnt[(size_t)(j * nx + i)]);
-      if (di) worst = std::max(worst, ++cnt[(size_t)(j * nx + i + di)]);
-      if (dj) worst = std::max(worst, ++cnt[(size_t)((j + dj) * nx + i)]);
-      if (di && dj) worst = std::max(worst, ++cnt[(size_t)((j + dj) * nx + i + di)]);
-    }
+    int64_t worst = 0;
+    for (int cy = 0; cy < my; ++cy)
+      for (int cx = 0; cx < mx; ++cx) {
+        const int32_t c = cell[(size_t)(cy * mx + cx)];
+        if (!c) continue;
+        const double fx = (cx + 0.5) * cs * g.ilx, fy = (cy + 0.5) * cs * g.ily;
+        const int i = std::min(std::max((int)std::floor(fx), 0), nx - 1);
+        const int j = std::min(std::max((int)std::floor(fy), 0), ny - 1);
+        const double rx = fx - i, ry = fy - j;
+        const int di = (i > 0 && rx < g.hx) ? -1 : (i + 1 < nx && rx > 1.0 - g.hx) ? 1 : 0;
+        const int dj = (j > 0 && ry < g.hy) ? -1 : (j + 1 < ny && ry > 1.0 - g.hy) ? 1 : 0;
+        worst = std::max(worst, cnt[(size_t)(j * nx + i)] += c);
+        if (di) worst = std::max(worst, cnt[(size_t)(j * nx + i + di)] += c);
+        if (dj) worst = std::max(worst, cnt[(size_t)((j + dj) * nx + i)] += c);
+        if (di && dj) worst = std::max(worst, cnt[(size_t)((j + dj) * nx + i + di)] += c);
+      }
     if (worst <= target || it >= 12 || (int64_t)nx * ny >= tmax || (nx >= nxmax && ny >= nymax))
       break;
     nt *= 1.3;
@@ -964,6 +1012,7 @@ struct BatchTables {
   std::vector<StripeShape> SS;
   std::vector<char> direct;          // per pair: 0 frames, 1 per-pose stripe buckets, 2 tiles
   std::vector<int64_t> n_b;          // per pair: points of scan B
+  std::vector<char> maybe_tiled;     // per pair: frames until its scan's order is known
   std::vector<int32_t> frame_start;  // per pair: first entry in the frame table
   EvalLaunch L;
   EvalLaunch Lt;                     // launch of the tiled per-pose form
@@ -979,9 +1028,55 @@ struct BatchTables {
   mi_tuning tuning = {};             // in force, the auto hash resolved to its size
 };
 
-// tiles: per-pose pairs may be tiled (scan B is read when the plan is made).
+// The tiled form's launch under the auto tuning: one workgroup of kTileWaves
+// waves per CU whose hash takes the LDS that the rest of the layout leaves.
+void auto_tile_launch(EvalLaunch &Lt) {
+  Lt.waves = kTileWaves;
+  Lt.wgs_per_cu = 1;
+  Lt.hist_copies = 1;
+  Lt.plan_bytes = 8;
+  const int slot = eval_hash_slot_bytes(Lt.zvar);
+  Lt.cap = 64;
+  const int64_t rest = (int64_t)eval_lds_bytes(Lt) - 64 * slot;
+  Lt.cap = (int32_t)std::max<int64_t>(
+      64, std::min<int64_t>(65536, ((int64_t)max_lds_per_block() - rest - 256) / slot) &
+              ~(int64_t)63);
+  while (Lt.cap > 64 && (int64_t)eval_lds_bytes(Lt) > max_lds_per_block()) Lt.cap -= 64;
+}
+
+// Hash slots of the tiled launch for one grid alone (the tile size of a scan
+// evaluated on it), under the tuning in force.
+int32_t tile_cap_for(const GridInfo &gi) {
+  const Tuning tu = tuning_now();
+  EvalLaunch L;
+  L.waves = tu.waves;
+  L.hist_copies = tu.hist_copies;
+  L.hist_words = gi.nb[0] * gi.nb[0] + (gi.nf > 1 ? gi.nb[1] * gi.nb[1] : 0);
+  L.plan_bytes = 8;
+  L.wgs_per_cu = tu.wgs_per_cu;
+  L.zvar = (gi.features & (MI_FEAT_ZVAR | MI_FEAT_JOINT)) != 0;
+  L.near_face = false;
+  if (tu.hash_bytes == 0) {
+    auto_tile_launch(L);
+    return L.cap;
+  }
+  return (int32_t)std::max<int64_t>(
+      64, std::min<int64_t>(65536, ((int64_t)tu.hash_bytes / eval_hash_slot_bytes(L.zvar))) &
+              ~(int64_t)63);
+}
+
+// Poses per rotation up to which a scan in random order is evaluated in tiles
+// rather than in shared frames (with few poses per frame and no runs of
+// neighbouring points, a frame saves little of a pose's work).
+constexpr int64_t kTilePosesPerRotation = 128;
+constexpr double kTileCoherenceMax = 0.25;
+
+// tiles: pairs may be tiled (scan B is read when the plan is made): per-pose
+// pairs, and pairs with shared rotations whose scan order is incoherent when
+// geo (per item; known = false where not measured) says so.  Without geo such
+// pairs stay in frames but get tile storage too (for workspace sizes).
 mi_status prepare_batch(const mi_work_item *w, int64_t n, uint32_t flags, BatchTables &B,
-                        bool tiles = false) {
+                        bool tiles = false, const TileGeom *geo = nullptr) {
   if (n < 0 || (n > 0 && !w)) return fail(MI_E_INVALID, "bad work item list");
   if (n >= ((int64_t)1 << 20)) return fail(MI_E_UNSUPPORTED, "more than 2^20 work items");
   if (flags & ~(uint32_t)(MI_EVAL_NEAR_FACE | MI_EVAL_PER_POSE | MI_EVAL_SHARED_FRAMES))
@@ -1003,6 +1098,7 @@ mi_status prepare_batch(const mi_work_item *w, int64_t n, uint32_t flags, BatchT
   B.SS.assign((size_t)n, StripeShape());
   B.direct.assign((size_t)n, 0);
   B.n_b.assign((size_t)n, 0);
+  B.maybe_tiled.assign((size_t)n, 0);
   B.frame_start.assign((size_t)n, 0);
   Tuning tu = tuning_now();
   const bool auto_tuned = tu.hash_bytes == 0;
@@ -1064,8 +1160,14 @@ mi_status prepare_batch(const mi_work_item *w, int64_t n, uint32_t flags, BatchT
     B.n_b[(size_t)i] = it.n_b;
     // tiled: the tile entries (at most 4 per point) are addressed with 32-bit
     // offsets, and the whole-grid voxel key fits 31 bits
-    const bool tiled = direct && tiles && it.n_b > 0 && it.n_b < ((int64_t)1 << 26) &&
-                       bits_for(gi.dims[0]) + bits_for(gi.dims[1]) + bits_for(gi.dims[2]) <= 31;
+    const bool tileable = tiles && it.n_b > 0 && it.n_b < ((int64_t)1 << 26) &&
+                          bits_for(gi.dims[0]) + bits_for(gi.dims[1]) + bits_for(gi.dims[2]) <= 31;
+    // shared rotations with few poses each, on a scan in random order
+    const bool few = tileable && !direct && !(flags & MI_EVAL_SHARED_FRAMES) && it.K > 0 &&
+                     it.K <= kTilePosesPerRotation * (int64_t)T.F;
+    const bool tiled = tileable && (direct || (few && geo && geo[i].known &&
+                                               geo[i].coherence < kTileCoherenceMax));
+    B.maybe_tiled[(size_t)i] = few && !tiled && !(geo && geo[i].known);
     B.direct[(size_t)i] = tiled ? 2 : direct ? 1 : 0;
     if (direct && !tiled) {
       // A per-pose brick rescans its stripe's whole bucket, so overflow retries
@@ -1128,18 +1230,7 @@ mi_status prepare_batch(const mi_work_item *w, int64_t n, uint32_t flags, BatchT
   EvalLaunch &Lt = B.Lt;
   Lt = L;
   Lt.plan_bytes = 8;
-  if (auto_tuned) {
-    Lt.waves = kTileWaves;
-    Lt.wgs_per_cu = 1;
-    Lt.hist_copies = 1;
-    const int slot = eval_hash_slot_bytes(zvar);
-    Lt.cap = 64;
-    const int64_t rest = (int64_t)eval_lds_bytes(Lt) - 64 * slot;
-    Lt.cap = (int32_t)std::max<int64_t>(
-        64, std::min<int64_t>(65536, ((int64_t)max_lds_per_block() - rest - 256) / slot) &
-                ~(int64_t)63);
-    while (Lt.cap > 64 && (int64_t)eval_lds_bytes(Lt) > max_lds_per_block()) Lt.cap -= 64;
-  }
+  if (auto_tuned) auto_tile_launch(Lt);
   const int64_t n_tile_items = B.n_items - B.n_frame_items - B.n_stripe_items;
   if (n_tile_items > 0) {
     if ((int64_t)eval_lds_bytes(Lt) > max_lds_per_block())
@@ -1210,8 +1301,9 @@ void plan_fixed(const BatchTables &B, int64_t n_pairs, Carver &c, PlanLayout *L)
   // the tile tables at their largest
   int32_t *tiled = c.take<int32_t>((size_t)std::max(B.n_tiled, 1));
   int64_t words = 0;
+  auto has_tiles = [&](size_t i) { return B.direct[i] == 2 || (!B.maybe_tiled.empty() && B.maybe_tiled[i]); };
   for (size_t i = 0; i < B.direct.size(); ++i)
-    if (B.direct[i] == 2) words += 2 * tiles_max(B.n_b[i]);
+    if (has_tiles(i)) words += 2 * tiles_max(B.n_b[i]);
   uint32_t *tcnt = c.take<uint32_t>((size_t)std::max<int64_t>(words, 1));
   if (L) {
     L->tile_xyz.assign(B.direct.size(), nullptr);
@@ -1221,7 +1313,7 @@ void plan_fixed(const BatchTables &B, int64_t n_pairs, Carver &c, PlanLayout *L)
   }
   int64_t w0 = 0;
   for (size_t i = 0; i < B.direct.size(); ++i) {
-    if (B.direct[i] != 2) continue;
+    if (!has_tiles(i)) continue;
     const int64_t tm = tiles_max(B.n_b[i]);
     float *xyz = c.take<float>((size_t)(12 * B.n_b[i]));
     uint32_t *off = c.take<uint32_t>((size_t)(tm + 1));
@@ -1281,15 +1373,59 @@ size_t single_plan_bytes(int64_t K, int32_t F, int64_t ncols, int64_t n_b) {
 // tiles: per-pose pairs use the tiled form (batch plans, whose scans are fixed
 // here: each tiled scan is copied to the host once to choose its tiles, so
 // this call waits for the stream).
+// geo: the tile geometry of each item's scan when the caller has it (else it
+// is computed here for the pairs that may be tiled).
 mi_status create_plan(const mi_work_item *w, int64_t n, uint32_t flags, void *ws, size_t ws_bytes,
                       size_t budget, void *stream, bool bind_per_execution, mi_plan **out,
-                      bool no_alloc = false, bool tiles = false) {
+                      bool no_alloc = false, bool tiles = false, const TileGeom *geo = nullptr) {
   if (!out) return fail(MI_E_INVALID, "NULL output handle");
   *out = nullptr;
   BatchTables B;
+  tiles = tiles && !bind_per_execution && !no_alloc;
   // argument errors before workspace errors
-  mi_status st = prepare_batch(w, n, flags, B, tiles && !bind_per_execution && !no_alloc);
+  mi_status st = prepare_batch(w, n, flags, B, tiles, geo);
   if (st != MI_OK) return st;
+  // tile geometry: each scan that may be tiled is read back once
+  std::vector<TileGeom> geom((size_t)n);
+  if (geo) {
+    std::copy(geo, geo + n, geom.begin());
+  } else if (tiles) {
+    std::vector<int32_t> need;
+    bool maybe = false;
+    for (int64_t i = 0; i < n; ++i)
+      if (B.direct[(size_t)i] == 2 || B.maybe_tiled[(size_t)i]) {
+        need.push_back((int32_t)i);
+        maybe = maybe || B.maybe_tiled[(size_t)i];
+      }
+    if (!need.empty()) {
+      std::vector<std::vector<float>> hb(need.size());
+      for (size_t k = 0; k < need.size(); ++k) {
+        const int64_t nb = w[need[k]].n_b;
+        hb[k].resize((size_t)(3 * nb));
+        HIP_TRY(hipMemcpyAsync(hb[k].data(), w[need[k]].xyz_b, sizeof(float) * 3 * (size_t)nb,
+                               hipMemcpyDeviceToHost, (hipStream_t)stream),
+                "scan B to host");
+      }
+      HIP_TRY(hipStreamSynchronize((hipStream_t)stream), "scan B to host");
+      std::atomic<size_t> next(0);
+      auto work = [&]() {
+        for (size_t k; (k = next.fetch_add(1)) < need.size();) {
+          const int32_t i = need[k];
+          geom[(size_t)i] = choose_tiles(hb[k].data(), w[i].n_b, w[i].ref->g->gi.voxel, B.Lt.cap);
+        }
+      };
+      const size_t nthr = std::min<size_t>(need.size(), 8);
+      std::vector<std::thread> pool;
+      for (size_t t = 1; t < nthr; ++t) pool.emplace_back(work);
+      work();
+      for (std::thread &t : pool) t.join();
+      if (maybe) {  // the forms of pairs with shared rotations follow their scans' order
+        B = BatchTables();
+        st = prepare_batch(w, n, flags, B, tiles, geom.data());
+        if (st != MI_OK) return st;
+      }
+    }
+  }
   if (!ws || ((uintptr_t)ws & 255)) return fail(MI_E_WORKSPACE, "workspace NULL or not 256-aligned");
   if (no_alloc && B.scratch_slots > 0) {
     // the buckets take what the tables leave (half of it when frames need room too)
@@ -1443,35 +1579,12 @@ mi_status create_plan(const mi_work_item *w, int64_t n, uint32_t flags, void *ws
     group_by_xcd(items, p->chunk_item[ch], p->chunk_item[ch + 1], p->chunk_xcd[ch]);
   group_by_xcd(items, B.n_frame_items, B.n_frame_items + B.n_stripe_items, p->direct_xcd);
   group_by_xcd(items, B.n_frame_items + B.n_stripe_items, B.n_items, p->tile_xcd);
-  // tiled pairs: each scan is read back once to choose its tiles
-  std::vector<TileGeom> geom((size_t)n);
   std::vector<int32_t> tiled;
   for (int64_t i = 0; i < n; ++i)
-    if (B.direct[(size_t)i] == 2) tiled.push_back((int32_t)i);
-  if (!tiled.empty()) {
-    std::vector<std::vector<float>> hb(tiled.size());
-    for (size_t k = 0; k < tiled.size(); ++k) {
-      const int64_t nb = w[tiled[k]].n_b;
-      hb[k].resize((size_t)(3 * nb));
-      HIP_TRY(hipMemcpyAsync(hb[k].data(), w[tiled[k]].xyz_b, sizeof(float) * 3 * (size_t)nb,
-                             hipMemcpyDeviceToHost, (hipStream_t)stream),
-              "scan B to host");
-      p->tile_max_n = std::max(p->tile_max_n, nb);
+    if (B.direct[(size_t)i] == 2) {
+      tiled.push_back((int32_t)i);
+      p->tile_max_n = std::max(p->tile_max_n, w[i].n_b);
     }
-    HIP_TRY(hipStreamSynchronize((hipStream_t)stream), "scan B to host");
-    std::atomic<size_t> next(0);
-    auto work = [&]() {
-      for (size_t k; (k = next.fetch_add(1)) < tiled.size();) {
-        const int32_t i = tiled[k];
-        geom[(size_t)i] = choose_tiles(hb[k].data(), w[i].n_b, w[i].ref->g->gi.voxel, B.Lt.cap);
-      }
-    };
-    const size_t nthr = std::min<size_t>(tiled.size(), 8);
-    std::vector<std::thread> pool;
-    for (size_t t = 1; t < nthr; ++t) pool.emplace_back(work);
-    work();
-    for (std::thread &t : pool) t.join();
-  }
   std::vector<PairDev> pairs((size_t)n);
   for (int64_t i = 0; i < n; ++i) {
     const GridInfo &gi = w[i].ref->g->gi;
@@ -2255,6 +2368,7 @@ struct Request {
   bool holds_ref_tail = false;     // the reference workspace's transient tail held
   std::vector<double> P;           // poses of the current level
   size_t slot = 0;                 // place of its argmax in the pinned results
+  TileGeom geo;                    // tiles of scan B (chosen when submitted)
 };
 
 double seconds_since(std::chrono::steady_clock::time_point t0) {
@@ -2291,9 +2405,15 @@ size_t req_step_bytes(const Request &r) {
   const double spread_y = 2.0 * r.search.half_range[1] * gi.s + 4.0;
   const int64_t ncols = (int64_t)(gi.dims[0] + spread_x) * (int64_t)(gi.dims[1] + spread_y);
   const FrameBytes fb = frame_bytes(r.n_b, ncols);
+  // tiles: up to 4 entries per point and the tile tables (a level runs in
+  // frames or in tiles; both are counted)
+  const int64_t tm = tiles_max(r.n_b);
+  const size_t tiles = al256((size_t)(12 * std::max<int64_t>(r.n_b, 1)) * sizeof(float)) +
+                       al256((size_t)(tm + 1) * 4) + al256((size_t)tm * 4) +
+                       al256((size_t)(2 * tm) * 4) + 256;
   return al256((size_t)K * sizeof(PoseDev)) + al256(sizeof(PairDev)) +
          al256((size_t)K * sizeof(FrameDev)) + al256(((size_t)gi.nf + 1) * K * 8) + 4 * 256 + fb.v +
-         fb.off + al256(fb.cur) + 4096;
+         fb.off + al256(fb.cur) + tiles + 4096;
 }
 
 // Give back every arena block the request still holds: scan B and the
@@ -2387,6 +2507,7 @@ mi_status run_level(mi_server *s, Request *const *rs, size_t n,
   std::vector<double *> mis(n);
   std::vector<int64_t *> ams(n);
   std::vector<double *> mvs(n);
+  std::vector<TileGeom> geo(n);
   char *base = s->arena + s->step_bytes;
   for (size_t i = 0; i < n; ++i) {
     Request *r = rs[i];
@@ -2403,13 +2524,14 @@ mi_status run_level(mi_server *s, Request *const *rs, size_t n,
     w.poses = r->P.data();
     w.K = K;
     w.mi_out = mis[i];
+    geo[i] = r->geo;
   }
   c.take<char>(0);
   mi_status st = MI_E_WORKSPACE;
   mi_plan *p = nullptr;
   if (c.fits())
     st = create_plan(items.data(), (int64_t)n, 0, (void *)c.cur, s->step_bytes - c.used(), 0,
-                     s->stream, false, &p);
+                     s->stream, false, &p, false, true, geo.data());
   if (st != MI_OK && st != MI_E_DEVICE && n > 1) {
     // split until every part fits, or a single request shows what is wrong with it
     const size_t h = n / 2;
@@ -2502,6 +2624,9 @@ extern "C" mi_status mi_server_submit(mi_server *s, const mi_request *q, int64_t
   r->n_b = q->n_b;
   r->a.assign(q->xyz_a, q->xyz_a + 3 * q->n_a);
   r->b.assign(q->xyz_b, q->xyz_b + 3 * q->n_b);
+  // the tiles of scan B and its point order, from the host copy (here, in the
+  // submitting thread, rather than in the step loop)
+  r->geo = choose_tiles(r->b.data(), q->n_b, gi.voxel, tile_cap_for(gi));
   for (int a = 0; a < 6; ++a) { r->ctr[a] = q->init[a]; r->h[a] = q->search.half_range[a]; }
   size_t keep = 0;
   r->ref_bytes = mi_features_ref_workspace(r->g, q->n_a, &keep);

@@ -140,3 +140,35 @@ def test_tiles_degenerate_scans(M):
     for j, (it, b) in enumerate(zip(items, (one, spot, nan))):
         _say("degenerate scan", j, "points", b.shape[1])
         _check(M, og, grid, pair.A, b, poses, it.results(), f"degenerate {j}")
+
+
+def test_shared_rotation_levels_follow_scan_order(M):
+    """A 4^6 grid level (64 rotations x 64 translations): on a scan in random
+    point order a batch evaluates it in tiles, on a scanner-ordered scan in
+    shared frames; either way the results equal the level evaluated alone
+    (single-pair plan, shared frames) and the oracle on a sample."""
+    half = np.array([2.0, 2.0, 0.2, 2 * D2R, 2 * D2R, 8 * D2R])
+    rng = np.random.default_rng(21)
+    surf = synth.surface_pair(rng, 30_000, 0.5, half_extent=40.0)
+    ring = synth.urban_pair()
+    for label, pair in (("random order", surf), ("scanner order", ring)):
+        kw = dict(origin=pair.origin, dims=pair.dims, voxel=pair.voxel, features=3,
+                  nb_count=32, nb_zvar=32)
+        grid = M.Grid(**kw)
+        ref = M.Ref(grid, pair.A)
+        center = pair.eta_gt if hasattr(pair, "eta_gt") else np.zeros(6)
+        P = synth.level_poses(center, half, (4, 4, 4, 4, 4, 4))
+        it = M.WorkItem(ref, pair.B, P, want_hist=True, want_stats=True)
+        M.Batch([it], flags=M.EVAL_NEAR_FACE).execute()
+        alone = M.eval_poses(ref, pair.B, P, flags=M.EVAL_NEAR_FACE | M.EVAL_SHARED_FRAMES,
+                             want_hist=True, want_stats=True)
+        torch.cuda.synchronize()
+        _say("grid level,", label, "n_b", pair.B.shape[1], "poses", len(P))
+        res = it.results()
+        _same(res, alone, grid.nf, label)
+        sel = np.sort(rng.choice(len(P), 8, replace=False))
+        sub = dict(mi=res["mi"][:, sel], hist=[h[sel] for h in res["hist"]],
+                   stats_raw=torch.from_numpy(
+                       M.stats_to_numpy(res["stats_raw"], len(P))[sel].view(np.uint8).copy()
+                   ).cuda())
+        _check(M, O.Grid(**kw), grid, pair.A, pair.B, P[sel], sub, label)
