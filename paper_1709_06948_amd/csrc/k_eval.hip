@@ -486,17 +486,30 @@ __global__ void __launch_bounds__(1024) k_eval(const PairDev *__restrict__ pairs
           const int max_probe =
               ((int64_t)(ten - tst) <= cfg.load_max || lvl >= 2) ? cap : kMaxProbe;
           unsigned long long bnear = 0;
-          // 256 consecutive entries per wave step, four per lane, 64 apart
-          for (uint32_t b = tst + (uint32_t)wid * 256u; b < ten; b += 256u * (uint32_t)W) {
-            float fx[4], fy[4], fz[4];
+          // 256 consecutive entries per wave step, four per lane, 64 apart; the
+          // next step's loads are issued before this step's points are hashed
+          float nxf[4], nyf[4], nzf[4];
+          auto load4 = [&](uint32_t b, float (&ox)[4], float (&oy)[4], float (&oz)[4]) {
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
               const uint32_t idx = b + (uint32_t)j * 64u + (uint32_t)lane;
               const uint32_t e = idx < ten ? idx : tst;
-              fx[j] = buf_f32(rt, 4u * e, 0u);
-              fy[j] = buf_f32(rt, 4u * e, toy);
-              fz[j] = buf_f32(rt, 4u * e, toz);
+              ox[j] = buf_f32(rt, 4u * e, 0u);
+              oy[j] = buf_f32(rt, 4u * e, toy);
+              oz[j] = buf_f32(rt, 4u * e, toz);
             }
+          };
+          const uint32_t bstep = 256u * (uint32_t)W;
+          if (tst + (uint32_t)wid * 256u < ten) load4(tst + (uint32_t)wid * 256u, nxf, nyf, nzf);
+          for (uint32_t b = tst + (uint32_t)wid * 256u; b < ten; b += bstep) {
+            float fx[4], fy[4], fz[4];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+              fx[j] = nxf[j];
+              fy[j] = nyf[j];
+              fz[j] = nzf[j];
+            }
+            if (b + bstep < ten) load4(b + bstep, nxf, nyf, nzf);
             bool inb[4];
             uint32_t key[4];
             unsigned long long add1[4], add2[4];
