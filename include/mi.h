@@ -183,17 +183,29 @@ mi_status mi_pose_to_matrix(const double eta[6], double rt[12]);
 /* Workspace for mi_features_ref: the resident part (bins and per-bin
  * summed-volume tables of scan A, read by every evaluation) followed by a
  * transient part that is free again once the call has completed on the
- * stream.  persistent_bytes (nullable) receives the resident size. */
+ * stream.  persistent_bytes (nullable) receives the largest resident size
+ * (every table at 4 bytes per entry); mi_ref_resident_bytes gives the size a
+ * built reference keeps. */
 size_t mi_features_ref_workspace(const mi_grid *g, int64_t n_a, size_t *persistent_bytes);
 
 /* Alg. 1 initialisation: voxel ids of all points of scan A and A's feature
  * map for all voxels (bin 0 = empty), A's index box and, per feature bin, a
  * summed-volume table of A's occupied voxels (used to count A's voxels of each
- * bin inside any overlap box).  xyz_a: device SoA [3][n_a], n_a >= 0.
+ * bin inside any overlap box).  Each table has the fewest bytes per entry (1,
+ * 2 or 4) that hold its bin's voxel count, with entries modulo 2^(8 width):
+ * box counts, which lie between 0 and that count, stay exact.  The call reads
+ * A's per-bin voxel counts back once to lay the tables out, so it waits for
+ * the stream's work so far.  xyz_a: device SoA [3][n_a], n_a >= 0.
  * The grid must outlive the returned mi_ref. */
 mi_status mi_features_ref(const mi_grid *g, const float *xyz_a, int64_t n_a, void *ws,
                           size_t ws_bytes, void *stream, mi_ref **out);
 void mi_ref_destroy(mi_ref *r);
+
+/* Bytes at the start of the reference's workspace that the reference keeps
+ * (bins, box, counters and the tables as laid out for scan A); the rest of
+ * the workspace may be reused by work ordered after mi_features_ref on its
+ * stream.  0 for NULL. */
+size_t mi_ref_resident_bytes(const mi_ref *r);
 
 /* Device pointer to A's bin of every voxel for feature slot f (slot 0 = count
  * when enabled, then z-variance), uint8 [dims z][y][x]. */

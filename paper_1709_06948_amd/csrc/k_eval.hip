@@ -959,9 +959,11 @@ __global__ void __launch_bounds__(1024) k_eval(const PairDev *__restrict__ pairs
       const int64_t plane = (int64_t)(nx + 1) * (ny + 1) * (nz + 1);
       for (int t = tid; t < nf * 64; t += T) {
         const int f = t >> 6, a = t & 63;
-        if (a >= 1 && a < P.nb[f])
-          cntA[t] = sat_box(P.sat[f] + (int64_t)(a - 1) * plane, nx, ny, olo[0], olo[1], olo[2],
-                            ohi[0], ohi[1], ohi[2]);
+        if (a >= 1 && a < P.nb[f]) {
+          const SatLayout &L = P.sat_layout[f];
+          cntA[t] = sat_box(P.sat[f] + sat_offset(L, a, plane), sat_width(L, a), nx, ny, olo[0],
+                            olo[1], olo[2], ohi[0], ohi[1], ohi[2]);
+        }
       }
     }
     __syncthreads();

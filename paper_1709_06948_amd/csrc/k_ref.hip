@@ -6,7 +6,10 @@
 // 2. bins: bin of every voxel per feature (0 = empty, the phi value).
 // 3. summed-volume table per feature and bin a >= 1, so that the number of
 //    A voxels of bin a inside any box is 8 lookups (used for the voxels of
-//    the overlap box that B leaves empty).
+//    the overlap box that B leaves empty).  Each table has the fewest bytes
+//    per entry (1, 2 or 4) that hold its bin's voxel count, counted in step 2;
+//    its entries are the prefix sums modulo 2^(8 width), and box counts of
+//    them are exact because they lie in [0, that count].
 #include "mi_device.h"
 #include "mi_internal.h"
 
@@ -20,6 +23,7 @@ __global__ void k_ref_init(RefDev rd) {
     rd.abox[3 + threadIdx.x] = -1;
   }
   if (threadIdx.x < 4) rd.counters[threadIdx.x] = 0ull;
+  for (int i = threadIdx.x; i < 128; i += blockDim.x) rd.bin_cnt[i] = 0u;
 }
 
 __global__ void __launch_bounds__(256) k_ref_scatter(RefDev rd, const float *__restrict__ xyz,
@@ -64,7 +68,12 @@ __global__ void __launch_bounds__(256) k_ref_scatter(RefDev rd, const float *__r
   }
 }
 
+// Bins per voxel and feature, and each bin's voxel count (in LDS per
+// workgroup, then one global atomic per bin).
 __global__ void __launch_bounds__(256) k_ref_bins(RefDev rd) {
+  __shared__ uint32_t lc[128];
+  for (int i = threadIdx.x; i < 128; i += blockDim.x) lc[i] = 0u;
+  __syncthreads();
   const int64_t V = (int64_t)rd.nx * rd.ny * rd.nz;
   unsigned long long occ = 0;
   for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < V;
@@ -75,16 +84,30 @@ __global__ void __launch_bounds__(256) k_ref_bins(RefDev rd) {
       const int b = feature_bin_dev(rd.kind[f], n, rd.s1[v], rd.s2[v], rd.nbc, rd.count_edges,
                                     rd.nbz, rd.zvar_edges);
       rd.bins[f][v] = (uint8_t)b;
+      if (b) atomicAdd(&lc[64 * f + b], 1u);
     }
   }
   occ = wave_sum_u64(occ);
   if ((threadIdx.x & 63) == 0 && occ) atomicAdd(&rd.counters[3], occ);
+  __syncthreads();
+  for (int i = threadIdx.x; i < 128; i += blockDim.x)
+    if (lc[i]) atomicAdd(&rd.bin_cnt[i], lc[i]);
+}
+
+// Entry i of a table of w bytes per entry, written modulo 2^(8 w).
+__device__ __forceinline__ void sat_store(uint8_t *S, int w, int64_t i, uint32_t v) {
+  if (w == 4) ((uint32_t *)S)[i] = v;
+  else if (w == 2) ((uint16_t *)S)[i] = (uint16_t)v;
+  else S[i] = (uint8_t)v;
+}
+__device__ __forceinline__ uint32_t sat_get(const uint8_t *S, int w, int64_t i) {
+  return w == 4 ? ((const uint32_t *)S)[i] : w == 2 ? (uint32_t)((const uint16_t *)S)[i] : (uint32_t)S[i];
 }
 
 // Pass 1 of the summed-volume tables: one thread per (a, yy, x) column of the
 // padded table, marks voxels of bin a and sums them along z.
-__global__ void __launch_bounds__(256) k_sat_z(const uint8_t *__restrict__ bins, uint32_t *S,
-                                               int nx, int ny, int nz, int nbm1) {
+__global__ void __launch_bounds__(256) k_sat_z(const uint8_t *__restrict__ bins, uint8_t *S,
+                                               SatLayout L, int nx, int ny, int nz, int nbm1) {
   const int64_t cols = (int64_t)(ny + 1) * (nx + 1);
   const int64_t plane = cols * (nz + 1);
   const int64_t total = cols * nbm1;
@@ -93,18 +116,20 @@ __global__ void __launch_bounds__(256) k_sat_z(const uint8_t *__restrict__ bins,
     const int a = (int)(t / cols) + 1;
     const int64_t r = t % cols;
     const int yy = (int)(r / (nx + 1)), x = (int)(r % (nx + 1));
-    uint32_t *col = S + (int64_t)(a - 1) * plane + r;
-    col[0] = 0;
+    uint8_t *T = S + sat_offset(L, a, plane);
+    const int w = sat_width(L, a);
+    sat_store(T, w, r, 0u);
     uint32_t run = 0;
     for (int zz = 1; zz <= nz; ++zz) {
       if (yy > 0 && x > 0) run += bins[((int64_t)(zz - 1) * ny + (yy - 1)) * nx + (x - 1)] == a;
-      col[(int64_t)zz * cols] = run;
+      sat_store(T, w, r + (int64_t)zz * cols, run);
     }
   }
 }
 
 // Pass 2: prefix along y, one thread per (a, zz, x).
-__global__ void __launch_bounds__(256) k_sat_y(uint32_t *S, int nx, int ny, int nz, int nbm1) {
+__global__ void __launch_bounds__(256) k_sat_y(uint8_t *S, SatLayout L, int nx, int ny, int nz,
+                                               int nbm1) {
   const int64_t cols = (int64_t)(ny + 1) * (nx + 1);
   const int64_t plane = cols * (nz + 1);
   const int64_t per_a = (int64_t)(nz + 1) * (nx + 1);
@@ -114,41 +139,50 @@ __global__ void __launch_bounds__(256) k_sat_y(uint32_t *S, int nx, int ny, int 
     const int64_t a1 = t / per_a;
     const int64_t r = t % per_a;
     const int64_t zz = r / (nx + 1), x = r % (nx + 1);
-    uint32_t *p = S + a1 * plane + zz * cols + x;
+    uint8_t *T = S + sat_offset(L, (int)a1 + 1, plane);
+    const int w = sat_width(L, (int)a1 + 1);
+    const int64_t i0 = zz * cols + x;
     uint32_t run = 0;
     // eight rows' loads in flight at a time (the sums only chain the adds)
     for (int y0 = 0; y0 <= ny; y0 += 8) {
       uint32_t v[8];
 #pragma unroll
-      for (int j = 0; j < 8; ++j) v[j] = y0 + j <= ny ? p[(int64_t)(y0 + j) * (nx + 1)] : 0u;
+      for (int j = 0; j < 8; ++j)
+        v[j] = y0 + j <= ny ? sat_get(T, w, i0 + (int64_t)(y0 + j) * (nx + 1)) : 0u;
 #pragma unroll
       for (int j = 0; j < 8; ++j) {
         run += v[j];
-        if (y0 + j <= ny) p[(int64_t)(y0 + j) * (nx + 1)] = run;
+        if (y0 + j <= ny) sat_store(T, w, i0 + (int64_t)(y0 + j) * (nx + 1), run);
       }
     }
   }
 }
 
 // Pass 3: prefix along x, one wave per row (a, zz, yy) with a wave scan.
-__global__ void __launch_bounds__(256) k_sat_x(uint32_t *S, int nx, int ny, int nz, int nbm1) {
+__global__ void __launch_bounds__(256) k_sat_x(uint8_t *S, SatLayout L, int nx, int ny, int nz,
+                                               int nbm1) {
   const int lane = threadIdx.x & 63;
-  const int64_t rows = (int64_t)nbm1 * (nz + 1) * (ny + 1);
+  const int64_t per_a = (int64_t)(nz + 1) * (ny + 1);
+  const int64_t plane = per_a * (nx + 1);
+  const int64_t rows = (int64_t)nbm1 * per_a;
   const int64_t wave0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
   const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
   for (int64_t row = wave0; row < rows; row += nwaves) {
-    uint32_t *p = S + row * (nx + 1);
+    const int a = (int)(row / per_a) + 1;
+    uint8_t *T = S + sat_offset(L, a, plane);
+    const int w = sat_width(L, a);
+    const int64_t i0 = (row % per_a) * (nx + 1);
     uint32_t carry = 0;
     for (int x0 = 0; x0 <= nx; x0 += 64) {
       const int x = x0 + lane;
-      uint32_t v = x <= nx ? p[x] : 0u;
+      uint32_t v = x <= nx ? sat_get(T, w, i0 + x) : 0u;
 #pragma unroll
       for (int o = 1; o < 64; o <<= 1) {
         const uint32_t u = __shfl_up(v, o, 64);
         if (lane >= o) v += u;
       }
       v += carry;
-      if (x <= nx) p[x] = v;
+      if (x <= nx) sat_store(T, w, i0 + x, v);
       carry = __shfl(v, 63, 64);
     }
   }
@@ -161,8 +195,7 @@ static int grid_for(int64_t n, int block) {
   return (int)g;
 }
 
-hipError_t launch_ref(const RefDev &rd, const RefDev *, const float *xyz, int64_t n,
-                      hipStream_t s) {
+hipError_t launch_ref_bins(const RefDev &rd, const float *xyz, int64_t n, hipStream_t s) {
   const int64_t V = (int64_t)rd.nx * rd.ny * rd.nz;
   hipError_t e;
   k_ref_init<<<1, 64, 0, s>>>(rd);
@@ -175,18 +208,23 @@ hipError_t launch_ref(const RefDev &rd, const RefDev *, const float *xyz, int64_
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
   k_ref_bins<<<grid_for(V, 256), 256, 0, s>>>(rd);
-  if ((e = hipGetLastError()) != hipSuccess) return e;
+  return hipGetLastError();
+}
+
+hipError_t launch_ref_sat(const RefDev &rd, hipStream_t s) {
+  hipError_t e;
   for (int f = 0; f < rd.nf; ++f) {
     const int nbm1 = rd.nb[f] - 1;
     const int64_t cols = (int64_t)(rd.ny + 1) * (rd.nx + 1);
-    k_sat_z<<<grid_for(cols * nbm1, 256), 256, 0, s>>>(rd.bins[f], rd.sat[f], rd.nx, rd.ny,
-                                                       rd.nz, nbm1);
+    k_sat_z<<<grid_for(cols * nbm1, 256), 256, 0, s>>>(rd.bins[f], rd.sat[f], rd.sat_layout[f],
+                                                       rd.nx, rd.ny, rd.nz, nbm1);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     k_sat_y<<<grid_for((int64_t)(rd.nz + 1) * (rd.nx + 1) * nbm1, 256), 256, 0, s>>>(
-        rd.sat[f], rd.nx, rd.ny, rd.nz, nbm1);
+        rd.sat[f], rd.sat_layout[f], rd.nx, rd.ny, rd.nz, nbm1);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     const int64_t rows = (int64_t)nbm1 * (rd.nz + 1) * (rd.ny + 1);
-    k_sat_x<<<grid_for(rows * 64, 256), 256, 0, s>>>(rd.sat[f], rd.nx, rd.ny, rd.nz, nbm1);
+    k_sat_x<<<grid_for(rows * 64, 256), 256, 0, s>>>(rd.sat[f], rd.sat_layout[f], rd.nx, rd.ny,
+                                                     rd.nz, nbm1);
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
   return hipSuccess;

@@ -136,7 +136,11 @@ Staging *staging_acquire(size_t bytes, hipError_t *err) {
   *err = hipHostMalloc(&s->p, s->cap, hipHostMallocDefault);
   if (*err != hipSuccess) { delete s; return nullptr; }
   *err = hipEventCreateWithFlags(&s->ev, hipEventDisableTiming);
-  if (*err != hipSuccess) { hipHostFree(s->p); delete s; return nullptr; }
+  if (*err != hipSuccess) {
+    (void)hipHostFree(s->p);  // *err keeps the failure that matters
+    delete s;
+    return nullptr;
+  }
   s->busy = true;
   g_staging.push_back(s);
   return s;
@@ -295,14 +299,18 @@ void prof_end(hipStream_t s, hipEvent_t a, int stage, int64_t poses, int64_t poi
 extern "C" mi_status mi_profile_enable(int32_t on) {
   return guarded("mi_profile_enable", [&]() -> mi_status {
   std::lock_guard<std::mutex> lk(g_prof_mu);
+  // the recorded spans' events go back to the pool once their work is done
+  hipError_t e = hipSuccess;
   for (auto &sp : g_spans) {
-    hipEventSynchronize(sp.b);
+    const hipError_t es = hipEventSynchronize(sp.b);
+    if (e == hipSuccess) e = es;
     g_event_pool.push_back(sp.a);
     g_event_pool.push_back(sp.b);
   }
   g_spans.clear();
   for (auto &c : g_prof_counts) c = 0;
   g_prof_on = on != 0;
+  if (e != hipSuccess) return dev_fail(e, "profile spans");
   return MI_OK;
   });
 }
@@ -484,29 +492,46 @@ struct mi_ref {
   const mi_grid *g;
   RefDev rd;
   int64_t n_a;
+  size_t resident;             // bytes of the workspace the reference keeps
 };
 
-static size_t ref_layout(const GridInfo &gi, Carver &c, RefDev *rd) {
+static int64_t sat_plane(const GridInfo &gi) {
+  return (int64_t)(gi.dims[0] + 1) * (gi.dims[1] + 1) * (gi.dims[2] + 1);
+}
+
+// Resident part: bins, box and counters, per-bin voxel counts, then the
+// tables themselves, last so that what they leave unused is
+// the resident part's tail (the region is sized for 4 bytes per entry; each
+// table gets 1, 2 or 4 once the bins are counted).  Transient part: the
+// per-voxel sums.
+static size_t ref_layout(const GridInfo &gi, Carver &c, RefDev *rd, uint8_t **sat_region) {
   const int64_t V = gi.V;
-  const int64_t plane = (int64_t)(gi.dims[0] + 1) * (gi.dims[1] + 1) * (gi.dims[2] + 1);
   uint8_t *bins[2] = {nullptr, nullptr};
-  uint32_t *sat[2] = {nullptr, nullptr};
   for (int f = 0; f < gi.nf; ++f) bins[f] = c.take<uint8_t>((size_t)V);
-  for (int f = 0; f < gi.nf; ++f) sat[f] = c.take<uint32_t>((size_t)plane * (gi.nb[f] - 1));
   int32_t *abox = c.take<int32_t>(8);
   unsigned long long *ctr = c.take<unsigned long long>(4);
+  uint32_t *bin_cnt = c.take<uint32_t>(128);
+  size_t region = 0;
+  for (int f = 0; f < gi.nf; ++f)
+    region += (size_t)(gi.nb[f] - 1) * (size_t)sat_table_bytes(sat_plane(gi), 4);
+  uint8_t *sat = c.take<uint8_t>(region);
   const size_t persistent = c.used();
   uint32_t *cnt = c.take<uint32_t>((size_t)V);
   unsigned long long *s1 = c.take<unsigned long long>((size_t)V);
   unsigned long long *s2 = c.take<unsigned long long>((size_t)V);
   if (rd) {
-    for (int f = 0; f < 2; ++f) { rd->bins[f] = bins[f]; rd->sat[f] = sat[f]; }
+    for (int f = 0; f < 2; ++f) {
+      rd->bins[f] = bins[f];
+      rd->sat[f] = nullptr;  // placed once the bins are counted
+    }
+    rd->bin_cnt = bin_cnt;
     rd->abox = abox;
     rd->counters = ctr;
     rd->cnt = cnt;
     rd->s1 = s1;
     rd->s2 = s2;
   }
+  if (sat_region) *sat_region = sat;
   return persistent;
 }
 
@@ -514,7 +539,7 @@ extern "C" size_t mi_features_ref_workspace(const mi_grid *g, int64_t, size_t *p
   return guarded_size([&]() -> size_t {
   if (!g) return 0;
   Carver c(nullptr, 0);
-  const size_t pers = ref_layout(g->gi, c, nullptr);
+  const size_t pers = ref_layout(g->gi, c, nullptr, nullptr);
   if (persistent_bytes) *persistent_bytes = pers;
   return c.used() + 256;
   });
@@ -532,7 +557,8 @@ extern "C" mi_status mi_features_ref(const mi_grid *g, const float *xyz_a, int64
   Carver c(ws, ws_bytes);
   RefDev rd;
   memset(&rd, 0, sizeof rd);
-  ref_layout(gi, c, &rd);
+  uint8_t *sat_region = nullptr;
+  ref_layout(gi, c, &rd, &sat_region);
   if (!c.fits()) return fail(MI_E_WORKSPACE, "features_ref workspace needs %zu bytes, got %zu",
                              c.used(), ws_bytes);
   rd.nx = gi.dims[0]; rd.ny = gi.dims[1]; rd.nz = gi.dims[2]; rd.nf = gi.nf;
@@ -543,18 +569,40 @@ extern "C" mi_status mi_features_ref(const mi_grid *g, const float *xyz_a, int64
   for (int a = 0; a < 3; ++a) rd.c0[a] = (0.0 - gi.origin[a]) * gi.s;
   memcpy(rd.count_edges, gi.count_edges, sizeof rd.count_edges);
   memcpy(rd.zvar_edges, gi.zvar_edges, sizeof rd.zvar_edges);
-  HIP_TRY(launch_ref(rd, nullptr, xyz_a, n_a, (hipStream_t)stream), "features_ref launch");
-  mi_ref *r = (mi_ref *)malloc(sizeof(mi_ref));
+  const hipStream_t hs = (hipStream_t)stream;
+  HIP_TRY(launch_ref_bins(rd, xyz_a, n_a, hs), "features_ref launch");
+  std::unique_ptr<mi_ref, void (*)(mi_ref *)> r((mi_ref *)calloc(1, sizeof(mi_ref)),
+                                                 [](mi_ref *p) { free(p); });
   if (!r) return fail(MI_E_INVALID, "out of host memory");
+  // The tables' layout follows A's voxel count per bin: each table gets the
+  // fewest bytes per entry that hold its count (read back once).
+  uint32_t counts[128];
+  HIP_TRY(hipMemcpyAsync(counts, rd.bin_cnt, sizeof counts, hipMemcpyDeviceToHost, hs),
+          "bin counts");
+  HIP_TRY(hipStreamSynchronize(hs), "bin counts");
+  size_t used = 0;
+  for (int f = 0; f < gi.nf; ++f) {
+    rd.sat[f] = sat_region + used;
+    SatLayout &L = rd.sat_layout[f];
+    for (int a = 1; a < gi.nb[f]; ++a) {
+      const uint32_t n = counts[64 * f + a];
+      L.mask[n < 256u ? 0 : n < 65536u ? 1 : 2] |= 1ull << a;
+    }
+    used += (size_t)sat_offset(L, gi.nb[f], sat_plane(gi));
+  }
+  HIP_TRY(launch_ref_sat(rd, hs), "features_ref tables");
   r->g = g;
   r->rd = rd;
   r->n_a = n_a;
-  *out = r;
+  r->resident = (size_t)(sat_region - (uint8_t *)ws) + used;
+  *out = r.release();
   return MI_OK;
   });
 }
 
 extern "C" void mi_ref_destroy(mi_ref *r) { free(r); }
+
+extern "C" size_t mi_ref_resident_bytes(const mi_ref *r) { return r ? r->resident : 0; }
 
 extern "C" mi_status mi_ref_bins(const mi_ref *r, int32_t f, const uint8_t **dev_bins) {
   return guarded("mi_ref_bins", [&]() -> mi_status {
@@ -1598,6 +1646,7 @@ mi_status create_plan(const mi_work_item *w, int64_t n, uint32_t flags, void *ws
       P.nb[f] = gi.nb[f];
       P.binA[f] = rd.bins[f];
       P.sat[f] = rd.sat[f];
+      P.sat_layout[f] = rd.sat_layout[f];
     }
     P.nbc = gi.nbc;
     P.nbz = gi.nbz;
@@ -2489,7 +2538,11 @@ mi_status req_start(mi_server *s, Request *r) {
   if (st != MI_OK) return st;
   s->heap.release(r->off_a, req_points_bytes(r->n_a));
   r->holds_a = false;
-  s->heap.release(r->off_ref + r->ref_keep, al256(r->ref_bytes) - r->ref_keep);
+  // everything past what the reference keeps: the transient sums and the
+  // part of the table region that A's bin counts left unused
+  const size_t keep = al256(mi_ref_resident_bytes(r->ref));
+  s->heap.release(r->off_ref + keep, al256(r->ref_bytes) - keep);
+  r->ref_keep = keep;
   r->holds_ref_tail = false;
   std::vector<float>().swap(r->a);
   std::vector<float>().swap(r->b);

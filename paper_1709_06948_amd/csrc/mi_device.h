@@ -164,16 +164,30 @@ __device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long v)
   return v;
 }
 
-// Box count of a summed-volume table with dims (nx+1)(ny+1)(nz+1):
-// number of marked voxels in [x0,x1] x [y0,y1] x [z0,z1] (inclusive).
-__device__ __forceinline__ uint32_t sat_box(const uint32_t *S, int nx, int ny, int x0, int y0,
+// Voxels of the table's bin in the box [x0, x1] x [y0, y1] x [z0, z1] of a
+// table with (nx+1)(ny+1)(nz+1) entries of w bytes: the inclusion-exclusion of
+// 8 entries, modulo 2^(8 w) like the entries (exact: the count lies in
+// [0, 2^(8 w))).  Each entry is read as the aligned dword that holds it (an
+// entry never straddles one, and the dword of the last entry lies within the
+// table's 256-byte rounding) and shifted down; the bits above it drop out in
+// the final mask, because the low 8 w bits of a sum or difference depend only
+// on the operands' low 8 w bits.  The 8 loads are issued before any is used.
+__device__ __forceinline__ uint32_t sat_box(const uint8_t *S, int w, int nx, int ny, int x0, int y0,
                                             int z0, int x1, int y1, int z1) {
-  const int64_t sx = 1, sy = nx + 1, sz = (int64_t)(nx + 1) * (ny + 1);
-  const int64_t X0 = x0, X1 = x1 + 1, Y0 = y0, Y1 = y1 + 1, Z0 = z0, Z1 = z1 + 1;
-  auto at = [&](int64_t x, int64_t y, int64_t z) { return (int64_t)ldg(S + (z * sz + y * sy + x * sx)); };
-  const int64_t v = at(X1, Y1, Z1) - at(X0, Y1, Z1) - at(X1, Y0, Z1) - at(X1, Y1, Z0) +
-                    at(X0, Y0, Z1) + at(X0, Y1, Z0) + at(X1, Y0, Z0) - at(X0, Y0, Z0);
-  return (uint32_t)v;
+  const int64_t sy = nx + 1, sz = (int64_t)(nx + 1) * (ny + 1);
+  const int64_t X0 = x0, X1 = x1 + 1, Y0 = y0 * sy, Y1 = (y1 + 1) * sy, Z0 = z0 * sz,
+                Z1 = (z1 + 1) * sz;
+  // corners: + (X1 Y1 Z1), - (X0 Y1 Z1), - (X1 Y0 Z1), - (X1 Y1 Z0),
+  //          + (X0 Y0 Z1), + (X0 Y1 Z0), + (X1 Y0 Z0), - (X0 Y0 Z0)
+  const int64_t idx[8] = {X1 + Y1 + Z1, X0 + Y1 + Z1, X1 + Y0 + Z1, X1 + Y1 + Z0,
+                          X0 + Y0 + Z1, X0 + Y1 + Z0, X1 + Y0 + Z0, X0 + Y0 + Z0};
+  uint32_t e[8];
+#pragma unroll
+  for (int k = 0; k < 8; ++k) e[k] = ldg((const uint32_t *)(S + ((idx[k] * w) & ~(int64_t)3)));
+#pragma unroll
+  for (int k = 0; k < 8; ++k) e[k] >>= 8 * (int)((idx[k] * w) & 3);
+  const uint32_t v = e[0] - e[1] - e[2] - e[3] + e[4] + e[5] + e[6] - e[7];
+  return w == 4 ? v : v & ((1u << (8 * w)) - 1u);
 }
 
 }  // namespace mi

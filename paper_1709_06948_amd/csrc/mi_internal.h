@@ -33,6 +33,30 @@ struct GridInfo {
 
 // ------------------------------------------------------------------ reference
 
+// Layout of one feature's summed-volume tables, one per bin a >= 1 over the
+// (nz+1)(ny+1)(nx+1) padded grid: bin a's table has 1, 2 or 4 bytes per entry
+// (bit a set in mask[0], mask[1] or mask[2]), the fewest that hold the bin's
+// voxel count in scan A; its entries are kept modulo 2^(8 width), which leaves
+// every box count exact, since it lies in [0, that count].  The tables follow
+// each other in bin order, each rounded up to 256 bytes.
+struct SatLayout {
+  uint64_t mask[3];
+};
+
+__host__ __device__ inline int64_t sat_table_bytes(int64_t plane, int w) {
+  return (plane * w + 255) & ~(int64_t)255;
+}
+__host__ __device__ inline int sat_width(const SatLayout &L, int a) {
+  return (L.mask[2] >> a) & 1u ? 4 : (L.mask[1] >> a) & 1u ? 2 : 1;
+}
+// Byte offset of bin a's table: the tables of bins 1 .. a-1 before it.
+__host__ __device__ inline int64_t sat_offset(const SatLayout &L, int a, int64_t plane) {
+  const uint64_t below = (a >= 64 ? ~0ull : (1ull << a) - 1ull) & ~1ull;
+  return __builtin_popcountll(L.mask[0] & below) * sat_table_bytes(plane, 1) +
+         __builtin_popcountll(L.mask[1] & below) * sat_table_bytes(plane, 2) +
+         __builtin_popcountll(L.mask[2] & below) * sat_table_bytes(plane, 4);
+}
+
 struct RefDev {
   int32_t nx, ny, nz, nf;
   uint32_t kind[2];
@@ -47,13 +71,18 @@ struct RefDev {
   unsigned long long *s1, *s2;
   // resident
   uint8_t *bins[2];          // [V] per feature slot
-  uint32_t *sat[2];          // [(nb-1)][(nz+1)(ny+1)(nx+1)] per feature slot
+  uint8_t *sat[2];           // summed-volume tables per feature slot
+  SatLayout sat_layout[2];   // set by the host from bin_cnt
+  uint32_t *bin_cnt;         // [2][64] voxels of A per bin
   int32_t *abox;             // lo[3], hi[3]
   unsigned long long *counters; // in, out, nonfinite, occupied
 };
 
-hipError_t launch_ref(const RefDev &rd, const RefDev *rd_dev, const float *xyz, int64_t n,
-                      hipStream_t s);
+// The reference's voxel sums, bins and per-bin voxel counts (bin_cnt), then,
+// once the host has laid out the tables from those counts (sat_layout),
+// the summed-volume tables.
+hipError_t launch_ref_bins(const RefDev &rd, const float *xyz, int64_t n, hipStream_t s);
+hipError_t launch_ref_sat(const RefDev &rd, hipStream_t s);
 
 // ------------------------------------------------------------------- frames
 
@@ -84,7 +113,8 @@ struct PairDev {
   int32_t nbc, nbz;
   double voxel;
   const uint8_t *binA[2];
-  const uint32_t *sat[2];
+  const uint8_t *sat[2];      // A's summed-volume tables
+  SatLayout sat_layout[2];
   const int32_t *abox;
   int32_t stripe_h;          // voxel rows per stripe (bricks are pieces of stripes)
   int32_t n_stripes;

@@ -116,6 +116,7 @@ def _load():
         "mi_features_ref_workspace": ([vp, i64, C.POINTER(sz)], sz),
         "mi_features_ref": ([vp, vp, i64, vp, sz, vp, C.POINTER(vp)], st),
         "mi_ref_destroy": ([vp], None),
+        "mi_ref_resident_bytes": ([vp], sz),
         "mi_ref_bins": ([vp, st, C.POINTER(vp)], st),
         "mi_ref_summary": ([vp, vp, C.POINTER(C.c_int32), C.POINTER(C.c_int64)], st),
         "mi_eval_poses_workspace": ([vp, i64, dp, i64, u32, sz], sz),
@@ -159,7 +160,8 @@ _lib = _load()
 EXPORTED = ("mi_status_str", "mi_last_error", "mi_tuning_set", "mi_tuning_get",
             "mi_profile_enable", "mi_profile_read", "mi_grid_create",
             "mi_grid_destroy", "mi_grid_edges", "mi_pose_to_matrix", "mi_features_ref_workspace",
-            "mi_features_ref", "mi_ref_destroy", "mi_ref_bins", "mi_ref_summary",
+            "mi_features_ref", "mi_ref_destroy", "mi_ref_resident_bytes", "mi_ref_bins",
+            "mi_ref_summary",
             "mi_eval_poses_workspace", "mi_eval_poses", "mi_eval_poses_plain_workspace",
             "mi_eval_poses_plain", "mi_plan_create", "mi_plan_execute", "mi_plan_destroy",
             "mi_plan_launch", "mi_server_info",
@@ -351,6 +353,9 @@ class Ref:
                                         self.ws.numel(), _stream(stream), C.byref(h)),
                    "mi_features_ref")
         self._h = h
+        # the bytes of the workspace the reference keeps (its tables as laid out
+        # for this scan A; persistent_bytes is the most they could take)
+        self.resident_bytes = _lib.mi_ref_resident_bytes(h)
 
     def __del__(self):
         if getattr(self, "_h", None) and _lib is not None:
