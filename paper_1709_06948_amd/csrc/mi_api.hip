@@ -545,22 +545,31 @@ extern "C" size_t mi_features_ref_workspace(const mi_grid *g, int64_t, size_t *p
   });
 }
 
-extern "C" mi_status mi_features_ref(const mi_grid *g, const float *xyz_a, int64_t n_a, void *ws,
-                                     size_t ws_bytes, void *stream, mi_ref **out) {
-  return guarded("mi_features_ref", [&]() -> mi_status {
-  if (!g || !out) return fail(MI_E_INVALID, "mi_features_ref: NULL argument");
-  *out = nullptr;
+// A reference under construction: its bins and per-bin voxel counts are
+// enqueued (ref_begin), the counts are copied to host memory, and once they
+// have arrived the tables are laid out and built (ref_finish).  The server
+// begins all of a step's new references before it waits once for their counts.
+struct RefBuild {
+  RefDev rd;
+  uint8_t *sat_region;
+  void *ws;
+  int64_t n_a;
+};
+
+static mi_status ref_begin(const mi_grid *g, const float *xyz_a, int64_t n_a, void *ws,
+                           size_t ws_bytes, hipStream_t hs, uint32_t *counts_host, RefBuild *b) {
   if (n_a < 0 || (n_a > 0 && !xyz_a)) return fail(MI_E_INVALID, "bad scan A");
   if (n_a >= ((int64_t)1 << 32)) return fail(MI_E_UNSUPPORTED, "n_a >= 2^32");
   if (!ws || ((uintptr_t)ws & 255)) return fail(MI_E_WORKSPACE, "workspace NULL or not 256-aligned");
   const GridInfo &gi = g->gi;
   Carver c(ws, ws_bytes);
-  RefDev rd;
+  RefDev &rd = b->rd;
   memset(&rd, 0, sizeof rd);
-  uint8_t *sat_region = nullptr;
-  ref_layout(gi, c, &rd, &sat_region);
+  ref_layout(gi, c, &rd, &b->sat_region);
   if (!c.fits()) return fail(MI_E_WORKSPACE, "features_ref workspace needs %zu bytes, got %zu",
                              c.used(), ws_bytes);
+  b->ws = ws;
+  b->n_a = n_a;
   rd.nx = gi.dims[0]; rd.ny = gi.dims[1]; rd.nz = gi.dims[2]; rd.nf = gi.nf;
   for (int f = 0; f < 2; ++f) { rd.kind[f] = gi.kind[f]; rd.nb[f] = gi.nb[f]; }
   rd.nbc = gi.nbc;
@@ -569,20 +578,26 @@ extern "C" mi_status mi_features_ref(const mi_grid *g, const float *xyz_a, int64
   for (int a = 0; a < 3; ++a) rd.c0[a] = (0.0 - gi.origin[a]) * gi.s;
   memcpy(rd.count_edges, gi.count_edges, sizeof rd.count_edges);
   memcpy(rd.zvar_edges, gi.zvar_edges, sizeof rd.zvar_edges);
-  const hipStream_t hs = (hipStream_t)stream;
   HIP_TRY(launch_ref_bins(rd, xyz_a, n_a, hs), "features_ref launch");
+  HIP_TRY(hipMemcpyAsync(counts_host, rd.bin_cnt, 128 * sizeof(uint32_t), hipMemcpyDeviceToHost,
+                         hs),
+          "bin counts");
+  return MI_OK;
+}
+
+// counts: the 128 per-bin voxel counts ref_begin copied out, already arrived.
+// The tables' layout follows them: each table gets the fewest bytes per entry
+// that hold its bin's count.
+static mi_status ref_finish(const mi_grid *g, RefBuild &b, const uint32_t *counts, hipStream_t hs,
+                            mi_ref **out) {
+  const GridInfo &gi = g->gi;
+  RefDev &rd = b.rd;
   std::unique_ptr<mi_ref, void (*)(mi_ref *)> r((mi_ref *)calloc(1, sizeof(mi_ref)),
                                                  [](mi_ref *p) { free(p); });
   if (!r) return fail(MI_E_INVALID, "out of host memory");
-  // The tables' layout follows A's voxel count per bin: each table gets the
-  // fewest bytes per entry that hold its count (read back once).
-  uint32_t counts[128];
-  HIP_TRY(hipMemcpyAsync(counts, rd.bin_cnt, sizeof counts, hipMemcpyDeviceToHost, hs),
-          "bin counts");
-  HIP_TRY(hipStreamSynchronize(hs), "bin counts");
   size_t used = 0;
   for (int f = 0; f < gi.nf; ++f) {
-    rd.sat[f] = sat_region + used;
+    rd.sat[f] = b.sat_region + used;
     SatLayout &L = rd.sat_layout[f];
     for (int a = 1; a < gi.nb[f]; ++a) {
       const uint32_t n = counts[64 * f + a];
@@ -593,10 +608,24 @@ extern "C" mi_status mi_features_ref(const mi_grid *g, const float *xyz_a, int64
   HIP_TRY(launch_ref_sat(rd, hs), "features_ref tables");
   r->g = g;
   r->rd = rd;
-  r->n_a = n_a;
-  r->resident = (size_t)(sat_region - (uint8_t *)ws) + used;
+  r->n_a = b.n_a;
+  r->resident = (size_t)(b.sat_region - (uint8_t *)b.ws) + used;
   *out = r.release();
   return MI_OK;
+}
+
+extern "C" mi_status mi_features_ref(const mi_grid *g, const float *xyz_a, int64_t n_a, void *ws,
+                                     size_t ws_bytes, void *stream, mi_ref **out) {
+  return guarded("mi_features_ref", [&]() -> mi_status {
+  if (!g || !out) return fail(MI_E_INVALID, "mi_features_ref: NULL argument");
+  *out = nullptr;
+  const hipStream_t hs = (hipStream_t)stream;
+  RefBuild b;
+  uint32_t counts[128];
+  const mi_status st = ref_begin(g, xyz_a, n_a, ws, ws_bytes, hs, counts, &b);
+  if (st != MI_OK) return st;
+  HIP_TRY(hipStreamSynchronize(hs), "bin counts");
+  return ref_finish(g, b, counts, hs, out);
   });
 }
 
@@ -2438,7 +2467,7 @@ struct mi_server {
   std::unordered_map<int64_t, std::unique_ptr<Request>> table;
   int64_t next_id = 1;
   std::chrono::steady_clock::time_point t0;
-  char *pinned = nullptr;          // [max_active] x (argmax, MI)
+  char *pinned = nullptr;          // [max_active] x (argmax, MI), then [max_active] x 128 counts
 };
 
 namespace {
@@ -2519,7 +2548,9 @@ bool req_reserve(mi_server *s, Request *r) {
 // reference's transient sums go back to the heap as soon as the kernels that
 // use them are enqueued (later users of that memory run after them on the
 // same stream).
-mi_status req_start(mi_server *s, Request *r) {
+// Upload the request's scans and begin its reference; A's per-bin voxel
+// counts go to counts (pinned host memory) on the server's stream.
+mi_status req_begin(mi_server *s, Request *r, RefBuild *b, uint32_t *counts) {
   char *base = s->arena + s->step_bytes;
   float *db = (float *)(base + r->off_b), *da = (float *)(base + r->off_a);
   const size_t bb = (size_t)r->n_b * 3 * sizeof(float), ba = (size_t)r->n_a * 3 * sizeof(float);
@@ -2533,13 +2564,17 @@ mi_status req_start(mi_server *s, Request *r) {
     e = staging_upload(sg, ups, 2, s->stream);
     if (e != hipSuccess) return dev_fail(e, "scan upload");
   }
-  mi_status st = mi_features_ref(r->g, da, r->n_a, base + r->off_ref, r->ref_bytes, s->stream,
-                                 &r->ref);
+  return ref_begin(r->g, da, r->n_a, base + r->off_ref, r->ref_bytes, s->stream, counts, b);
+}
+
+// Once the counts have arrived: build the reference's tables, then give back
+// scan A's block and everything past what the reference keeps (the transient
+// sums and the part of the table region that A's bin counts left unused).
+mi_status req_finish(mi_server *s, Request *r, RefBuild &b, const uint32_t *counts) {
+  mi_status st = ref_finish(r->g, b, counts, s->stream, &r->ref);
   if (st != MI_OK) return st;
   s->heap.release(r->off_a, req_points_bytes(r->n_a));
   r->holds_a = false;
-  // everything past what the reference keeps: the transient sums and the
-  // part of the table region that A's bin counts left unused
   const size_t keep = al256(mi_ref_resident_bytes(r->ref));
   s->heap.release(r->off_ref + keep, al256(r->ref_bytes) - keep);
   r->ref_keep = keep;
@@ -2635,7 +2670,8 @@ extern "C" mi_status mi_server_create(const mi_server_desc *d, void *stream, mi_
   s->stream = (hipStream_t)stream;
   s->heap.init((d->arena_bytes - step) & ~(size_t)255);
   s->t0 = std::chrono::steady_clock::now();
-  HIP_TRY(hipHostMalloc((void **)&s->pinned, 16 * (size_t)d->max_active, hipHostMallocDefault),
+  HIP_TRY(hipHostMalloc((void **)&s->pinned, (16 + 128 * sizeof(uint32_t)) * (size_t)d->max_active,
+                        hipHostMallocDefault),
           "pinned results");
   *out = s.release();
   return MI_OK;
@@ -2725,9 +2761,19 @@ extern "C" mi_status mi_server_step(mi_server *s, int32_t *n_active, int32_t *n_
       admitted.push_back(r);
     }
   }
-  for (Request *r : admitted) {
-    const mi_status st = req_start(s, r);
-    if (st != MI_OK) req_fail(s, r, st);
+  // new references: all begun, one wait for their bin counts, all finished
+  if (!admitted.empty()) {
+    uint32_t *counts = (uint32_t *)(s->pinned + 16 * (size_t)s->max_active);
+    std::vector<RefBuild> builds(admitted.size());
+    std::vector<mi_status> began(admitted.size());
+    for (size_t i = 0; i < admitted.size(); ++i)
+      began[i] = req_begin(s, admitted[i], &builds[i], counts + 128 * i);
+    HIP_TRY(hipStreamSynchronize(s->stream), "bin counts");
+    for (size_t i = 0; i < admitted.size(); ++i) {
+      const mi_status st =
+          began[i] == MI_OK ? req_finish(s, admitted[i], builds[i], counts + 128 * i) : began[i];
+      if (st != MI_OK) req_fail(s, admitted[i], st);
+    }
   }
   std::vector<Request *> live;
   for (Request *r : s->active)
