@@ -961,12 +961,45 @@ __global__ void __launch_bounds__(1024) k_eval(const PairDev *__restrict__ pairs
         const int f = t >> 6, a = t & 63;
         if (a >= 1 && a < P.nb[f]) {
           const SatLayout &L = P.sat_layout[f];
-          cntA[t] = sat_box(P.sat[f] + sat_offset(L, a, plane), sat_width(L, a), nx, ny, olo[0],
-                            olo[1], olo[2], ohi[0], ohi[1], ohi[2]);
+          cntA[t] = sat_has_table(L, a)
+                        ? sat_box(P.sat[f] + sat_offset(L, a, plane), sat_width(L, a), nx, ny,
+                                  olo[0], olo[1], olo[2], ohi[0], ohi[1], ohi[2])
+                        : 0u;
         }
       }
     }
     __syncthreads();
+    // A's voxels of the bins kept as a list: count those inside O.  A thread
+    // loads 8 entries before it tests any.  The list is grouped by bin, so a
+    // wave's entries mostly share one; it then adds them with one atomic.
+    if (nonempty && P.alist_n) {
+      const uint32_t n = P.alist_n;
+      for (uint32_t e0 = tid; e0 < n; e0 += 8u * T) {
+        uint64_t q[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+          const uint32_t e = e0 + (uint32_t)k * T;
+          q[k] = e < n ? ldg(P.alist + e) : ~0ull;  // ~0: past the end
+        }
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+          if (e0 + (uint32_t)k * T >= n) break;  // the rest of this thread's entries are past it too
+          const int x = (int)(q[k] & 0xFFFFFu), y = (int)((q[k] >> 20) & 0xFFFFFu);
+          const int z = (int)((q[k] >> 40) & 0xFFFFu), fa = (int)(q[k] >> 56);
+          const bool in = x >= olo[0] && x <= ohi[0] && y >= olo[1] && y <= ohi[1] &&
+                          z >= olo[2] && z <= ohi[2];
+          const int first = __ffsll((unsigned long long)__ballot(1)) - 1;  // first active lane
+          const int fa0 = __shfl(fa, first, 64);
+          const uint64_t inm = __ballot(in), mixed = __ballot(in && fa != fa0);
+          if (mixed == 0) {
+            if (inm && lane == first) atomicAdd(&cntA[fa0], (uint32_t)__popcll(inm));
+          } else if (in) {
+            atomicAdd(&cntA[fa], 1u);
+          }
+        }
+      }
+      __syncthreads();
+    }
     if (nonempty) {
       for (int t = tid; t < nf * 64; t += T) {
         const int f = t >> 6, a = t & 63, nb = P.nb[f];

@@ -4,12 +4,14 @@
 //    fixed order u = fl(fl(x*s) + c0)), dense per-voxel n, S1 = sum q,
 //    S2 = sum q^2 with q = floor(frac(u_z) * 2^20); A's index box.
 // 2. bins: bin of every voxel per feature (0 = empty, the phi value).
-// 3. summed-volume table per feature and bin a >= 1, so that the number of
-//    A voxels of bin a inside any box is 8 lookups (used for the voxels of
-//    the overlap box that B leaves empty).  Each table has the fewest bytes
-//    per entry (1, 2 or 4) that hold its bin's voxel count, counted in step 2;
-//    its entries are the prefix sums modulo 2^(8 width), and box counts of
-//    them are exact because they lie in [0, that count].
+// 3. summed-volume table per feature and occupied bin a >= 1, so that the
+//    number of A voxels of bin a inside any box is 8 lookups (used for the
+//    voxels of the overlap box that B leaves empty).  Each table has the
+//    fewest bytes per entry (1, 2 or 4) that hold its bin's voxel count,
+//    counted in step 2; its entries are the prefix sums modulo 2^(8 width),
+//    and box counts of them are exact because they lie in [0, that count].
+//    On large grids the sparsest bins are a voxel list instead (step 4).
+// 4. the voxel list of those bins.
 #include "mi_device.h"
 #include "mi_internal.h"
 
@@ -114,6 +116,7 @@ __global__ void __launch_bounds__(256) k_sat_z(const uint8_t *__restrict__ bins,
   for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total;
        t += (int64_t)gridDim.x * blockDim.x) {
     const int a = (int)(t / cols) + 1;
+    if (!sat_has_table(L, a)) continue;
     const int64_t r = t % cols;
     const int yy = (int)(r / (nx + 1)), x = (int)(r % (nx + 1));
     uint8_t *T = S + sat_offset(L, a, plane);
@@ -137,6 +140,7 @@ __global__ void __launch_bounds__(256) k_sat_y(uint8_t *S, SatLayout L, int nx, 
   for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total;
        t += (int64_t)gridDim.x * blockDim.x) {
     const int64_t a1 = t / per_a;
+    if (!sat_has_table(L, (int)a1 + 1)) continue;
     const int64_t r = t % per_a;
     const int64_t zz = r / (nx + 1), x = r % (nx + 1);
     uint8_t *T = S + sat_offset(L, (int)a1 + 1, plane);
@@ -169,6 +173,7 @@ __global__ void __launch_bounds__(256) k_sat_x(uint8_t *S, SatLayout L, int nx, 
   const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
   for (int64_t row = wave0; row < rows; row += nwaves) {
     const int a = (int)(row / per_a) + 1;
+    if (!sat_has_table(L, a)) continue;  // uniform over the wave: one row per wave
     uint8_t *T = S + sat_offset(L, a, plane);
     const int w = sat_width(L, a);
     const int64_t i0 = (row % per_a) * (nx + 1);
@@ -184,6 +189,34 @@ __global__ void __launch_bounds__(256) k_sat_x(uint8_t *S, SatLayout L, int nx, 
       v += carry;
       if (x <= nx) sat_store(T, w, i0 + x, v);
       carry = __shfl(v, 63, 64);
+    }
+  }
+}
+
+// Starts of the voxel list's per-bin segments: bins in list_mask, in order.
+__global__ void k_list_starts(uint32_t *cur, const uint32_t *cnt, uint64_t m0, uint64_t m1) {
+  if (threadIdx.x != 0) return;
+  uint32_t run = 0;
+  for (int i = 0; i < 128; ++i) {
+    cur[i] = run;
+    if ((((i < 64 ? m0 : m1) >> (i & 63)) & 1u)) run += cnt[i];
+  }
+}
+
+// One entry per voxel of a listed bin, (f * 64 + a) << 56 | z << 40 | y << 20
+// | x, at its bin's cursor (the order within a bin is not fixed; only counts
+// are taken from it).
+__global__ void __launch_bounds__(256) k_ref_list(RefDev rd) {
+  const int64_t V = (int64_t)rd.nx * rd.ny * rd.nz;
+  for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < V;
+       v += (int64_t)gridDim.x * blockDim.x) {
+    for (int f = 0; f < rd.nf; ++f) {
+      const int a = rd.bins[f][v];
+      if (!((rd.list_mask[f] >> a) & 1u)) continue;
+      const int64_t x = v % rd.nx, y = (v / rd.nx) % rd.ny, z = v / ((int64_t)rd.nx * rd.ny);
+      const uint32_t pos = atomicAdd(&rd.list_cur[64 * f + a], 1u);
+      rd.alist[pos] = ((uint64_t)(64 * f + a) << 56) | ((uint64_t)z << 40) | ((uint64_t)y << 20) |
+                      (uint64_t)x;
     }
   }
 }
@@ -225,6 +258,12 @@ hipError_t launch_ref_sat(const RefDev &rd, hipStream_t s) {
     const int64_t rows = (int64_t)nbm1 * (rd.nz + 1) * (rd.ny + 1);
     k_sat_x<<<grid_for(rows * 64, 256), 256, 0, s>>>(rd.sat[f], rd.sat_layout[f], rd.nx, rd.ny,
                                                      rd.nz, nbm1);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
+  if (rd.alist_n) {
+    k_list_starts<<<1, 64, 0, s>>>(rd.list_cur, rd.bin_cnt, rd.list_mask[0], rd.list_mask[1]);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    k_ref_list<<<grid_for((int64_t)rd.nx * rd.ny * rd.nz, 256), 256, 0, s>>>(rd);
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
   return hipSuccess;

@@ -511,6 +511,7 @@ static size_t ref_layout(const GridInfo &gi, Carver &c, RefDev *rd, uint8_t **sa
   int32_t *abox = c.take<int32_t>(8);
   unsigned long long *ctr = c.take<unsigned long long>(4);
   uint32_t *bin_cnt = c.take<uint32_t>(128);
+  uint32_t *list_cur = c.take<uint32_t>(128);
   size_t region = 0;
   for (int f = 0; f < gi.nf; ++f)
     region += (size_t)(gi.nb[f] - 1) * (size_t)sat_table_bytes(sat_plane(gi), 4);
@@ -525,6 +526,7 @@ static size_t ref_layout(const GridInfo &gi, Carver &c, RefDev *rd, uint8_t **sa
       rd->sat[f] = nullptr;  // placed once the bins are counted
     }
     rd->bin_cnt = bin_cnt;
+    rd->list_cur = list_cur;
     rd->abox = abox;
     rd->counters = ctr;
     rd->cnt = cnt;
@@ -586,8 +588,12 @@ static mi_status ref_begin(const mi_grid *g, const float *xyz_a, int64_t n_a, vo
 }
 
 // counts: the 128 per-bin voxel counts ref_begin copied out, already arrived.
-// The tables' layout follows them: each table gets the fewest bytes per entry
-// that hold its bin's count.
+// The layout follows them.  An empty bin has no table.  On a grid of at least
+// 2^20 table entries, the sparsest bins, in ascending count up to kListMax
+// voxels in all, are kept as a voxel list instead of a table (each frees at
+// least 4 MiB of the region sized for 4-byte tables; the list takes at most
+// 64 KiB).  Every other bin gets a table with the fewest bytes per entry that
+// hold its count.
 static mi_status ref_finish(const mi_grid *g, RefBuild &b, const uint32_t *counts, hipStream_t hs,
                             mi_ref **out) {
   const GridInfo &gi = g->gi;
@@ -595,16 +601,36 @@ static mi_status ref_finish(const mi_grid *g, RefBuild &b, const uint32_t *count
   std::unique_ptr<mi_ref, void (*)(mi_ref *)> r((mi_ref *)calloc(1, sizeof(mi_ref)),
                                                  [](mi_ref *p) { free(p); });
   if (!r) return fail(MI_E_INVALID, "out of host memory");
+  const int64_t plane = sat_plane(gi);
+  uint32_t listed = 0;
+  if (plane >= ((int64_t)1 << 20) && list_fits(gi.dims[0], gi.dims[1], gi.dims[2])) {
+    std::vector<std::pair<uint32_t, int>> sparse;
+    for (int f = 0; f < gi.nf; ++f)
+      for (int a = 1; a < gi.nb[f]; ++a) {
+        const uint32_t n = counts[64 * f + a];
+        if (n > 0 && n < 65536u) sparse.push_back({n, 64 * f + a});
+      }
+    std::sort(sparse.begin(), sparse.end());
+    for (const auto &sb : sparse) {
+      if (listed + sb.first > kListMax) break;
+      listed += sb.first;
+      rd.list_mask[sb.second >> 6] |= 1ull << (sb.second & 63);
+    }
+  }
   size_t used = 0;
   for (int f = 0; f < gi.nf; ++f) {
     rd.sat[f] = b.sat_region + used;
     SatLayout &L = rd.sat_layout[f];
     for (int a = 1; a < gi.nb[f]; ++a) {
       const uint32_t n = counts[64 * f + a];
+      if (n == 0 || ((rd.list_mask[f] >> a) & 1u)) continue;
       L.mask[n < 256u ? 0 : n < 65536u ? 1 : 2] |= 1ull << a;
     }
-    used += (size_t)sat_offset(L, gi.nb[f], sat_plane(gi));
+    used += (size_t)sat_offset(L, gi.nb[f], plane);
   }
+  rd.alist = listed ? (uint64_t *)(b.sat_region + used) : nullptr;
+  rd.alist_n = listed;
+  used += ((size_t)listed * sizeof(uint64_t) + 255) & ~(size_t)255;
   HIP_TRY(launch_ref_sat(rd, hs), "features_ref tables");
   r->g = g;
   r->rd = rd;
@@ -1677,6 +1703,8 @@ mi_status create_plan(const mi_work_item *w, int64_t n, uint32_t flags, void *ws
       P.sat[f] = rd.sat[f];
       P.sat_layout[f] = rd.sat_layout[f];
     }
+    P.alist = rd.alist;
+    P.alist_n = rd.alist_n;
     P.nbc = gi.nbc;
     P.nbz = gi.nbz;
     P.voxel = gi.voxel;

@@ -33,15 +33,28 @@ struct GridInfo {
 
 // ------------------------------------------------------------------ reference
 
-// Layout of one feature's summed-volume tables, one per bin a >= 1 over the
-// (nz+1)(ny+1)(nx+1) padded grid: bin a's table has 1, 2 or 4 bytes per entry
+// Layout of one feature's summed-volume tables over the (nz+1)(ny+1)(nx+1)
+// padded grid: bin a's table, if it has one, has 1, 2 or 4 bytes per entry
 // (bit a set in mask[0], mask[1] or mask[2]), the fewest that hold the bin's
 // voxel count in scan A; its entries are kept modulo 2^(8 width), which leaves
 // every box count exact, since it lies in [0, that count].  The tables follow
-// each other in bin order, each rounded up to 256 bytes.
+// each other in bin order, each rounded up to 256 bytes.  A bin without a
+// table is empty in A or kept in the reference's voxel list.
 struct SatLayout {
   uint64_t mask[3];
 };
+
+// Voxel lists (for sparse bins on large grids): one 64-bit entry per voxel of
+// A, (f * 64 + a) << 56 | z << 40 | y << 20 | x, grouped by bin.  At most
+// kListMax entries per reference, so counting them in a box is a short scan.
+constexpr uint32_t kListMax = 8192;
+__host__ __device__ inline bool list_fits(int nx, int ny, int nz) {
+  return nx < (1 << 20) && ny < (1 << 20) && nz < (1 << 16);
+}
+
+__host__ __device__ inline bool sat_has_table(const SatLayout &L, int a) {
+  return ((L.mask[0] | L.mask[1] | L.mask[2]) >> a) & 1u;
+}
 
 __host__ __device__ inline int64_t sat_table_bytes(int64_t plane, int w) {
   return (plane * w + 255) & ~(int64_t)255;
@@ -73,6 +86,10 @@ struct RefDev {
   uint8_t *bins[2];          // [V] per feature slot
   uint8_t *sat[2];           // summed-volume tables per feature slot
   SatLayout sat_layout[2];   // set by the host from bin_cnt
+  uint64_t *alist;           // voxel list of the bins in list_mask
+  uint32_t alist_n;
+  uint64_t list_mask[2];
+  uint32_t *list_cur;        // [2][64] cursors while the list is built
   uint32_t *bin_cnt;         // [2][64] voxels of A per bin
   int32_t *abox;             // lo[3], hi[3]
   unsigned long long *counters; // in, out, nonfinite, occupied
@@ -115,6 +132,8 @@ struct PairDev {
   const uint8_t *binA[2];
   const uint8_t *sat[2];      // A's summed-volume tables
   SatLayout sat_layout[2];
+  const uint64_t *alist;      // A's voxel list (sparse bins without a table)
+  uint32_t alist_n;
   const int32_t *abox;
   int32_t stripe_h;          // voxel rows per stripe (bricks are pieces of stripes)
   int32_t n_stripes;

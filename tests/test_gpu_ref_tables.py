@@ -36,28 +36,45 @@ def _r256(b):
 
 
 def _table_bytes(og, A, dims, nb):
-    """The tables' bytes as the layout rule gives them from the oracle's bins
-    of scan A: per bin a >= 1 of each feature, the fewest of 1, 2 or 4 bytes per
-    entry that hold the bin's voxel count, each table rounded to 256 bytes.
-    Also returns the widths used."""
+    """The tables' and voxel list's bytes as the layout rule gives them from
+    the oracle's bins of scan A: an empty bin has no table; on a grid of at
+    least 2^20 table entries the sparsest bins (ascending count, ties by
+    feature and bin, while the list holds at most 8192 voxels) form the voxel
+    list, 8 bytes per voxel; every other bin a >= 1 has a table of the fewest of
+    1, 2 or 4 bytes per entry that hold its voxel count, each table (and the
+    list) rounded to 256 bytes.  Also returns the widths (0: no table) and the
+    number of listed voxels."""
     plane = (dims[0] + 1) * (dims[1] + 1) * (dims[2] + 1)
     bins = O.scan_features(og, A)["bins"]
+    cnt = [np.bincount(bins[f], minlength=nb[f]) for f in range(bins.shape[0])]
+    listed = set()
+    n_list = 0
+    if plane >= 1 << 20:
+        sparse = sorted((int(cnt[f][a]), 64 * f + a) for f in range(len(cnt))
+                        for a in range(1, nb[f]) if 0 < cnt[f][a] < 65536)
+        for n, key in sparse:
+            if n_list + n > 8192:
+                break
+            n_list += n
+            listed.add(key)
     total, widths = 0, []
-    for f in range(bins.shape[0]):
-        cnt = np.bincount(bins[f], minlength=nb[f])
+    for f in range(len(cnt)):
         for a in range(1, nb[f]):
-            w = 1 if cnt[a] < 256 else 2 if cnt[a] < 65536 else 4
+            n = cnt[f][a]
+            w = 0 if n == 0 or 64 * f + a in listed else 1 if n < 256 else 2 if n < 65536 else 4
             widths.append(w)
             total += _r256(plane * w)
+    total += _r256(8 * n_list)
     worst = sum(_r256(plane * 4) * (n - 1) for n in nb)
-    return total, worst, widths
+    return total, worst, widths, n_list
 
 
-def test_compact_tables_all_widths_bit_exact(M):
+def test_compact_tables_and_voxel_list_bit_exact(M):
     """A 0.25 m pair of 250k points: count bin 1 holds well over 65,536
     voxels (4-byte entries), bin 2 tens of thousands (2-byte), the upper
-    bins a few or none (1-byte).  Poses spread so that the overlap boxes
-    cut the tables everywhere."""
+    count bins a few or none and the z-variance bins 2-31 a few hundred to
+    two thousand each (the voxel list), the empty bins no table.  Poses
+    spread so that the overlap boxes cut the tables and the list everywhere."""
     rng = np.random.default_rng(31)
     pair = synth.surface_pair(rng, 250_000, 0.25)
     kw = dict(origin=pair.origin, dims=pair.dims, voxel=pair.voxel, features=3, nb_count=32,
@@ -65,10 +82,12 @@ def test_compact_tables_all_widths_bit_exact(M):
     grid = M.Grid(**kw)
     og = O.Grid(**kw)
     ref = M.Ref(grid, pair.A)
-    tables, worst, widths = _table_bytes(og, pair.A, pair.dims, (32, 32))
-    _say("resident", ref.resident_bytes, "of at most", ref.persistent_bytes, "widths", widths)
-    assert {1, 2, 4} <= set(widths)
+    tables, worst, widths, n_list = _table_bytes(og, pair.A, pair.dims, (32, 32))
+    _say("resident", ref.resident_bytes, "of at most", ref.persistent_bytes, "widths", widths,
+         "listed voxels", n_list)
+    assert {0, 2, 4} <= set(widths) and n_list > 5000
     assert ref.resident_bytes == ref.persistent_bytes - worst + tables
+    assert ref.resident_bytes < 1 << 30
     poses = pair.eta_gt + rng.uniform(-1, 1, (24, 6)) * np.array(
         [30.0, 30.0, 2.0, 3 * D2R, 3 * D2R, 30 * D2R])
     res = M.eval_poses(ref, pair.B, poses, want_hist=True, want_stats=True)
@@ -83,7 +102,8 @@ def test_compact_tables_all_widths_bit_exact(M):
 
 
 def test_compact_tables_small_scan(M):
-    """A scan of 200 points: every bin fits one byte per entry."""
+    """A scan of 200 points on a small grid (no voxel list): every occupied
+    bin fits one byte per entry."""
     pair = synth.tiny_pair()
     A = np.ascontiguousarray(pair.A[:, :200])
     kw = dict(origin=pair.origin, dims=pair.dims, voxel=pair.voxel, features=3, nb_count=8,
@@ -91,9 +111,9 @@ def test_compact_tables_small_scan(M):
     grid = M.Grid(**kw)
     og = O.Grid(**kw)
     ref = M.Ref(grid, A)
-    tables, worst, widths = _table_bytes(og, A, pair.dims, (8, 8))
+    tables, worst, widths, n_list = _table_bytes(og, A, pair.dims, (8, 8))
     _say("resident", ref.resident_bytes, "of at most", ref.persistent_bytes, "widths", widths)
-    assert set(widths) == {1}
+    assert set(widths) <= {0, 1} and 1 in widths and n_list == 0
     assert ref.resident_bytes == ref.persistent_bytes - worst + tables
     poses = synth.grid8_poses(2)[:64]
     res = M.eval_poses(ref, pair.B, poses, want_hist=True)
