@@ -61,7 +61,7 @@ __host__ __device__ inline Layout eval_layout(int waves, int hist_copies, int hi
   Layout L;
   int o = al16(hist_copies * hist_words * 4);
   L.off_cnta = o;   o += 512;                   // cntA[2][64]
-  L.off_edges = o;  o += 256 + 512 + 512;       // 64 u32 + 64 u64 + 64 f64
+  L.off_edges = o;  o += 256 + 512 + 512;       // 64 u32 + 64 u64 + 64 f64 (finish: 2 x 66 f64)
   L.off_wave = o;   o += al16(waves * 48 + 16); // box [W][8] i32, counts [W][2] u64, flags
   L.off_plan = o;   o += al16(plan_bytes);
   o = (o + 255) & ~255;
@@ -1000,48 +1000,70 @@ __global__ void __launch_bounds__(1024) k_eval(const PairDev *__restrict__ pairs
       }
       __syncthreads();
     }
+    // Cells of voxels empty in B (integers, exact in any order), one wave per
+    // row with the lanes over the columns: H[a][0] = (A's voxels of bin a in
+    // O) - sum_{b>=1} H[a][b] for a >= 1, and H[0][0] = |O| - sum_{a>=1} (A's
+    // voxels of bin a in O) - sum_{b>=1} H[0][b].
     if (nonempty) {
-      for (int t = tid; t < nf * 64; t += T) {
-        const int f = t >> 6, a = t & 63, nb = P.nb[f];
-        if (a >= 1 && a < nb) {
-          uint32_t *row = hist + (f ? hoff1 : 0) + a * nb;
-          uint32_t rs = 0;
-          for (int b = 1; b < nb; ++b) rs += row[b];
-          row[0] = cntA[t] - rs;
+      for (int r = wid; r < nf * 64; r += W) {
+        const int f = r >> 6, a = r & 63, nb = f ? nb1 : nb0;
+        if (a >= nb) continue;
+        uint32_t *H = hist + (f ? hoff1 : 0);
+        const bool col = lane >= 1 && lane < nb;
+        if (a >= 1) {
+          const unsigned long long rs =
+              wave_sum_u64(col ? (unsigned long long)H[a * nb + lane] : 0ull);
+          if (lane == 0) H[a * nb] = cntA[r] - (uint32_t)rs;
+        } else {
+          const unsigned long long s = wave_sum_u64(
+              col ? (unsigned long long)cntA[(f << 6) + lane] + H[lane] : 0ull);
+          if (lane == 0) H[0] = (uint32_t)(nO - (int64_t)s);
         }
       }
-    }
-    __syncthreads();
-    if (nonempty && tid < nf) {
-      const int f = tid, nb = P.nb[f];
-      uint32_t *H = hist + (f ? hoff1 : 0);
-      int64_t rest = nO;
-      for (int a = 1; a < nb; ++a) rest -= cntA[(f << 6) + a];
-      for (int b = 1; b < nb; ++b) rest -= H[b];
-      H[0] = (uint32_t)rest;
     }
     __syncthreads();
 
-    if (wid < nf) {
-      const int f = wid, nb = P.nb[f];
-      const uint32_t *H = hist + (f ? hoff1 : 0);
-      double hxy = 0.0, hx = 0.0, hy = 0.0;
-      if (nonempty) {
-        const double N = (double)nO;
-        for (int i = lane; i < nb * nb; i += 64) hxy += plogp_term(H[i], N);
-        if (lane < nb) {
-          uint64_t r = 0, c = 0;
-          for (int b = 0; b < nb; ++b) r += H[lane * nb + b];
-          for (int a = 0; a < nb; ++a) c += H[a * nb + lane];
-          hx = plogp_term(r, N);
-          hy = plogp_term(c, N);
+    // Entropies (Eqs. 2-5) in a fixed order that does not depend on the launch
+    // shape: H(X,Y) as wave sums over 64-cell chunks of the histogram, then a
+    // wave sum over the chunks; H(X) and H(Y) as wave sums over the rows' and
+    // columns' terms.  The tasks are spread over the waves; their results go to
+    // the bin-edge area of LDS, which the next item loads afresh.
+    double *part = (double *)cedge;  // [feature][66]: chunks, then H(X), H(Y)
+    const int ch0 = (nb0 * nb0 + 63) >> 6, ch1 = (nb1 * nb1 + 63) >> 6;
+    if (nonempty) {
+      const double N = (double)nO;
+      const int ntask = ch0 + 2 + (nf > 1 ? ch1 + 2 : 0);
+      for (int k = wid; k < ntask; k += W) {
+        const int f = k < ch0 + 2 ? 0 : 1, j = f ? k - (ch0 + 2) : k;
+        const int nb = f ? nb1 : nb0, ch = f ? ch1 : ch0;
+        const uint32_t *H = hist + (f ? hoff1 : 0);
+        double v = 0.0;
+        if (j < ch) {
+          const int i = (j << 6) + lane;
+          if (i < nb * nb) v = plogp_term(H[i], N);
+        } else if (lane < nb) {
+          uint64_t m = 0;
+          if (j == ch) {
+            for (int b = 0; b < nb; ++b) m += H[lane * nb + b];  // row sums: H(X)
+          } else {
+            for (int a = 0; a < nb; ++a) m += H[a * nb + lane];  // column sums: H(Y)
+          }
+          v = plogp_term(m, N);
         }
+        v = wave_sum_f64(v);
+        if (lane == 0) part[f * 66 + (j < ch ? j : 64 + (j - ch))] = v;
       }
+    }
+    __syncthreads();
+    if (wid < nf) {
+      const int f = wid, nb = f ? nb1 : nb0, ch = f ? ch1 : ch0;
+      double hxy = nonempty && lane < ch ? part[f * 66 + lane] : 0.0;
       hxy = wave_sum_f64(hxy);
-      hx = wave_sum_f64(hx);
-      hy = wave_sum_f64(hy);
-      if (lane == 0) P.mi_out[(int64_t)f * P.K + pose.out_index] = nonempty ? (hx + hy) - hxy : 0.0;
+      if (lane == 0)
+        P.mi_out[(int64_t)f * P.K + pose.out_index] =
+            nonempty ? (part[f * 66 + 64] + part[f * 66 + 65]) - hxy : 0.0;
       if (P.hist_out) {
+        const uint32_t *H = hist + (f ? hoff1 : 0);
         uint32_t *dst = P.hist_out + P.hist_off[f] + (int64_t)pose.out_index * nb * nb;
         for (int i = lane; i < nb * nb; i += 64) dst[i] = nonempty ? H[i] : 0u;
       }
