@@ -38,7 +38,8 @@ def _r256(b):
 def _table_bytes(og, A, dims, nb):
     """The tables' and voxel list's bytes as the layout rule gives them from
     the oracle's bins of scan A: an empty bin has no table; on a grid of at
-    least 2^20 table entries the sparsest bins (ascending count, ties by
+    least 2^20 table entries (with x and y below 2^20 voxels and z below 2^16,
+    the list entry's fields) the sparsest bins (ascending count, ties by
     feature and bin, while the list holds at most 8192 voxels) form the voxel
     list, 8 bytes per voxel; every other bin a >= 1 has a table of the fewest of
     1, 2 or 4 bytes per entry that hold its voxel count, each table (and the
@@ -49,7 +50,7 @@ def _table_bytes(og, A, dims, nb):
     cnt = [np.bincount(bins[f], minlength=nb[f]) for f in range(bins.shape[0])]
     listed = set()
     n_list = 0
-    if plane >= 1 << 20:
+    if plane >= 1 << 20 and dims[0] < 1 << 20 and dims[1] < 1 << 20 and dims[2] < 1 << 16:
         sparse = sorted((int(cnt[f][a]), 64 * f + a) for f in range(len(cnt))
                         for a in range(1, nb[f]) if 0 < cnt[f][a] < 65536)
         for n, key in sparse:
@@ -122,3 +123,57 @@ def test_compact_tables_small_scan(M):
     for f in range(2):
         assert np.array_equal(res["hist"][f].cpu().numpy().astype(np.int64),
                               oh[f].astype(np.int64))
+
+
+def _sparse_case(M, dims, voxel, A, B, poses, label):
+    origin = (0.0, 0.0, 0.0)
+    kw = dict(origin=origin, dims=dims, voxel=voxel, features=3, nb_count=16, nb_zvar=16)
+    grid = M.Grid(**kw)
+    og = O.Grid(**kw)
+    ref = M.Ref(grid, A)
+    tables, worst, widths, n_list = _table_bytes(og, A, dims, (16, 16))
+    _say(label, "resident", ref.resident_bytes, "widths", widths, "listed", n_list)
+    assert ref.resident_bytes == ref.persistent_bytes - worst + tables
+    res = M.eval_poses(ref, B, poses, want_hist=True, want_stats=True)
+    torch.cuda.synchronize()
+    omi, oh, ost = O.eval_poses(og, A, B, poses, want_hist=True, want_stats=True)
+    for f in range(2):
+        assert np.array_equal(res["hist"][f].cpu().numpy().astype(np.int64),
+                              oh[f].astype(np.int64)), (label, f)
+        assert np.max(np.abs(res["mi"][f].cpu().numpy() - omi[f])) <= 1e-6, label
+    st = M.stats_to_numpy(res["stats_raw"], len(poses))
+    assert np.array_equal(st["n_overlap"], ost[:, 6]), label
+    return widths, n_list
+
+
+def test_all_bins_listed_on_a_large_grid(M):
+    """A 400 x 400 x 8 grid (over 2^20 table entries) and a scan A of 3,000
+    points: every occupied bin is sparse, so the reference keeps no table at
+    all, only the voxel list.  Poses move scan B across A's extent so that the
+    overlap boxes take every part of the list, or none of it."""
+    rng = np.random.default_rng(5)
+    A = np.stack([rng.uniform(0, 40, 3000), rng.uniform(0, 40, 3000),
+                  rng.uniform(0, 0.8, 3000)]).astype(np.float32)
+    B = np.stack([rng.uniform(5, 25, 2000), rng.uniform(5, 25, 2000),
+                  rng.uniform(0, 0.8, 2000)]).astype(np.float32)
+    poses = np.zeros((12, 6))
+    poses[:, 0] = np.linspace(-30, 30, 12)
+    poses[:, 1] = np.linspace(20, -20, 12)
+    poses[:, 5] = np.linspace(-0.3, 0.3, 12)
+    poses[0, 0] = 100.0  # B off the grid: no overlap
+    widths, n_list = _sparse_case(M, (400, 400, 8), 0.1, A, B, poses, "all listed")
+    assert set(widths) == {0} and n_list == 5996
+
+
+def test_one_voxel_reference(M):
+    """Scan A in one voxel of a large grid: the voxel list has one entry per
+    feature, and the poses put that voxel inside and outside the overlap box."""
+    rng = np.random.default_rng(6)
+    A = np.full((3, 50), 12.05, np.float32)
+    A[2] = 0.05
+    B = np.stack([rng.uniform(10, 14, 500), rng.uniform(10, 14, 500),
+                  rng.uniform(0, 0.8, 500)]).astype(np.float32)
+    poses = np.zeros((6, 6))
+    poses[:, 0] = [0.0, 0.05, -1.0, 1.0, 3.0, -3.0]
+    widths, n_list = _sparse_case(M, (400, 400, 8), 0.1, A, B, poses, "one voxel")
+    assert n_list == 2 and set(widths) == {0}  # one voxel, two features
