@@ -189,22 +189,24 @@ mi_status mi_pose_to_matrix(const double eta[6], double rt[12]);
 size_t mi_features_ref_workspace(const mi_grid *g, int64_t n_a, size_t *persistent_bytes);
 
 /* Alg. 1 initialisation: voxel ids of all points of scan A and A's feature
- * map for all voxels (bin 0 = empty), A's index box and, per feature bin, a
- * summed-volume table of A's occupied voxels (used to count A's voxels of each
- * bin inside any overlap box).  Each table has the fewest bytes per entry (1,
- * 2 or 4) that hold its bin's voxel count, with entries modulo 2^(8 width):
- * box counts, which lie between 0 and that count, stay exact.  The call reads
- * A's per-bin voxel counts back once to lay the tables out, so it waits for
- * the stream's work so far.  xyz_a: device SoA [3][n_a], n_a >= 0.
- * The grid must outlive the returned mi_ref. */
+ * map for all voxels (bin 0 = empty), A's index box and what counts A's voxels
+ * of each bin inside any overlap box: per occupied bin a summed-volume table
+ * with the fewest bytes per entry (1, 2 or 4) that hold the bin's voxel count,
+ * entries modulo 2^(8 width) (box counts, which lie between 0 and that count,
+ * stay exact); on grids of at least 2^20 table entries (fewer than 2^20
+ * voxels in x and y, 2^16 in z) the sparsest bins, up to 8192 voxels in all,
+ * as a list of their voxels instead.  The call reads A's per-bin voxel counts
+ * back once to lay this out, so it waits for the stream's work so far.
+ * xyz_a: device SoA [3][n_a], n_a >= 0.  The grid must outlive the returned
+ * mi_ref. */
 mi_status mi_features_ref(const mi_grid *g, const float *xyz_a, int64_t n_a, void *ws,
                           size_t ws_bytes, void *stream, mi_ref **out);
 void mi_ref_destroy(mi_ref *r);
 
 /* Bytes at the start of the reference's workspace that the reference keeps
- * (bins, box, counters and the tables as laid out for scan A); the rest of
- * the workspace may be reused by work ordered after mi_features_ref on its
- * stream.  0 for NULL. */
+ * (bins, box, counters, the tables and voxel list as laid out for scan A);
+ * the rest of the workspace may be reused by work ordered after
+ * mi_features_ref on its stream.  0 for NULL. */
 size_t mi_ref_resident_bytes(const mi_ref *r);
 
 /* Device pointer to A's bin of every voxel for feature slot f (slot 0 = count
