@@ -2796,7 +2796,12 @@ extern "C" mi_status mi_server_step(mi_server *s, int32_t *n_active, int32_t *n_
     std::vector<mi_status> began(admitted.size());
     for (size_t i = 0; i < admitted.size(); ++i)
       began[i] = req_begin(s, admitted[i], &builds[i], counts + 128 * i);
-    HIP_TRY(hipStreamSynchronize(s->stream), "bin counts");
+    const hipError_t se = hipStreamSynchronize(s->stream);
+    if (se != hipSuccess) {
+      // none of them has a reference: they fail rather than stay active
+      for (Request *r : admitted) req_fail(s, r, MI_E_DEVICE);
+      return dev_fail(se, "bin counts");
+    }
     for (size_t i = 0; i < admitted.size(); ++i) {
       const mi_status st =
           began[i] == MI_OK ? req_finish(s, admitted[i], builds[i], counts + 128 * i) : began[i];
