@@ -72,10 +72,11 @@ def _table_bytes(og, A, dims, nb):
 
 def test_compact_tables_and_voxel_list_bit_exact(M):
     """A 0.25 m pair of 250k points: count bin 1 holds well over 65,536
-    voxels (4-byte entries), bin 2 tens of thousands (2-byte), the upper
-    count bins a few or none and the z-variance bins 2-31 a few hundred to
-    two thousand each (the voxel list), the empty bins no table.  Poses
-    spread so that the overlap boxes cut the tables and the list everywhere."""
+    voxels (4-byte entries), bins 2 and 3 thousands (2-byte), the upper count
+    bins a few or none; the z-variance bins 2-31 hold a few hundred to two
+    thousand each, the sparsest of them in the voxel list and the rest in
+    2-byte tables; the empty bins have no table.  Poses spread so that the
+    overlap boxes cut the tables and the list everywhere."""
     rng = np.random.default_rng(31)
     pair = synth.surface_pair(rng, 250_000, 0.25)
     kw = dict(origin=pair.origin, dims=pair.dims, voxel=pair.voxel, features=3, nb_count=32,
