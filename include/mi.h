@@ -209,6 +209,16 @@ void mi_ref_destroy(mi_ref *r);
  * mi_features_ref on its stream.  0 for NULL. */
 size_t mi_ref_resident_bytes(const mi_ref *r);
 
+/* Moves a built reference into another workspace (device memory of at least
+ * mi_ref_resident_bytes(r) bytes, 256-byte aligned, not overlapping the old
+ * one): the resident bytes are copied on the stream and the reference then
+ * lives there, so that a caller can build in a workspace sized for the worst
+ * case and keep only what scan A needs.  The old workspace is free once the
+ * copy, and every evaluation enqueued before it that reads the reference, has
+ * completed.  Plans and batches created before the move still point at the old
+ * workspace: create them after it.  The copy itself does not wait. */
+mi_status mi_ref_move(mi_ref *r, void *ws, size_t ws_bytes, void *stream);
+
 /* Device pointer to A's bin of every voxel for feature slot f (slot 0 = count
  * when enabled, then z-variance), uint8 [dims z][y][x]. */
 mi_status mi_ref_bins(const mi_ref *r, int32_t feature_slot, const uint8_t **dev_bins);

@@ -493,6 +493,7 @@ struct mi_ref {
   RefDev rd;
   int64_t n_a;
   size_t resident;             // bytes of the workspace the reference keeps
+  uint8_t *base;               // the workspace it keeps them in
 };
 
 static int64_t sat_plane(const GridInfo &gi) {
@@ -636,6 +637,7 @@ static mi_status ref_finish(const mi_grid *g, RefBuild &b, const uint32_t *count
   r->rd = rd;
   r->n_a = b.n_a;
   r->resident = (size_t)(b.sat_region - (uint8_t *)b.ws) + used;
+  r->base = (uint8_t *)b.ws;
   *out = r.release();
   return MI_OK;
 }
@@ -658,6 +660,37 @@ extern "C" mi_status mi_features_ref(const mi_grid *g, const float *xyz_a, int64
 extern "C" void mi_ref_destroy(mi_ref *r) { free(r); }
 
 extern "C" size_t mi_ref_resident_bytes(const mi_ref *r) { return r ? r->resident : 0; }
+
+extern "C" mi_status mi_ref_move(mi_ref *r, void *ws, size_t ws_bytes, void *stream) {
+  return guarded("mi_ref_move", [&]() -> mi_status {
+  if (!r) return fail(MI_E_INVALID, "mi_ref_move: NULL reference");
+  if (!ws || ((uintptr_t)ws & 255)) return fail(MI_E_WORKSPACE, "workspace NULL or not 256-aligned");
+  if (ws_bytes < r->resident)
+    return fail(MI_E_WORKSPACE, "mi_ref_move needs %zu bytes, got %zu", r->resident, ws_bytes);
+  uint8_t *nb = (uint8_t *)ws, *ob = r->base;
+  if (nb == ob) return MI_OK;
+  if (nb < ob + r->resident && ob < nb + r->resident)
+    return fail(MI_E_INVALID, "mi_ref_move: the workspaces overlap");
+  HIP_TRY(hipMemcpyAsync(nb, ob, r->resident, hipMemcpyDeviceToDevice, (hipStream_t)stream),
+          "reference copy");
+  // every resident address keeps its offset; the per-voxel sums are gone
+  auto at = [&](auto *p) { return p ? (decltype(p))(nb + ((uint8_t *)p - ob)) : p; };
+  RefDev &rd = r->rd;
+  for (int f = 0; f < 2; ++f) {
+    rd.bins[f] = at(rd.bins[f]);
+    rd.sat[f] = at(rd.sat[f]);
+  }
+  rd.alist = at(rd.alist);
+  rd.abox = at(rd.abox);
+  rd.counters = at(rd.counters);
+  rd.bin_cnt = at(rd.bin_cnt);
+  rd.list_cur = at(rd.list_cur);
+  rd.cnt = nullptr;
+  rd.s1 = rd.s2 = nullptr;
+  r->base = nb;
+  return MI_OK;
+  });
+}
 
 extern "C" mi_status mi_ref_bins(const mi_ref *r, int32_t f, const uint8_t **dev_bins) {
   return guarded("mi_ref_bins", [&]() -> mi_status {

@@ -117,6 +117,7 @@ def _load():
         "mi_features_ref": ([vp, vp, i64, vp, sz, vp, C.POINTER(vp)], st),
         "mi_ref_destroy": ([vp], None),
         "mi_ref_resident_bytes": ([vp], sz),
+        "mi_ref_move": ([vp, vp, sz, vp], st),
         "mi_ref_bins": ([vp, st, C.POINTER(vp)], st),
         "mi_ref_summary": ([vp, vp, C.POINTER(C.c_int32), C.POINTER(C.c_int64)], st),
         "mi_eval_poses_workspace": ([vp, i64, dp, i64, u32, sz], sz),
@@ -160,7 +161,7 @@ _lib = _load()
 EXPORTED = ("mi_status_str", "mi_last_error", "mi_tuning_set", "mi_tuning_get",
             "mi_profile_enable", "mi_profile_read", "mi_grid_create",
             "mi_grid_destroy", "mi_grid_edges", "mi_pose_to_matrix", "mi_features_ref_workspace",
-            "mi_features_ref", "mi_ref_destroy", "mi_ref_resident_bytes", "mi_ref_bins",
+            "mi_features_ref", "mi_ref_destroy", "mi_ref_resident_bytes", "mi_ref_move", "mi_ref_bins",
             "mi_ref_summary",
             "mi_eval_poses_workspace", "mi_eval_poses", "mi_eval_poses_plain_workspace",
             "mi_eval_poses_plain", "mi_plan_create", "mi_plan_execute", "mi_plan_destroy",
@@ -339,7 +340,10 @@ def pose_to_matrix(eta) -> np.ndarray:
 class Ref:
     """mi_ref: scan A's resident feature map (Alg. 1 initialisation)."""
 
-    def __init__(self, grid: Grid, xyz_a, stream=None):
+    def __init__(self, grid: Grid, xyz_a, stream=None, compact=True):
+        """compact: once built, move the reference into a workspace of just
+        its resident size (mi_ref_move), so that the worst-case workspace it
+        was built in goes back to torch's allocator."""
         self.grid = grid
         with _on(stream):
             self.xyz_a = _dev_points(xyz_a)
@@ -356,6 +360,13 @@ class Ref:
         # the bytes of the workspace the reference keeps (its tables as laid out
         # for this scan A; persistent_bytes is the most they could take)
         self.resident_bytes = _lib.mi_ref_resident_bytes(h)
+        if compact and self.resident_bytes < self.ws.numel():
+            with _on(stream):
+                ws = _workspace(self.resident_bytes)
+                _check(_lib.mi_ref_move(h, _dptr(ws), ws.numel(), _stream(stream)),
+                       "mi_ref_move")
+                # the old block is reused only by work ordered after the copy
+                self.ws = ws
 
     def __del__(self):
         if getattr(self, "_h", None) and _lib is not None:

@@ -178,3 +178,45 @@ def test_one_voxel_reference(M):
     poses[:, 0] = [0.0, 0.05, -1.0, 1.0, 3.0, -3.0]
     widths, n_list = _sparse_case(M, (400, 400, 8), 0.1, A, B, poses, "one voxel")
     assert n_list == 2 and set(widths) == {0}  # one voxel, two features
+
+
+def test_moved_reference_matches(M):
+    """A reference moved into a workspace of its resident size (the binding's
+    default) evaluates bit for bit like one left in its worst-case workspace,
+    also after a second move once the workspace it left is overwritten."""
+    import ctypes as C
+    rng = np.random.default_rng(8)
+    pair = synth.surface_pair(rng, 60_000, 0.25)
+    kw = dict(origin=pair.origin, dims=pair.dims, voxel=pair.voxel, features=3, nb_count=32,
+              nb_zvar=32)
+    grid = M.Grid(**kw)
+    full = M.Ref(grid, pair.A, compact=False)
+    small = M.Ref(grid, pair.A)
+    _say("workspaces", full.ws.numel(), small.ws.numel(), "resident", small.resident_bytes)
+    assert small.ws.numel() < full.ws.numel() and small.ws.numel() >= small.resident_bytes
+    poses = pair.eta_gt + rng.uniform(-1, 1, (16, 6)) * np.array(
+        [20.0, 20.0, 1.0, 2 * D2R, 2 * D2R, 20 * D2R])
+
+    def run(ref):
+        r = M.eval_poses(ref, pair.B, poses, want_hist=True, want_stats=True)
+        torch.cuda.synchronize()
+        return r
+
+    a, b = run(full), run(small)
+    for f in range(2):
+        assert torch.equal(full.bins(f), small.bins(f))
+        assert torch.equal(a["hist"][f], b["hist"][f])
+    assert torch.equal(a["mi"], b["mi"]) and torch.equal(a["stats_raw"], b["stats_raw"])
+    ws3 = torch.empty(small.resident_bytes, dtype=torch.uint8, device="cuda")
+    st = M.lib().mi_ref_move(small._h, C.c_void_p(ws3.data_ptr()), ws3.numel(),
+                             C.c_void_p(torch.cuda.current_stream().cuda_stream))
+    assert st == 0
+    old, small.ws = small.ws, ws3
+    old.fill_(0xAB)
+    c = run(small)
+    for f in range(2):
+        assert torch.equal(a["hist"][f], c["hist"][f])
+    assert torch.equal(a["mi"], c["mi"])
+    # too small a workspace is refused
+    tiny = torch.empty(256, dtype=torch.uint8, device="cuda")
+    assert M.lib().mi_ref_move(small._h, C.c_void_p(tiny.data_ptr()), tiny.numel(), None) != 0
