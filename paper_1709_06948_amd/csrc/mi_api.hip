@@ -500,11 +500,11 @@ static int64_t sat_plane(const GridInfo &gi) {
   return (int64_t)(gi.dims[0] + 1) * (gi.dims[1] + 1) * (gi.dims[2] + 1);
 }
 
-// Resident part: bins, box and counters, per-bin voxel counts, then the
-// tables themselves, last so that what they leave unused is
-// the resident part's tail (the region is sized for 4 bytes per entry; each
-// table gets 1, 2 or 4 once the bins are counted).  Transient part: the
-// per-voxel sums.
+// Resident part: bins, box and counters, per-bin voxel counts and list
+// cursors, then the region of the tables and the voxel list, last so that
+// what they leave unused is the resident part's tail (the region is sized for
+// a 4-byte table per bin; ref_finish lays it out once the bins are counted).
+// Transient part: the per-voxel sums.
 static size_t ref_layout(const GridInfo &gi, Carver &c, RefDev *rd, uint8_t **sat_region) {
   const int64_t V = gi.V;
   uint8_t *bins[2] = {nullptr, nullptr};
