@@ -366,6 +366,31 @@ mi_status mi_autotune(const mi_work_item *items, int64_t n_items, uint32_t flags
                       int64_t max_poses, void *ws, size_t ws_bytes, void *stream,
                       mi_autotune_report *out);
 
+/* Tuning cache: a JSON file of one object whose members map a workload key to
+ * a tuning, [waves, hash_bytes, hist_copies, stripe_rows, wgs_per_cu].  The
+ * key names what the best launch shape depends on: the GPU architecture, the
+ * feature set and bin counts, and the size classes of scan B and of the grid
+ * (the ceiling of log2 of the largest point count and voxel count),
+ * "<arch>/f<features>/b<nb0>x<nb1>/n<bits>/v<bits>"; buf receives it (len
+ * bytes at most, NUL-terminated; MI_E_INVALID when it does not fit).
+ * mi_tuning_cache_get sets *found to 1 and fills *t when the file has the key
+ * (a missing file is an empty cache); mi_tuning_cache_put adds or replaces
+ * it, rewriting the file through a temporary in the same directory.  Host
+ * only: no device is used.  Not safe against concurrent writers. */
+mi_status mi_tuning_cache_key(const char *arch, uint32_t features, int32_t nb0, int32_t nb1,
+                              int64_t n_b, int64_t voxels, char *buf, size_t len);
+mi_status mi_tuning_cache_get(const char *path, const char *key, mi_tuning *t, int32_t *found);
+mi_status mi_tuning_cache_put(const char *path, const char *key, const mi_tuning *t);
+
+/* mi_autotune through the cache at `path`: the items' key (their largest
+ * scan B and grid, the first item's features and bin counts, the current
+ * device's architecture) is looked up; a cached tuning is made current without
+ * timing anything (report: that tuning, tried = 0, times 0); otherwise
+ * mi_autotune runs and its best tuning is stored under the key. */
+mi_status mi_autotune_cached(const mi_work_item *items, int64_t n_items, uint32_t flags,
+                             int64_t max_poses, void *ws, size_t ws_bytes, void *stream,
+                             const char *path, mi_autotune_report *out);
+
 /* ------------------------------------------------------------- search */
 
 /* Coarse-to-fine grid search for Eq. 1 from the initial guess T_o = init

@@ -2079,6 +2079,159 @@ extern "C" mi_status mi_autotune(const mi_work_item *items, int64_t n_items, uin
   });
 }
 
+// ------------------------------------------------------------ tuning cache
+
+namespace {
+
+int ceil_log2(int64_t n) {
+  int b = 0;
+  while (b < 62 && ((int64_t)1 << b) < n) ++b;
+  return b;
+}
+
+// The cache file: {"key": [w, h, c, r, p], ...}.  Keys hold no quotes or
+// backslashes (they are built by mi_tuning_cache_key).
+bool cache_read(const char *path, std::map<std::string, std::array<int64_t, 5>> &m) {
+  FILE *f = fopen(path, "rb");
+  if (!f) return true;  // no file: an empty cache
+  std::string text;
+  char buf[4096];
+  size_t k;
+  while ((k = fread(buf, 1, sizeof buf, f)) > 0) text.append(buf, k);
+  fclose(f);
+  size_t p = text.find('{');
+  if (p == std::string::npos) return false;
+  for (;;) {
+    const size_t q0 = text.find('"', p);
+    if (q0 == std::string::npos) break;
+    const size_t q1 = text.find('"', q0 + 1);
+    if (q1 == std::string::npos) return false;
+    const std::string key = text.substr(q0 + 1, q1 - q0 - 1);
+    const size_t b0 = text.find('[', q1), b1 = text.find(']', q1);
+    if (b0 == std::string::npos || b1 == std::string::npos || b1 < b0) return false;
+    std::array<int64_t, 5> v{};
+    const char *c = text.c_str() + b0 + 1;
+    for (int n = 0; n < 5; ++n) {
+      char *end = nullptr;
+      v[n] = strtoll(c, &end, 10);
+      if (end == c) return false;
+      c = end;
+      while (*c == ' ' || *c == ',' || *c == '\n' || *c == '\t' || *c == '\r') ++c;
+    }
+    m[key] = v;
+    p = b1 + 1;
+  }
+  return true;
+}
+
+bool key_ok(const char *key) {
+  if (!key || !*key) return false;
+  for (const char *c = key; *c; ++c)
+    if (*c == '"' || *c == '\\' || (unsigned char)*c < 0x20) return false;
+  return true;
+}
+
+}  // namespace
+
+extern "C" mi_status mi_tuning_cache_key(const char *arch, uint32_t features, int32_t nb0,
+                                         int32_t nb1, int64_t n_b, int64_t voxels, char *buf,
+                                         size_t len) {
+  return guarded("mi_tuning_cache_key", [&]() -> mi_status {
+  if (!arch || !buf || len == 0) return fail(MI_E_INVALID, "mi_tuning_cache_key: bad argument");
+  // the architecture up to its first ':' (feature suffixes such as :sramecc+)
+  std::string a(arch);
+  a = a.substr(0, a.find(':'));
+  const int n = snprintf(buf, len, "%s/f%u/b%dx%d/n%d/v%d", a.c_str(), features, nb0, nb1,
+                         ceil_log2(std::max<int64_t>(n_b, 1)),
+                         ceil_log2(std::max<int64_t>(voxels, 1)));
+  if (n < 0 || (size_t)n >= len) return fail(MI_E_INVALID, "mi_tuning_cache_key: buffer too small");
+  if (!key_ok(buf)) return fail(MI_E_INVALID, "mi_tuning_cache_key: bad architecture name");
+  return MI_OK;
+  });
+}
+
+extern "C" mi_status mi_tuning_cache_get(const char *path, const char *key, mi_tuning *t,
+                                         int32_t *found) {
+  return guarded("mi_tuning_cache_get", [&]() -> mi_status {
+  if (!path || !key_ok(key) || !t || !found)
+    return fail(MI_E_INVALID, "mi_tuning_cache_get: bad argument");
+  *found = 0;
+  std::map<std::string, std::array<int64_t, 5>> m;
+  if (!cache_read(path, m)) return fail(MI_E_INVALID, "tuning cache %s: not a cache file", path);
+  const auto it = m.find(key);
+  if (it == m.end()) return MI_OK;
+  const auto &v = it->second;
+  *t = mi_tuning{(int32_t)v[0], (int32_t)v[1], (int32_t)v[2], (int32_t)v[3], (int32_t)v[4]};
+  *found = 1;
+  return MI_OK;
+  });
+}
+
+extern "C" mi_status mi_tuning_cache_put(const char *path, const char *key, const mi_tuning *t) {
+  return guarded("mi_tuning_cache_put", [&]() -> mi_status {
+  if (!path || !key_ok(key) || !t) return fail(MI_E_INVALID, "mi_tuning_cache_put: bad argument");
+  std::map<std::string, std::array<int64_t, 5>> m;
+  if (!cache_read(path, m)) return fail(MI_E_INVALID, "tuning cache %s: not a cache file", path);
+  m[key] = {t->waves, t->hash_bytes, t->hist_copies, t->stripe_rows, t->wgs_per_cu};
+  const std::string tmp = std::string(path) + ".tmp";
+  FILE *f = fopen(tmp.c_str(), "wb");
+  if (!f) return fail(MI_E_INVALID, "tuning cache %s: cannot write", tmp.c_str());
+  fputs("{\n", f);
+  size_t k = 0;
+  for (const auto &e : m) {
+    const auto &v = e.second;
+    fprintf(f, "  \"%s\": [%lld, %lld, %lld, %lld, %lld]%s\n", e.first.c_str(), (long long)v[0],
+            (long long)v[1], (long long)v[2], (long long)v[3], (long long)v[4],
+            ++k < m.size() ? "," : "");
+  }
+  fputs("}\n", f);
+  const bool ok = fclose(f) == 0;
+  if (!ok || rename(tmp.c_str(), path) != 0) {
+    remove(tmp.c_str());
+    return fail(MI_E_INVALID, "tuning cache %s: cannot write", path);
+  }
+  return MI_OK;
+  });
+}
+
+extern "C" mi_status mi_autotune_cached(const mi_work_item *items, int64_t n_items,
+                                        uint32_t flags, int64_t max_poses, void *ws,
+                                        size_t ws_bytes, void *stream, const char *path,
+                                        mi_autotune_report *out) {
+  return guarded("mi_autotune_cached", [&]() -> mi_status {
+  if (!items || n_items <= 0 || !out || !path)
+    return fail(MI_E_INVALID, "mi_autotune_cached: bad arguments");
+  int64_t nb_max = 0, v_max = 0;
+  for (int64_t i = 0; i < n_items; ++i) {
+    if (!items[i].ref) return fail(MI_E_INVALID, "work item %lld: NULL reference", (long long)i);
+    nb_max = std::max(nb_max, items[i].n_b);
+    v_max = std::max(v_max, items[i].ref->g->gi.V);
+  }
+  const GridInfo &gi = items[0].ref->g->gi;
+  int dev = 0;
+  hipDeviceProp_t prop;
+  HIP_TRY(hipGetDevice(&dev), "device");
+  HIP_TRY(hipGetDeviceProperties(&prop, dev), "device properties");
+  char key[256];
+  mi_status st = mi_tuning_cache_key(prop.gcnArchName, gi.features, gi.nb[0],
+                                     gi.nf > 1 ? gi.nb[1] : 0, nb_max, v_max, key, sizeof key);
+  if (st != MI_OK) return st;
+  mi_tuning t;
+  int32_t found = 0;
+  st = mi_tuning_cache_get(path, key, &t, &found);
+  if (st != MI_OK) return st;
+  if (found) {
+    st = mi_tuning_set(&t);
+    if (st != MI_OK) return st;
+    *out = mi_autotune_report{t, 0.0, 0.0, 0};
+    return MI_OK;
+  }
+  st = mi_autotune(items, n_items, flags, max_poses, ws, ws_bytes, stream, out);
+  if (st != MI_OK) return st;
+  return mi_tuning_cache_put(path, key, &out->best);
+  });
+}
+
 extern "C" size_t mi_eval_poses_workspace(const mi_ref *r, int64_t n_b, const double *poses,
                                           int64_t K, uint32_t flags, size_t budget) {
   return guarded_size([&]() -> size_t {

@@ -138,6 +138,12 @@ def _load():
         "mi_autotune_workspace": ([C.POINTER(_WorkItem), i64, u32, i64], sz),
         "mi_autotune": ([C.POINTER(_WorkItem), i64, u32, i64, vp, sz, vp,
                          C.POINTER(_AutotuneReport)], st),
+        "mi_autotune_cached": ([C.POINTER(_WorkItem), i64, u32, i64, vp, sz, vp, C.c_char_p,
+                                C.POINTER(_AutotuneReport)], st),
+        "mi_tuning_cache_key": ([C.c_char_p, u32, st, st, i64, i64, C.c_char_p, sz], st),
+        "mi_tuning_cache_get": ([C.c_char_p, C.c_char_p, C.POINTER(_Tuning),
+                                 C.POINTER(C.c_int32)], st),
+        "mi_tuning_cache_put": ([C.c_char_p, C.c_char_p, C.POINTER(_Tuning)], st),
         "mi_align_nm_workspace": ([vp, i64, C.c_int32], sz),
         "mi_align_nelder_mead": ([vp, vp, i64, dp, C.c_int32, C.POINTER(_NMDesc), dp, dp,
                                   C.POINTER(C.c_int32), vp, sz, vp], st),
@@ -167,7 +173,8 @@ EXPORTED = ("mi_status_str", "mi_last_error", "mi_tuning_set", "mi_tuning_get",
             "mi_eval_poses_plain", "mi_plan_create", "mi_plan_execute", "mi_plan_destroy",
             "mi_plan_launch", "mi_server_info",
             "mi_batch_workspace", "mi_batch_create", "mi_batch_execute", "mi_eval_batch",
-            "mi_autotune_workspace", "mi_autotune",
+            "mi_autotune_workspace", "mi_autotune", "mi_autotune_cached",
+            "mi_tuning_cache_key", "mi_tuning_cache_get", "mi_tuning_cache_put",
             "mi_align_workspace", "mi_align_coarse_to_fine", "mi_align_nm_workspace",
             "mi_align_nelder_mead", "mi_server_create",
             "mi_server_submit", "mi_server_step", "mi_server_poll", "mi_server_release",
@@ -607,9 +614,11 @@ def eval_batch(items, flags=0, stream=None):
 
 
 @_stream_ordered
-def autotune(items, flags=0, max_poses=4096, stream=None) -> dict:
+def autotune(items, flags=0, max_poses=4096, stream=None, cache=None) -> dict:
     """mi_autotune: time candidate tunings on a sample of the workload and make
-    the fastest current.  Returns the chosen tuning and the timings."""
+    the fastest current.  Returns the chosen tuning and the timings.  cache: a
+    tuning-cache file (mi_autotune_cached): a tuning cached for this workload's
+    key is made current without timing (tried = 0); else the result is stored."""
     items = list(items)
     arr = _items_array(items)
     nbytes = _lib.mi_autotune_workspace(arr, len(items), flags, int(max_poses))
@@ -617,12 +626,45 @@ def autotune(items, flags=0, max_poses=4096, stream=None) -> dict:
         raise MIError(MI_E_INVALID, "mi_autotune_workspace", _lib.mi_last_error().decode())
     ws = _workspace(nbytes)
     rep = _AutotuneReport()
-    _check(_lib.mi_autotune(arr, len(items), flags, int(max_poses), _dptr(ws), ws.numel(),
-                            _stream(stream), C.byref(rep)), "mi_autotune")
+    if cache is None:
+        _check(_lib.mi_autotune(arr, len(items), flags, int(max_poses), _dptr(ws), ws.numel(),
+                                _stream(stream), C.byref(rep)), "mi_autotune")
+    else:
+        _check(_lib.mi_autotune_cached(arr, len(items), flags, int(max_poses), _dptr(ws),
+                                       ws.numel(), _stream(stream), os.fsencode(cache),
+                                       C.byref(rep)), "mi_autotune_cached")
     b = rep.best
     return dict(best=dict(waves=b.waves, hash_bytes=b.hash_bytes, hist_copies=b.hist_copies,
                           stripe_rows=b.stripe_rows, wgs_per_cu=b.wgs_per_cu),
                 best_ms=rep.best_ms, start_ms=rep.start_ms, tried=rep.tried)
+
+
+def tuning_cache_key(arch: str, features: int, nb0: int, nb1: int, n_b: int, voxels: int) -> str:
+    """mi_tuning_cache_key (host only)."""
+    buf = C.create_string_buffer(256)
+    _check(_lib.mi_tuning_cache_key(arch.encode(), int(features), int(nb0), int(nb1), int(n_b),
+                                    int(voxels), buf, len(buf)), "mi_tuning_cache_key")
+    return buf.value.decode()
+
+
+def tuning_cache_get(path, key: str):
+    """mi_tuning_cache_get (host only): the cached tuning as a dict, or None."""
+    t = _Tuning()
+    found = C.c_int32(0)
+    _check(_lib.mi_tuning_cache_get(os.fsencode(path), key.encode(), C.byref(t), C.byref(found)),
+           "mi_tuning_cache_get")
+    if not found.value:
+        return None
+    return dict(waves=t.waves, hash_bytes=t.hash_bytes, hist_copies=t.hist_copies,
+                stripe_rows=t.stripe_rows, wgs_per_cu=t.wgs_per_cu)
+
+
+def tuning_cache_put(path, key: str, tuning: dict):
+    """mi_tuning_cache_put (host only)."""
+    t = _Tuning(int(tuning["waves"]), int(tuning["hash_bytes"]), int(tuning["hist_copies"]),
+                int(tuning["stripe_rows"]), int(tuning["wgs_per_cu"]))
+    _check(_lib.mi_tuning_cache_put(os.fsencode(path), key.encode(), C.byref(t)),
+           "mi_tuning_cache_put")
 
 
 def _objective(d, feature_slot, weights):

@@ -217,6 +217,36 @@ def test_autotune_changes_speed_only(M):
         M.tuning_set(**orig)
 
 
+def test_autotune_through_the_cache(M, tmp_path):
+    """mi_autotune_cached: the first call times the candidates and stores the
+    best tuning under the workload's key; the second finds it, makes it
+    current without timing anything, and the results stay bit-identical."""
+    pair = synth.tiny_pair()
+    mg = M.Grid(pair.origin, pair.dims, pair.voxel, features=3, nb_count=32, nb_zvar=32)
+    ref = M.Ref(mg, pair.A)
+    P = synth.grid8_poses(4)
+    cache = str(tmp_path / "tuning.json")
+    orig = M.tuning_get()
+    try:
+        before = M.WorkItem(ref, pair.B, P, want_hist=True)
+        M.Batch([before]).execute()
+        torch.cuda.synchronize()
+        first = M.autotune([before], max_poses=1024, cache=cache)
+        M.tuning_set(**orig)
+        second = M.autotune([before], max_poses=1024, cache=cache)
+        _say("cached autotune", first["tried"], second)
+        assert first["tried"] >= 10 and second["tried"] == 0
+        assert second["best"] == first["best"] == M.tuning_get()
+        key = M.tuning_cache_key(torch.cuda.get_device_properties(0).gcnArchName, 3, 32, 32,
+                                 pair.B.shape[1], int(np.prod(mg.dims)))
+        assert M.tuning_cache_get(cache, key) == first["best"]
+        after = M.WorkItem(ref, pair.B, P, want_hist=True)
+        M.Batch([after]).execute()
+        _same(after.results(), before.results(), mg, "cached tuning vs default")
+    finally:
+        M.tuning_set(**orig)
+
+
 def test_auto_hash_survives_a_tuning_round_trip(M):
     # hash_bytes = 0 is the auto size (66 KiB, or 60 KiB where 66 would leave
     # one workgroup per CU); a get / set round trip keeps it, so a large
