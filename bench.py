@@ -464,6 +464,16 @@ def _run_batched(a, pair):
         res["cpu_baseline"] = {
             "value": len(Ps) / tc, "unit": "MI pose evals/s", "cores": cores, "kind": "oracle",
             "sample": f"every 128th of the 262,144 poses ({len(Ps)}), FP64 dense oracle, {tc:.1f} s"}
+        # the tiny plain search (11 x 11 x 11 x, y, yaw poses, count in 16 bins) in full,
+        # on one thread: the oracle's single-core rate on the smallest workload
+        og1 = O.Grid(pair.origin, pair.dims, pair.voxel, features=1, nb_count=16)
+        P1 = synth.tiny_search_poses()
+        t10 = time.perf_counter()
+        O.eval_poses(og1, pair.A, pair.B, P1, nthreads=1)
+        t1 = time.perf_counter() - t10
+        res["cpu_baseline"]["tiny_search_one_thread"] = {
+            "value": len(P1) / t1, "unit": "MI pose evals/s", "cores": 1, "poses": len(P1),
+            "seconds": t1}
     return res
 
 
